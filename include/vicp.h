@@ -1,0 +1,221 @@
+/*
+ * vicp.h -- C ABI of libvicp: dilation-based ICP with segmented, offset-
+ * addressed dilation memory on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Chang, Wang, Zhong and Miyazaki, "A dynamic memory
+ * assignment strategy for dilation-based ICP algorithm on embedded GPUs"
+ * (arXiv 2512.04996): align a source cloud P = {p_1..p_m} to a target cloud
+ * Q = {q_1..q_n} by the rigid R, t that minimise Eq. 1 (sum_i |R p_i + t - q'_i|^2,
+ * q'_i the correspondence of p_i), with correspondences found by a local search
+ * inside voxels of a dilated target grid (Sec. II.A, Steps 1-3) whose per-voxel
+ * memory is assigned from a histogram and its prefix offsets (Sec. III,
+ * Algorithms 1-4).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Layout     Point clouds are structure-of-arrays float32: three device arrays
+ *            x[k], y[k], z[k], each contiguous.  Batched calls take the pairs'
+ *            points concatenated in pair order, with per-pair counts in a HOST
+ *            array.  Voxel ids are x-fastest: v = ix + Dx*(iy + Dy*iz).
+ * Ownership  The caller owns every input and output buffer and keeps it alive
+ *            until the work queued on the stream has finished.  A grid keeps a
+ *            reference to the target arrays it was built from (not a copy of
+ *            the coordinates' ownership): they must outlive the grid.  The grid
+ *            owns its histogram, offsets, dilated voxel index and workspaces,
+ *            allocated through the caller's vicp_allocator, or with
+ *            hipMallocAsync on the given stream when that is NULL.
+ * Streams    All device work is queued on the caller's stream in order.  Calls
+ *            that must read a value back (grid sizing, registration results)
+ *            synchronise that stream, and say so.
+ * Errors     Every call returns VICP_OK (0) or a negative VICP_ERR_* code and
+ *            never aborts or prints; vicp_last_error() gives a message for the
+ *            calling thread.  Faults found on the device (non-finite source
+ *            coordinates, degenerate cross-covariance) are latched in the grid
+ *            and returned by the next call that synchronises.
+ * Threads    A grid may be used by one host thread at a time.  Distinct grids
+ *            are independent.
+ */
+#ifndef VICP_H
+#define VICP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define VICP_OK 0
+#define VICP_ERR_INVALID_ARG (-1)   /* bad size, pointer, voxel, ring count or pair count */
+#define VICP_ERR_GRID_TOO_LARGE (-2) /* V >= 2^31 voxels or n + 2V >= 2^32 words */
+#define VICP_ERR_OOM (-3)           /* the allocator returned NULL */
+#define VICP_ERR_HIP (-4)           /* a HIP runtime call failed */
+#define VICP_ERR_STATE (-5)         /* call out of order (e.g. dilating twice) */
+#define VICP_ERR_NONFINITE (-6)     /* NaN or Inf in the input coordinates */
+#define VICP_ERR_DEGENERATE (-7)    /* cross-covariance of rank < 2: pose kept */
+
+/* Mask(root) of a dilated voxel's count word (Alg. 3): bit 31 set. */
+#define VICP_MASK_BIT 0x80000000u
+
+typedef struct vicp_grid vicp_grid;
+
+/* Stream-ordered allocator supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc returns device memory of at least `bytes` usable on
+ * `stream`, or NULL; free releases it after the stream's queued work. */
+typedef struct vicp_allocator {
+    void* (*alloc)(size_t bytes, hipStream_t stream, void* user);
+    void (*free)(void* ptr, size_t bytes, hipStream_t stream, void* user);
+    void* user;
+} vicp_allocator;
+
+/* Description of one pair's grid (Sec. II.A Step 1; Table 1 accounting). */
+typedef struct vicp_grid_desc {
+    float origin[3];       /* lower corner: target box minimum minus pad_rings voxels */
+    float inv;             /* 1/voxel, rounded once to float32 */
+    float voxel;           /* voxel edge */
+    int32_t dims[3];       /* voxels per axis */
+    int64_t V;             /* dims[0]*dims[1]*dims[2] */
+    int64_t n;             /* target points */
+    int32_t pad_rings;     /* padding the grid was built with */
+    int32_t rings_applied; /* dilation rings applied so far (0 before vicp_dilate) */
+    int64_t occupied;      /* voxels holding >= 1 target point */
+    int64_t dilated;       /* empty voxels given a root by dilation */
+    uint32_t max_count;    /* largest per-voxel count */
+    int64_t static_bytes;  /* histogram + offsets: 8 V (Table 1, note 1) */
+    int64_t dynamic_bytes; /* dilated voxel index: 4 (n + 2V) */
+    int64_t vanicp_bytes;  /* fixed 64 KiB per voxel of the original VANICP (Sec. II.B) */
+    int64_t extra_bytes;   /* device bytes this library holds beyond the two above */
+} vicp_grid_desc;
+
+/* ICP options (Sec. IV.A "Parameter": maximum iterations and RMSE difference). */
+typedef struct vicp_icp_opts {
+    int32_t max_iter;   /* K >= 0 */
+    double rmse_eps;    /* stop when |RMSE_k - RMSE_{k-1}| < rmse_eps (k >= 1) ... */
+    int32_t early_stop; /* ... only if non-zero; 0 runs exactly K iterations */
+    int32_t use_graph;  /* non-zero: capture the K iterations once in a hipGraph and replay it */
+} vicp_icp_opts;
+
+/* Per-pair registration statistics.  The arrays are caller-owned HOST arrays
+ * of max_iter entries and may be NULL. */
+typedef struct vicp_icp_stats {
+    int32_t iters;          /* iterations run */
+    int32_t degenerate;     /* iterations whose solve kept the previous pose */
+    double* rmse;           /* RMSE_k = sqrt(mean nn_d2) of iteration k */
+    int64_t* fallbacks;     /* queries that took the global search in iteration k */
+} vicp_icp_stats;
+
+/* ---- build (Alg. 1 and Alg. 2) --------------------------------------------
+ * Voxelises the target (qx, qy, qz; n points, device) with edge `voxel` on the
+ * target's bounding box padded by `pad_rings` voxels, counts points per voxel,
+ * exclusive-scans count + 2 into segment offsets, and scatters point indices
+ * into their segments [lock = 0, count, indices ascending].  Synchronises the
+ * stream once, to read the 24-byte bounding box that sizes the grid.
+ * Errors: n <= 0, voxel <= 0 or non-finite, pad_rings < 0 -> INVALID_ARG;
+ * non-finite target coordinates -> NONFINITE; grid too large -> GRID_TOO_LARGE. */
+int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n,
+                    float voxel, int32_t pad_rings, const vicp_allocator* alloc,
+                    hipStream_t stream, vicp_grid** out);
+
+/* As vicp_build_grid for `npairs` independent targets concatenated in pair
+ * order; n_per_pair and voxel_per_pair are HOST arrays of npairs entries. */
+int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz,
+                            const int64_t* n_per_pair, int32_t npairs,
+                            const float* voxel_per_pair, int32_t pad_rings,
+                            const vicp_allocator* alloc, hipStream_t stream,
+                            vicp_grid** out);
+
+/* ---- dilation (Alg. 3) ----------------------------------------------------
+ * Applies `rings` synchronous dilation rings (0 <= rings <= pad_rings) to every
+ * pair: an empty voxel within L1 distance `rings` of an occupied voxel gets
+ * Mask(root) in its count word, root = the nearest occupied voxel, lowest id
+ * on ties.  May be called once per grid; again -> STATE.  Asynchronous. */
+int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t stream);
+
+/* ---- nearest-neighbour search (Alg. 4) ------------------------------------
+ * For each source point (px, py, pz; m points, device) of a single-pair grid:
+ * s = R p + t with Rt = 12 HOST floats (R row-major, then t); the voxel of s,
+ * then its own segment, its root's segment when dilated, or an exact search
+ * over all targets when the voxel is empty or s is outside the grid.  Writes
+ * nn_idx[m] (target index, ties to the lowest) and nn_d2[m] (float32 squared
+ * distance) to device memory, and the number of global searches to the device
+ * int32 *n_fallback when it is not NULL.  m == 0 is a no-op.  Asynchronous. */
+int vicp_nns(const vicp_grid* g, const float* px, const float* py, const float* pz,
+             int64_t m, const float Rt[12], int32_t* nn_idx, float* nn_d2,
+             int32_t* n_fallback, hipStream_t stream);
+
+/* Batched form: m_per_pair HOST array, Rt HOST float[npairs*12], outputs
+ * concatenated in pair order, n_fallback a device int32[npairs] or NULL. */
+int vicp_nns_batched(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                     const int64_t* m_per_pair, const float* Rt, int32_t* nn_idx,
+                     float* nn_d2, int32_t* n_fallback, hipStream_t stream);
+
+/* ---- registration (Sec. II.A loop, Eq. 1) ---------------------------------
+ * Runs the ICP loop on a single-pair grid: correspondences by Alg. 4 at the
+ * float32-rounded pose, then the closed-form rigid transform of Eq. 1 on
+ * (original p_i, q_c(i)) in float64, repeated opts->max_iter times or until
+ * the RMSE difference rule stops it.  Rt_io: 12 HOST doubles, initial pose in,
+ * final pose out.  `stats` may be NULL.  Synchronises the stream at the end.
+ * Returns DEGENERATE (pose still valid) if any solve kept the previous pose. */
+int vicp_register(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                  int64_t m, const vicp_icp_opts* opts, double Rt_io[12],
+                  vicp_icp_stats* stats, hipStream_t stream);
+
+/* Batched form: every pair runs its own loop inside one launch sequence.
+ * m_per_pair HOST int64[npairs]; Rt_io HOST double[npairs*12]; stats HOST
+ * array of npairs entries or NULL. */
+int vicp_register_batched(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                          const int64_t* m_per_pair, const vicp_icp_opts* opts, double* Rt_io,
+                          vicp_icp_stats* stats, hipStream_t stream);
+
+/* ---- differentiable point-to-point loss ------------------------------------
+ * For pair b with pose xi_b = (rho, phi) in R^6 (device float64[npairs*6]),
+ * T = Exp(xi_b) in SE(3), correspondences c_i from Alg. 4 at the float32-rounded
+ * T, and L_b = (1/m_b) sum_i |T p_i - q_c(i)|^2 (the objective of Eq. 1 per
+ * point).  Forward writes loss[npairs] (device float64).  Backward recomputes
+ * the correspondences (never stored) and, given dL/dL_b in gloss (device
+ * float64[npairs]), writes dP (device float32 SoA, same layout as p) and dxi
+ * (device float64[npairs*6], through the SE(3) left Jacobian).  Asynchronous. */
+int vicp_p2p_loss_fwd(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                      const int64_t* m_per_pair, const double* xi, double* loss,
+                      hipStream_t stream);
+int vicp_p2p_loss_bwd(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                      const int64_t* m_per_pair, const double* xi, const double* gloss,
+                      float* dpx, float* dpy, float* dpz, double* dxi, hipStream_t stream);
+
+/* ---- helpers ---------------------------------------------------------------- */
+/* Number of pairs in a grid. */
+int vicp_grid_npairs(const vicp_grid* g);
+/* Description of pair `pair`; synchronises the stream the grid was last used on. */
+int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out);
+/* Copies pair `pair`'s histogram (uint32[V]), offsets (uint32[V+1], relative to
+ * the pair's segment base) and dilated voxel index (uint32[n+2V]) into device
+ * buffers (any may be NULL).  Asynchronous. */
+int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t* off,
+                     uint32_t* vm, hipStream_t stream);
+/* Releases the grid and everything it owns (after its queued work). */
+int vicp_grid_free(vicp_grid* g);
+
+/* Autotuning: times the result-invariant launch schedules of the NNS and
+ * dilation kernels on this grid and source and keeps the fastest in the grid.
+ * Results never depend on the schedule.  Synchronises the stream. */
+int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz,
+                  const int64_t* m_per_pair, hipStream_t stream);
+
+/* Per-kernel timing with HIP events on the launch stream (0 = off).  While on,
+ * every launch of a named kernel is bracketed by events; vicp_prof_read gives
+ * the count and summed milliseconds (synchronises the events). */
+int vicp_prof_enable(int32_t on);
+int vicp_prof_read(const char* kernel, int64_t* launches, double* total_ms);
+int vicp_prof_reset(void);
+
+const char* vicp_status_str(int code);
+const char* vicp_last_error(void);
+const char* vicp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VICP_H */

@@ -1,0 +1,222 @@
+"""Python front end of libvicp: argument marshalling over torch device memory.
+
+Every step of the method runs in the HIP library; this module only passes
+pointers, sizes and torch's current stream, and converts results.  Point
+clouds are float32 CUDA tensors in structure-of-arrays layout, shape (3, k)
+(a (k, 3) tensor is accepted and transposed into a contiguous copy).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GridDesc, IcpOpts, IcpStats, VicpError, check, lib
+
+__all__ = ["Grid", "build_grid", "build_grid_batched", "IcpResult", "prof_enable", "prof_read", "prof_reset"]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _soa(x: torch.Tensor, what: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32")
+    if x.dim() != 2 or 3 not in x.shape:
+        raise ValueError(f"{what} must have shape (3, k) or (k, 3)")
+    if x.shape[0] != 3:
+        x = x.t()
+    return x.contiguous()
+
+
+def _ptrs(x: torch.Tensor):
+    if x.shape[1] == 0:
+        return C.c_void_p(0), C.c_void_p(0), C.c_void_p(0)
+    return tuple(C.c_void_p(x[a].data_ptr()) for a in range(3))
+
+
+def _i64(vals):
+    arr = (C.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+@dataclass
+class IcpResult:
+    Rt: np.ndarray            # (12,) float64 or (B, 12): R row-major then t
+    iters: np.ndarray         # (B,)
+    degenerate: np.ndarray    # (B,)
+    rmse: list                # per pair, float64[iters]
+    fallbacks: list           # per pair, int64[iters]
+    status: int
+
+
+class Grid:
+    """A built (and possibly dilated) target grid for one or more pairs."""
+
+    def __init__(self, handle: C.c_void_p, q: torch.Tensor, n_per_pair, voxels, pad_rings: int):
+        self._h = handle
+        self.q = q                       # keeps the target alive for the grid's lifetime
+        self.n_per_pair = [int(v) for v in n_per_pair]
+        self.voxels = [float(v) for v in voxels]
+        self.pad_rings = int(pad_rings)
+        self.npairs = len(self.n_per_pair)
+
+    # -- lifetime
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().vicp_grid_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise VicpError(_lib.ERR_STATE, "grid", "freed")
+        return self._h
+
+    # -- Alg. 3
+    def dilate(self, rings: int):
+        check(lib().vicp_dilate(self.handle, int(rings), _stream()), "vicp_dilate")
+        return self
+
+    # -- Alg. 4
+    def nns(self, p: torch.Tensor, Rt, m_per_pair=None):
+        """Correspondences of every source point at pose(s) Rt (float32,
+        (12,) or (B, 12)).  Returns (nn_idx int32[m], nn_d2 float32[m],
+        n_fallback int32[B]) as CUDA tensors."""
+        p = _soa(p, "p")
+        m = p.shape[1]
+        if m_per_pair is None:
+            if self.npairs != 1:
+                raise ValueError("m_per_pair is required for a batched grid")
+            m_per_pair = [m]
+        if sum(m_per_pair) != m:
+            raise ValueError("m_per_pair does not add up to the source size")
+        rt = np.ascontiguousarray(np.asarray(Rt, np.float32).reshape(self.npairs * 12))
+        idx = torch.empty(max(m, 1), dtype=torch.int32, device=p.device)
+        d2 = torch.empty(max(m, 1), dtype=torch.float32, device=p.device)
+        fb = torch.zeros(self.npairs, dtype=torch.int32, device=p.device)
+        px, py, pz = _ptrs(p)
+        check(lib().vicp_nns_batched(self.handle, px, py, pz, _i64(m_per_pair),
+                                     rt.ctypes.data_as(C.POINTER(C.c_float)), C.c_void_p(idx.data_ptr()),
+                                     C.c_void_p(d2.data_ptr()), C.c_void_p(fb.data_ptr()), _stream()),
+              "vicp_nns_batched")
+        return idx[:m], d2[:m], fb
+
+    # -- the ICP loop
+    def register(self, p: torch.Tensor, max_iter: int, rmse_eps: float = 1e-5, early_stop: bool = False,
+                 use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False) -> IcpResult:
+        p = _soa(p, "p")
+        m = p.shape[1]
+        B = self.npairs
+        if m_per_pair is None:
+            if B != 1:
+                raise ValueError("m_per_pair is required for a batched grid")
+            m_per_pair = [m]
+        if sum(m_per_pair) != m:
+            raise ValueError("m_per_pair does not add up to the source size")
+        if Rt0 is None:
+            Rt0 = np.tile(np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float64), (B, 1))
+        rt = np.ascontiguousarray(np.asarray(Rt0, np.float64).reshape(B * 12)).copy()
+        K = int(max_iter)
+        rm = np.zeros((B, max(K, 1)), np.float64)
+        fbk = np.zeros((B, max(K, 1)), np.int64)
+        stats = (IcpStats * B)()
+        for b in range(B):
+            stats[b].rmse = rm[b].ctypes.data_as(C.POINTER(C.c_double))
+            stats[b].fallbacks = fbk[b].ctypes.data_as(C.POINTER(C.c_int64))
+        opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)))
+        px, py, pz = _ptrs(p)
+        rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
+                                         rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())
+        allow = () if raise_degenerate else (_lib.ERR_DEGENERATE,)
+        check(rc, "vicp_register_batched", allow)
+        iters = np.array([stats[b].iters for b in range(B)])
+        deg = np.array([stats[b].degenerate for b in range(B)])
+        return IcpResult(rt.reshape(B, 12) if B > 1 else rt, iters, deg,
+                         [rm[b, :iters[b]].copy() for b in range(B)],
+                         [fbk[b, :iters[b]].copy() for b in range(B)], rc)
+
+    # -- helpers
+    def describe(self, pair: int = 0) -> dict:
+        d = GridDesc()
+        check(lib().vicp_grid_describe(self.handle, int(pair), C.byref(d)), "vicp_grid_describe")
+        return {
+            "origin": np.array(d.origin[:], np.float32), "inv": np.float32(d.inv), "voxel": np.float32(d.voxel),
+            "dims": np.array(d.dims[:], np.int32), "V": d.V, "n": d.n, "pad_rings": d.pad_rings,
+            "rings_applied": d.rings_applied, "occupied": d.occupied, "dilated": d.dilated,
+            "max_count": d.max_count, "static_bytes": d.static_bytes, "dynamic_bytes": d.dynamic_bytes,
+            "vanicp_bytes": d.vanicp_bytes, "extra_bytes": d.extra_bytes,
+        }
+
+    def export(self, pair: int = 0):
+        """(hist uint32[V], off uint32[V+1] relative to the pair, vm uint32[n+2V]) as numpy arrays."""
+        d = self.describe(pair)
+        V, n = d["V"], d["n"]
+        dev = self.q.device
+        hist = torch.empty(V, dtype=torch.int32, device=dev)
+        off = torch.empty(V + 1, dtype=torch.int32, device=dev)
+        vm = torch.empty(n + 2 * V, dtype=torch.int32, device=dev)
+        check(lib().vicp_grid_export(self.handle, int(pair), C.c_void_p(hist.data_ptr()), C.c_void_p(off.data_ptr()),
+                                     C.c_void_p(vm.data_ptr()), _stream()), "vicp_grid_export")
+        torch.cuda.current_stream().synchronize()
+        u = lambda t: t.cpu().numpy().view(np.uint32)
+        return u(hist), u(off), u(vm)
+
+    def autotune(self, p: torch.Tensor, m_per_pair=None):
+        p = _soa(p, "p")
+        if m_per_pair is None:
+            m_per_pair = [p.shape[1]]
+        px, py, pz = _ptrs(p)
+        check(lib().vicp_autotune(self.handle, px, py, pz, _i64(m_per_pair), _stream()), "vicp_autotune")
+        return self
+
+
+def build_grid(q: torch.Tensor, voxel: float, pad_rings: int) -> Grid:
+    """Alg. 1 + Alg. 2 on one target cloud (3, n) float32 CUDA."""
+    q = _soa(q, "q")
+    h = C.c_void_p()
+    qx, qy, qz = _ptrs(q)
+    check(lib().vicp_build_grid(qx, qy, qz, q.shape[1], C.c_float(voxel), int(pad_rings), None, _stream(),
+                                C.byref(h)), "vicp_build_grid")
+    return Grid(h, q, [q.shape[1]], [voxel], pad_rings)
+
+
+def build_grid_batched(q: torch.Tensor, n_per_pair, voxels, pad_rings: int) -> Grid:
+    """Alg. 1 + Alg. 2 on several targets concatenated along the point axis."""
+    q = _soa(q, "q")
+    if sum(int(v) for v in n_per_pair) != q.shape[1]:
+        raise ValueError("n_per_pair does not add up to the target size")
+    B = len(n_per_pair)
+    vox = (C.c_float * B)(*[float(v) for v in voxels])
+    h = C.c_void_p()
+    qx, qy, qz = _ptrs(q)
+    check(lib().vicp_build_grid_batched(qx, qy, qz, _i64(n_per_pair), B, vox, int(pad_rings), None, _stream(),
+                                        C.byref(h)), "vicp_build_grid_batched")
+    return Grid(h, q, n_per_pair, voxels, pad_rings)
+
+
+def prof_enable(on: bool = True):
+    check(lib().vicp_prof_enable(int(on)), "vicp_prof_enable")
+
+
+def prof_read(kernel: str):
+    n = C.c_int64()
+    ms = C.c_double()
+    check(lib().vicp_prof_read(kernel.encode(), C.byref(n), C.byref(ms)), "vicp_prof_read")
+    return n.value, ms.value
+
+
+def prof_reset():
+    check(lib().vicp_prof_reset(), "vicp_prof_reset")

@@ -1,0 +1,74 @@
+// k_dilate.hip -- voxel dilation (Alg. 3) under offset addressing.
+//
+// Ring r of a synchronous schedule: an empty voxel takes the lowest root id
+// among its six in-bounds face neighbours' roots after ring r-1 (pull form,
+// no atomics, no locks).  After the last ring every empty voxel that has a
+// root gets Mask(root) in the count word of its segment, found through the
+// offsets.  The ring state lives in a compact V-word array (root or none).
+#include "vicp_internal.hpp"
+
+namespace vicp {
+
+namespace {
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_dilate_ring(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
+                                                    uint32_t* __restrict__ vm, const uint32_t* __restrict__ src,
+                                                    uint32_t* __restrict__ dst, int first, int last)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t vi = (int64_t)job.start + threadIdx.x;
+    if (vi >= P.V) return;
+    const uint32_t v = (uint32_t)vi;
+    const int64_t vb = P.v_base;
+    const int64_t g = vb + v;
+    auto state = [&](uint32_t u) -> uint32_t {
+        const int64_t gu = vb + u;
+        return first ? (hist[gu] ? u : kNone) : src[gu];
+    };
+    uint32_t cur = state(v);
+    if (cur == kNone) {
+        const uint32_t Dx = (uint32_t)P.Dx, Dy = (uint32_t)P.Dy, Dz = (uint32_t)P.Dz;
+        const uint32_t x = v % Dx, yz = v / Dx;
+        const uint32_t y = yz % Dy, z = yz / Dy;
+        const uint32_t sxy = Dx * Dy;
+        if (x > 0) cur = min(cur, state(v - 1));
+        if (x + 1 < Dx) cur = min(cur, state(v + 1));
+        if (y > 0) cur = min(cur, state(v - Dx));
+        if (y + 1 < Dy) cur = min(cur, state(v + Dx));
+        if (z > 0) cur = min(cur, state(v - sxy));
+        if (z + 1 < Dz) cur = min(cur, state(v + sxy));
+    }
+    if (!last) {
+        dst[g] = cur;
+    } else if (cur != kNone && hist[g] == 0) {
+        vm[(int64_t)off[g] + 1] = cur | kMask;
+    }
+}
+
+}  // namespace
+
+void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block, const uint32_t* hist,
+                        const uint32_t* off, uint32_t* vm, const uint32_t* src, uint32_t* dst, int first, int last,
+                        hipStream_t s)
+{
+    if (njobs <= 0) return;
+    switch (block) {
+    case 64:
+        hipLaunchKernelGGL(k_dilate_ring<64>, dim3(njobs), dim3(64), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        break;
+    case 128:
+        hipLaunchKernelGGL(k_dilate_ring<128>, dim3(njobs), dim3(128), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_dilate_ring<512>, dim3(njobs), dim3(512), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        break;
+    default:
+        hipLaunchKernelGGL(k_dilate_ring<256>, dim3(njobs), dim3(256), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        break;
+    }
+}
+
+}  // namespace vicp

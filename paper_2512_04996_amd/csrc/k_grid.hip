@@ -1,0 +1,384 @@
+// k_grid.hip -- target grid build: bounding box, voxelise + count (Alg. 1,
+// GPU part), offsets by a single-pass scan (Alg. 1, CPU part, moved to the
+// GPU), scatter into segments and canonical in-segment order (Alg. 2).
+#include "vicp_internal.hpp"
+
+namespace vicp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+
+// Order-preserving map float -> uint32 (for atomic min/max of floats).
+__device__ __forceinline__ uint32_t ordered(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+    for (int d = kWave / 2; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+    for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+    return v;
+}
+
+// Voxel of a target point (float32: subtract, multiply, floor; x fastest).
+// Returns false when the point is outside the grid.
+__device__ __forceinline__ bool voxel_id(const PairDev& P, float x, float y, float z, uint32_t& v)
+{
+    float fx = (x - P.ox) * P.inv;
+    float fy = (y - P.oy) * P.inv;
+    float fz = (z - P.oz) * P.inv;
+    bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
+    if (!in) return false;
+    uint32_t ix = (uint32_t)floorf(fx), iy = (uint32_t)floorf(fy), iz = (uint32_t)floorf(fz);
+    v = ix + (uint32_t)P.Dx * (iy + (uint32_t)P.Dy * iz);
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// bounding box per pair: box[8 p + 0..2] = ordered min, [3..5] = ordered max,
+// [6] = non-finite flag
+// --------------------------------------------------------------------------
+__global__ void k_box_init(uint32_t* box, int npairs)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs * 8) return;
+    int f = i & 7;
+    box[i] = (f < 3) ? 0xFFFFFFFFu : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx, const float* __restrict__ qy,
+                                                   const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                                   const BlockJob* __restrict__ jobs, int items, uint32_t* box)
+{
+    __shared__ uint32_t red[7][kThreads / kWave];
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u}, bad = 0;
+    const int64_t end = min((int64_t)job.start + items, P.n);
+    for (int64_t i = job.start + threadIdx.x; i < end; i += kThreads) {
+        const int64_t g = P.q_base + i;
+        float c[3] = {qx[g], qy[g], qz[g]};
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(c[a])) {
+                bad = 1;
+                continue;
+            }
+            uint32_t o = ordered(c[a]);
+            mn[a] = min(mn[a], o);
+            mx[a] = max(mx[a], o);
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int a = 0; a < 3; ++a) {
+        mn[a] = wave_min(mn[a]);
+        mx[a] = wave_max(mx[a]);
+    }
+    bad = wave_max(bad);
+    if (lane == 0) {
+        for (int a = 0; a < 3; ++a) {
+            red[a][w] = mn[a];
+            red[3 + a][w] = mx[a];
+        }
+        red[6][w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        uint32_t r = red[threadIdx.x][0];
+        for (int k = 1; k < kThreads / kWave; ++k)
+            r = (threadIdx.x < 3) ? min(r, red[threadIdx.x][k]) : max(r, red[threadIdx.x][k]);
+        uint32_t* dst = box + 8 * job.pair + threadIdx.x;
+        if (threadIdx.x < 3)
+            atomicMin(dst, r);
+        else
+            atomicMax(dst, r);
+    }
+}
+
+// --------------------------------------------------------------------------
+// voxelise + count with a per-block LDS hash (32-bit key, 32-bit count):
+// one global atomic per distinct (block, voxel), which also hands each point
+// its slot inside the voxel's segment.
+// --------------------------------------------------------------------------
+constexpr int kSlots = 2 * kThreads;
+
+__global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
+                                                    const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                                    const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
+                                                    uint32_t* err)
+{
+    __shared__ uint32_t skey[kSlots];
+    __shared__ uint32_t scnt[kSlots];
+    __shared__ uint32_t sbase[kSlots];
+    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+        skey[s] = kNone;
+        scnt[s] = 0;
+    }
+    __syncthreads();
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    bool valid = i < P.n;
+    uint32_t v = 0, slot = 0, lr = 0;
+    int64_t g = 0;
+    if (valid) {
+        g = P.q_base + i;
+        if (!voxel_id(P, qx[g], qy[g], qz[g], v)) {
+            atomicOr(err, 1u);   // cannot happen for a target inside its own box
+            valid = false;
+        }
+    }
+    if (valid) {
+        slot = (v * 2654435761u) >> 23;   // 9 bits
+        while (true) {
+            uint32_t prev = atomicCAS(&skey[slot], kNone, v);
+            if (prev == kNone || prev == v) break;
+            slot = (slot + 1) & (kSlots - 1);
+        }
+        lr = atomicAdd(&scnt[slot], 1u);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+        const uint32_t k = skey[s];
+        if (k != kNone) sbase[s] = atomicAdd(&hist[P.v_base + k], scnt[s]);
+    }
+    __syncthreads();
+    if (valid) {
+        vox[g] = v;
+        rank[g] = sbase[slot] + lr;
+    }
+}
+
+// --------------------------------------------------------------------------
+// offsets: off[g] = sum_{u<g} (hist[u] + 2), off[total] = n + 2V, and the
+// segment headers vm[off[g]] = 0, vm[off[g] + 1] = hist[g].  Single pass,
+// decoupled look-back (tile ids from a ticket so predecessors are resident).
+// --------------------------------------------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+constexpr unsigned long long kFlagAgg = 1ull << 32;
+constexpr unsigned long long kFlagIncl = 2ull << 32;
+
+__device__ __forceinline__ unsigned long long ld_status(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_status(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ hist, int64_t total,
+                                                   uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
+                                                   unsigned long long* status, uint32_t* ticket)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wave[kThreads / kWave];
+    __shared__ uint32_t s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t h[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t g = base + k;
+        h[k] = (g < total) ? hist[g] : 0u;
+        sum += (g < total) ? h[k] + 2u : 0u;
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = (uint32_t)__shfl_up((int)incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    uint32_t wave_off = 0, agg = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / kWave; ++k) {
+        const uint32_t t = s_wave[k];
+        if (k < w) wave_off += t;
+        agg += t;
+    }
+    const uint32_t thread_excl = wave_off + incl - sum;
+    if (w == 0) {
+        if (tile == 0) {
+            if (lane == 0) {
+                st_status(&status[0], kFlagIncl | agg);
+                s_prefix = 0;
+            }
+        } else {
+            if (lane == 0) st_status(&status[tile], kFlagAgg | agg);
+            uint32_t excl = 0;
+            int64_t k = tile - 1;
+            while (true) {
+                const int64_t t = k - lane;
+                unsigned long long sv;
+                while (true) {
+                    sv = (t >= 0) ? ld_status(&status[t]) : kFlagIncl;
+                    if (!__any((sv >> 32) == 0)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                const unsigned long long incl_mask = __ballot((sv >> 32) == 2);
+                const int first = incl_mask ? __ffsll((long long)incl_mask) - 1 : kWave;
+                uint32_t c = (lane <= first) ? (uint32_t)(sv & 0xFFFFFFFFull) : 0u;
+                for (int d = kWave / 2; d > 0; d >>= 1) c += (uint32_t)__shfl_xor((int)c, d, kWave);
+                excl += c;
+                if (incl_mask) break;
+                k -= kWave;
+            }
+            if (lane == 0) {
+                st_status(&status[tile], kFlagIncl | (unsigned long long)(excl + agg));
+                s_prefix = excl;
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t run = s_prefix + thread_excl;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t g = base + k;
+        if (g < total) {
+            off[g] = run;
+            vm[run] = 0u;
+            vm[run + 1] = h[k];
+            run += h[k] + 2u;
+            if (g == total - 1) off[total] = run;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// scatter: point i of pair p goes to its voxel's compact slot (any order)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ vox, const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ off, uint32_t* __restrict__ tmp)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t gi = P.q_base + i;
+    const int64_t g = P.v_base + vox[gi];
+    const int64_t pos = (int64_t)off[g] - 2 * g + rank[gi];
+    tmp[pos] = (uint32_t)i;
+}
+
+// --------------------------------------------------------------------------
+// canonical order: each compact slot k holds point e of voxel g; its final
+// position is the number of points of g with a smaller index (ascending
+// order, the reading of Alg. 2 that removes the lock-order dependence).
+// Also writes the segment-ordered float4 copy of the target.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict__ qx, const float* __restrict__ qy,
+                                                        const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                                        const BlockJob* __restrict__ jobs, const uint32_t* __restrict__ vox,
+                                                        const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ tmp, uint32_t* __restrict__ vm,
+                                                        float4* __restrict__ qs4)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t k = (int64_t)job.start + threadIdx.x;
+    if (k >= P.n) return;
+    const uint32_t e = tmp[P.q_base + k];
+    const int64_t ge = P.q_base + e;
+    const int64_t g = P.v_base + vox[ge];
+    const uint32_t og = off[g];
+    const int64_t cs = (int64_t)og - 2 * g;
+    const uint32_t c = hist[g];
+    uint32_t r = 0;
+    for (uint32_t t = 0; t < c; ++t) r += (tmp[cs + t] < e) ? 1u : 0u;
+    vm[(int64_t)og + 2 + r] = e;
+    qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+void launch_box_init(uint32_t* box, int npairs, hipStream_t s)
+{
+    const int n = npairs * 8;
+    hipLaunchKernelGGL(k_box_init, dim3((n + 255) / 256), dim3(256), 0, s, box, npairs);
+}
+
+void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
+                 int njobs, int items_per_block, uint32_t* box, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_aabb, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, items_per_block, box);
+}
+
+void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
+                  int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_count, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
+}
+
+int scan_tiles(int64_t total) { return (int)((total + kScanTile - 1) / kScanTile); }
+
+void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, unsigned long long* status,
+                 uint32_t* ticket, hipStream_t s)
+{
+    const int tiles = scan_tiles(total);
+    if (tiles <= 0) return;
+    hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
+}
+
+void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* rank,
+                  const uint32_t* off, uint32_t* tmp, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_place, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, vox, rank, off, tmp);
+}
+
+void launch_rank_sort(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
+                      int njobs, const uint32_t* vox, const uint32_t* hist, const uint32_t* off, const uint32_t* tmp,
+                      uint32_t* vm, float4* qs4, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_rank_sort, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm,
+                       qs4);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+}
+
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+}
+
+}  // namespace vicp

@@ -1,0 +1,227 @@
+// k_solve.hip -- the closed-form rigid transform of Eq. 1 per pair, in
+// float64, and the ICP iteration bookkeeping (Sec. II.A; stop rule of
+// Sec. IV.A).  One block per pair reduces that pair's per-block moment
+// partials in a fixed order, then one lane forms the cross-covariance
+// H = sum (p - pbar)(q - qbar)^T = sum p q^T - m pbar qbar^T, takes its SVD
+// H = U S V^T by one-sided Jacobi, and sets R = V diag(1, 1, det(V U^T)) U^T,
+// t = qbar - R pbar.  When the second singular value is below 1e-12 times the
+// first, the rotation is not determined and the previous pose is kept.
+#include <math.h>
+
+#include "vicp_internal.hpp"
+
+namespace vicp {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ void svd3(double A[3][3], double U[3][3], double sig[3], double V[3][3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    // one-sided Jacobi: rotate column pairs of A until they are orthogonal
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double worst = 0.0;
+        for (int p = 0; p < 2; ++p) {
+            for (int q = p + 1; q < 3; ++q) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    al += A[r][p] * A[r][p];
+                    be += A[r][q] * A[r][q];
+                    ga += A[r][p] * A[r][q];
+                }
+                if (ga == 0.0) continue;
+                const double rel = fabs(ga) / sqrt(al * be);
+                worst = fmax(worst, rel);
+                if (!(rel > 1e-15)) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int r = 0; r < 3; ++r) {
+                    const double ap = A[r][p], aq = A[r][q];
+                    A[r][p] = c * ap - s * aq;
+                    A[r][q] = s * ap + c * aq;
+                    const double vp = V[r][p], vq = V[r][q];
+                    V[r][p] = c * vp - s * vq;
+                    V[r][q] = s * vp + c * vq;
+                }
+            }
+        }
+        if (!(worst > 1e-15)) break;
+    }
+    for (int j = 0; j < 3; ++j) {
+        double nrm = 0.0;
+        for (int r = 0; r < 3; ++r) nrm += A[r][j] * A[r][j];
+        sig[j] = sqrt(nrm);
+    }
+    // order by decreasing singular value (columns of A and V move together)
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (sig[b] > sig[a]) {
+                const double ts = sig[a];
+                sig[a] = sig[b];
+                sig[b] = ts;
+                for (int r = 0; r < 3; ++r) {
+                    double t = A[r][a];
+                    A[r][a] = A[r][b];
+                    A[r][b] = t;
+                    t = V[r][a];
+                    V[r][a] = V[r][b];
+                    V[r][b] = t;
+                }
+            }
+    for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 3; ++r) U[r][j] = sig[j] > 0.0 ? A[r][j] / sig[j] : 0.0;
+    if (sig[2] > 1e-13 * sig[0]) {
+        for (int r = 0; r < 3; ++r) U[r][2] = A[r][2] / sig[2];
+    } else {
+        // complete the basis: the third left vector of a rank-2 H is free
+        U[0][2] = U[1][0] * U[2][1] - U[2][0] * U[1][1];
+        U[1][2] = U[2][0] * U[0][1] - U[0][0] * U[2][1];
+        U[2][2] = U[0][0] * U[1][1] - U[1][0] * U[0][1];
+    }
+}
+
+__device__ double det3(const double M[3][3])
+{
+    return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+// Returns false (pose untouched) when H has rank < 2.
+__device__ bool kabsch(const double* mom, double Rt[12])
+{
+    const double m = mom[16];
+    if (!(m > 0.0)) return false;
+    double pb[3], qb[3], H[3][3];
+    for (int a = 0; a < 3; ++a) {
+        pb[a] = mom[a] / m;
+        qb[a] = mom[3 + a] / m;
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) H[a][b] = mom[6 + 3 * a + b] - m * pb[a] * qb[b];
+    double U[3][3], sig[3], V[3][3];
+    svd3(H, U, sig, V);
+    if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0]) return false;
+    const double d = (det3(U) * det3(V) < 0.0) ? -1.0 : 1.0;
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + d * V[i][2] * U[j][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Rt[3 * i + j] = R[i][j];
+    for (int i = 0; i < 3; ++i) Rt[9 + i] = qb[i] - (R[i][0] * pb[0] + R[i][1] * pb[1] + R[i][2] * pb[2]);
+    return true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin,
+                                                    const double* __restrict__ part, PairState* __restrict__ st,
+                                                    int32_t* __restrict__ fb_count, double* __restrict__ rmse_hist,
+                                                    int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist, int k,
+                                                    int K, int early_stop, double eps)
+{
+    __shared__ double red[kMoments][kThreads];
+    __shared__ double tot[kMoments];
+    const int pair = blockIdx.x;
+    PairState& S = st[pair];
+    if (S.done) return;
+    const int32_t b0 = job_begin[pair], b1 = job_begin[pair + 1];
+    double acc[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += kThreads) {
+#pragma unroll
+        for (int j = 0; j < kMoments; ++j) acc[j] += part[(int64_t)b * kMoments + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) red[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int j = 0; j < kMoments; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kMoments) tot[threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double m = tot[16];
+    const double rmse = m > 0.0 ? sqrt(tot[15] / m) : 0.0;
+    double Rt[12];
+    for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
+    const bool ok = kabsch(tot, Rt);
+    if (ok) {
+        for (int j = 0; j < 12; ++j) {
+            S.Rt[j] = Rt[j];
+            S.Rtf[j] = (float)Rt[j];
+        }
+    } else {
+        S.degenerate += 1;
+    }
+    rmse_hist[(int64_t)pair * K + k] = rmse;
+    fb_hist[(int64_t)pair * K + k] = fb_count[pair];
+    deg_hist[(int64_t)pair * K + k] = ok ? 0 : 1;
+    fb_count[pair] = 0;
+    S.iters = k + 1;
+    if (early_stop && k >= 1 && fabs(rmse - S.prev_rmse) < eps) S.done = 1;
+    S.prev_rmse = rmse;
+}
+
+// Initial state: pose rounded to float32 for the search; pairs with no
+// source points are done from the start.
+__global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restrict__ st, const double* __restrict__ rt64,
+                            int npairs)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    PairState& S = st[p];
+    S.done = pd[p].m > 0 ? 0 : 1;
+    for (int j = 0; j < 12; ++j) {
+        S.Rt[j] = rt64[12 * p + j];
+        S.Rtf[j] = (float)rt64[12 * p + j];
+    }
+    S.prev_rmse = 0.0;
+    S.iters = 0;
+    S.degenerate = 0;
+    S.status = 0;
+}
+
+}  // namespace
+
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st,
+                  int32_t* fb_count, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist, int k, int K,
+                  int early_stop, double eps, hipStream_t s)
+{
+    if (npairs <= 0) return;
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, rmse_hist,
+                       fb_hist, deg_hist, k, K, early_stop, eps);
+}
+
+void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)
+{
+    if (npairs <= 0) return;
+    hipLaunchKernelGGL(k_set_state, dim3((npairs + 63) / 64), dim3(64), 0, s, pd, st, rt64, npairs);
+}
+
+// Flags pairs whose source holds NaN or Inf (bit 0 of PairState::status).
+__global__ void k_check_finite(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                               const float* __restrict__ px, const float* __restrict__ py,
+                               const float* __restrict__ pz, int32_t* __restrict__ flags)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.m) return;
+    const int64_t g = P.p_base + i;
+    if (!(isfinite(px[g]) && isfinite(py[g]) && isfinite(pz[g]))) atomicOr(&flags[job.pair], 1);
+}
+
+void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                         const float* pz, int32_t* flags, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_check_finite, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, flags);
+}
+
+}  // namespace vicp

@@ -1,0 +1,1047 @@
+// vicp_api.hip -- host runtime behind the C ABI of include/vicp.h.
+//
+// It sizes grids, owns device memory, builds the per-block work tables,
+// queues the kernels of k_*.hip on the caller's stream, captures the ICP
+// iterations in a hipGraph when asked, and reads results back.  No
+// arithmetic of the method runs on the host except the grid specification
+// (float32 scalar code, identical rounding to the device's).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vicp.h"
+#include "vicp_internal.hpp"
+
+using namespace vicp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define VICP_HIP(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(VICP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- utilities
+
+// Small host -> device uploads travel as kernel arguments, so they never
+// depend on the lifetime of the caller's host buffer and can be captured.
+constexpr int kBlobWords = 512;
+struct Blob {
+    uint32_t w[kBlobWords];
+};
+
+__global__ void k_upload(Blob b, uint32_t* dst, int nwords)
+{
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = b.w[i];
+}
+
+void upload(const void* host, size_t bytes, void* dst, hipStream_t s)
+{
+    const uint32_t* src = (const uint32_t*)host;
+    size_t words = bytes / 4;
+    uint32_t* d = (uint32_t*)dst;
+    while (words > 0) {
+        Blob b;
+        const int n = (int)std::min<size_t>(words, kBlobWords);
+        memcpy(b.w, src, (size_t)n * 4);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, b, d, n);
+        src += n;
+        d += n;
+        words -= n;
+    }
+}
+
+__global__ void k_export_off(const uint32_t* __restrict__ off, int64_t count, uint32_t base, uint32_t* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = off[i] - base;
+}
+
+__global__ void k_grid_stats(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
+                             const uint32_t* __restrict__ vm, int64_t V, unsigned long long* out)
+{
+    unsigned long long occ = 0, dil = 0;
+    uint32_t mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = hist[v];
+        if (h) {
+            occ += 1;
+            mx = max(mx, h);
+        } else if (vm[(int64_t)off[v] + 1] & kMask) {
+            dil += 1;
+        }
+    }
+    if (occ) atomicAdd(&out[0], occ);
+    if (dil) atomicAdd(&out[1], dil);
+    if (mx) atomicMax(&out[2], (unsigned long long)mx);
+}
+
+// ----------------------------------------------------------- per-kernel timing
+
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> acc;
+} g_prof;
+
+hipEvent_t prof_event()
+{
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void prof_flush_locked()
+{
+    for (auto& r : g_prof.recs) {
+        float ms = 0.0f;
+        (void)hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto& x = g_prof.acc[r.name];
+            x.first += 1;
+            x.second += ms;
+        }
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+}
+
+// Brackets one launch with events when timing is on and the stream is not
+// being captured.
+struct ProfScope {
+    hipStream_t s;
+    const char* name;
+    hipEvent_t b = nullptr;
+    ProfScope(const char* nm, hipStream_t st, bool capturing) : s(st), name(nm)
+    {
+        if (!g_prof.on || capturing) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        hipEvent_t a = prof_event();
+        b = prof_event();
+        (void)hipEventRecord(a, s);
+        g_prof.recs.push_back({name, a, b});
+    }
+    ~ProfScope()
+    {
+        if (b) (void)hipEventRecord(b, s);
+    }
+};
+
+// ---------------------------------------------------------------- memory
+
+struct Mem {
+    vicp_allocator a{};
+    bool custom = false;
+    void* get(size_t bytes, hipStream_t s)
+    {
+        bytes = std::max<size_t>(bytes, 256);
+        if (custom) return a.alloc(bytes, s, a.user);
+        void* p = nullptr;
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+            (void)hipGetLastError();
+            if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, size_t bytes, hipStream_t s)
+    {
+        if (!p) return;
+        bytes = std::max<size_t>(bytes, 256);
+        if (custom) {
+            a.free(p, bytes, s, a.user);
+            return;
+        }
+        if (hipFreeAsync(p, s) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p);
+        }
+    }
+};
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PairHost {
+    int64_t n = 0, q_base = 0, V = 0, v_base = 0, vm_base = 0;
+    float origin[3] = {0, 0, 0}, inv = 0, voxel = 0;
+    int32_t dims[3] = {0, 0, 0};
+};
+
+// Block table: every block serves one pair; `items` items per block.
+void make_jobs(const std::vector<int64_t>& counts, int items, std::vector<BlockJob>& jobs, std::vector<int32_t>* begin)
+{
+    jobs.clear();
+    if (begin) begin->assign(1, 0);
+    for (size_t p = 0; p < counts.size(); ++p) {
+        for (int64_t s = 0; s < counts[p]; s += items) jobs.push_back({(int32_t)p, (int32_t)s});
+        if (begin) begin->push_back((int32_t)jobs.size());
+    }
+}
+
+constexpr int kBlockSizes[4] = {64, 128, 256, 512};
+
+int block_slot(int bs)
+{
+    for (int i = 0; i < 4; ++i)
+        if (kBlockSizes[i] == bs) return i;
+    return 2;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ the grid
+
+struct vicp_grid {
+    int B = 0;
+    const float *qx = nullptr, *qy = nullptr, *qz = nullptr;
+    int64_t n_total = 0, V_total = 0, vm_words = 0;
+    int32_t pad = 0, rings_applied = 0;
+    bool dilated = false;
+    std::vector<PairHost> pairs;
+    Mem mem;
+    std::vector<Buf> owned;
+
+    PairDev* d_pd = nullptr;
+    uint32_t *hist = nullptr, *off = nullptr, *vm = nullptr;
+    float4* qs4 = nullptr;
+    BlockJob* jobs_q = nullptr;
+    int njobs_q = 0;
+    BlockJob* jobs_v = nullptr;
+    int njobs_v = 0;
+    uint32_t* err = nullptr;
+
+    // tuning choices (result-invariant)
+    int nns_block = 256;
+    int fb_grid = 512;
+    int dil_block = 256;
+
+    // source workspace
+    std::vector<int64_t> m;   // source layout currently in d_pd / tables
+    int64_t m_total = -1;
+    int K_cap = 0;
+    PairState* st = nullptr;
+    void* staging = nullptr;
+    int32_t* fb_count = nullptr;
+    uint32_t* fb_list = nullptr;
+    unsigned long long* fb_key = nullptr;
+    int32_t* nn_idx = nullptr;
+    float* nn_d2 = nullptr;
+    double* part = nullptr;
+    int32_t* job_begin = nullptr;
+    BlockJob* jobs_p[4] = {nullptr, nullptr, nullptr, nullptr};
+    int njobs_p[4] = {0, 0, 0, 0};
+    int32_t* flags = nullptr;
+    double* jl6 = nullptr;
+    double* rmse_hist = nullptr;
+    int32_t* fb_hist = nullptr;
+    int32_t* deg_hist = nullptr;
+    std::vector<Buf> ws_bufs;
+
+    // captured registration
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<uintptr_t> gkey;
+
+    int32_t latched = 0;   // device faults seen at the last sync
+
+    void* take(size_t bytes, hipStream_t s, std::vector<Buf>& list)
+    {
+        void* p = mem.get(bytes, s);
+        if (p) list.push_back({p, bytes});
+        return p;
+    }
+    void release(std::vector<Buf>& list, hipStream_t s)
+    {
+        for (auto& b : list) mem.put(b.p, b.bytes, s);
+        list.clear();
+    }
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        gkey.clear();
+    }
+};
+
+namespace {
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusActive;
+}
+
+// (Re)build the source-side device state for a per-pair source layout.
+// Synchronises when the layout changes (rare), so that host staging can be
+// released safely.
+int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
+{
+    std::vector<int64_t> m(m_per_pair, m_per_pair + g->B);
+    for (auto v : m)
+        if (v < 0 || v > (int64_t)INT32_MAX) return fail(VICP_ERR_INVALID_ARG, "source size out of range");
+    const bool same = (m == g->m);
+    if (same && K <= g->K_cap) return VICP_OK;
+    VICP_HIP(hipStreamSynchronize(s));
+    g->drop_graph();
+    g->release(g->ws_bufs, s);
+    const int B = g->B;
+    int64_t mt = 0;
+    for (auto v : m) mt += v;
+    const int Kc = std::max(K, std::max(g->K_cap, 1));
+    // device pair table with the source fields
+    std::vector<PairDev> pd(B);
+    int64_t pb = 0;
+    for (int p = 0; p < B; ++p) {
+        const PairHost& h = g->pairs[p];
+        PairDev& d = pd[p];
+        d.q_base = h.q_base;
+        d.n = h.n;
+        d.v_base = h.v_base;
+        d.V = h.V;
+        d.p_base = pb;
+        d.m = m[p];
+        d.ox = h.origin[0];
+        d.oy = h.origin[1];
+        d.oz = h.origin[2];
+        d.inv = h.inv;
+        d.Dx = h.dims[0];
+        d.Dy = h.dims[1];
+        d.Dz = h.dims[2];
+        d.fDx = (float)h.dims[0];
+        d.fDy = (float)h.dims[1];
+        d.fDz = (float)h.dims[2];
+        d.pad = g->pad;
+        pb += m[p];
+    }
+    VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
+    std::vector<BlockJob> jobs[4];
+    std::vector<int32_t> begin;
+    for (int k = 0; k < 4; ++k) make_jobs(m, kBlockSizes[k], jobs[k], k == 2 ? &begin : nullptr);
+    auto& L = g->ws_bufs;
+    const size_t mt1 = (size_t)std::max<int64_t>(mt, 1);
+    g->st = (PairState*)g->take(sizeof(PairState) * B, s, L);
+    g->staging = g->take(sizeof(double) * 12 * B, s, L);
+    g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L);
+    g->flags = (int32_t*)g->take(sizeof(int32_t) * B, s, L);
+    g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L);
+    g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L);
+    g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L);
+    g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L);
+    g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[2].size(), 1), s, L);
+    g->job_begin = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L);
+    g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L);
+    g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L);
+    g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
+    g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
+    for (int k = 0; k < 4; ++k) {
+        g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L);
+        g->njobs_p[k] = (int)jobs[k].size();
+    }
+    if (L.size() != 18) {
+        g->release(g->ws_bufs, s);
+        g->m.clear();
+        g->K_cap = 0;
+        return fail(VICP_ERR_OOM, "workspace allocation failed");
+    }
+    for (int k = 0; k < 4; ++k)
+        if (!jobs[k].empty())
+            VICP_HIP(hipMemcpyAsync(g->jobs_p[k], jobs[k].data(), sizeof(BlockJob) * jobs[k].size(),
+                                    hipMemcpyHostToDevice, s));
+    VICP_HIP(hipMemcpyAsync(g->job_begin, begin.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    VICP_HIP(hipStreamSynchronize(s));
+    g->m = m;
+    g->m_total = mt;
+    g->K_cap = Kc;
+    return VICP_OK;
+}
+
+int check_grid(const vicp_grid* g)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (!g->hist) return fail(VICP_ERR_STATE, "grid not built");
+    return VICP_OK;
+}
+
+// Correspondence search for every pair at the poses in g->st (Alg. 4).
+void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
+                  hipStream_t s, bool cap)
+{
+    const int slot = block_slot(g->nns_block);
+    {
+        ProfScope ps("nns_local", s, cap);
+        launch_nns_local(g->d_pd, g->jobs_p[slot], g->njobs_p[slot], g->nns_block, px, py, pz, g->st, g->off, g->vm,
+                         g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, s);
+    }
+    {
+        ProfScope ps("fallback", s, cap);
+        launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count, g->fb_list,
+                        g->fb_key, s);
+    }
+}
+
+void queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
+                     double eps, hipStream_t s, bool cap)
+{
+    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
+    {
+        ProfScope ps("moments", s, cap);
+        launch_moments(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+                       g->nn_idx, g->nn_d2, g->part, g->flags, s);
+    }
+    {
+        ProfScope ps("solve", s, cap);
+        launch_solve(g->d_pd, g->B, g->job_begin, g->part, g->st, g->fb_count, g->rmse_hist, g->fb_hist, g->deg_hist,
+                     k, K, early, eps, s);
+    }
+}
+
+// float32 grid specification of one pair from its bounding box (host code,
+// compiled without contraction: the same roundings as the device).
+int grid_spec(PairHost& h, const float lo[3], const float hi[3], float voxel, int32_t pad)
+{
+    const float inv = 1.0f / voxel;
+    const float padw = (float)pad * voxel;
+    int64_t V = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.origin[a] = lo[a] - padw;
+        const float f = (hi[a] - h.origin[a]) * inv;
+        if (!(f < 1073741824.0f)) return fail(VICP_ERR_GRID_TOO_LARGE, "grid too large (voxels per axis)");
+        const int64_t d = (int64_t)floorf(f) + 1 + pad;
+        if (d > INT32_MAX) return fail(VICP_ERR_GRID_TOO_LARGE, "grid too large (voxels per axis)");
+        h.dims[a] = (int32_t)d;
+        V *= d;
+        if (V >= (int64_t)1 << 31) return fail(VICP_ERR_GRID_TOO_LARGE, "grid has 2^31 voxels or more");
+    }
+    if (h.n + 2 * V >= (int64_t)1 << 32) return fail(VICP_ERR_GRID_TOO_LARGE, "n + 2V does not fit 32-bit offsets");
+    h.inv = inv;
+    h.voxel = voxel;
+    h.V = V;
+    return VICP_OK;
+}
+
+float unordered(uint32_t k)
+{
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* vicp_version(void) { return "vicp 0.1 (gfx950)"; }
+
+const char* vicp_last_error(void) { return g_err.c_str(); }
+
+const char* vicp_status_str(int code)
+{
+    switch (code) {
+    case VICP_OK: return "ok";
+    case VICP_ERR_INVALID_ARG: return "invalid argument";
+    case VICP_ERR_GRID_TOO_LARGE: return "grid too large";
+    case VICP_ERR_OOM: return "out of device memory";
+    case VICP_ERR_HIP: return "HIP runtime error";
+    case VICP_ERR_STATE: return "call out of order";
+    case VICP_ERR_NONFINITE: return "non-finite coordinates";
+    case VICP_ERR_DEGENERATE: return "degenerate cross-covariance (pose kept)";
+    default: return "unknown status";
+    }
+}
+
+int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, const int64_t* n_per_pair, int32_t npairs,
+                            const float* voxel_per_pair, int32_t pad_rings, const vicp_allocator* alloc,
+                            hipStream_t s, vicp_grid** out)
+{
+    if (!out) return fail(VICP_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (!qx || !qy || !qz || !n_per_pair || !voxel_per_pair) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    if (npairs < 1 || npairs > 4096) return fail(VICP_ERR_INVALID_ARG, "npairs must be in [1, 4096]");
+    if (pad_rings < 0 || pad_rings > 1024) return fail(VICP_ERR_INVALID_ARG, "pad_rings must be in [0, 1024]");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(VICP_ERR_INVALID_ARG, "allocator without functions");
+    std::vector<PairHost> pairs(npairs);
+    int64_t nt = 0;
+    for (int p = 0; p < npairs; ++p) {
+        if (n_per_pair[p] <= 0 || n_per_pair[p] > (int64_t)INT32_MAX)
+            return fail(VICP_ERR_INVALID_ARG, "every pair needs 1 .. 2^31-1 target points");
+        const float vx = voxel_per_pair[p];
+        if (!(vx > 0.0f) || !isfinite(vx)) return fail(VICP_ERR_INVALID_ARG, "voxel must be finite and > 0");
+        pairs[p].n = n_per_pair[p];
+        pairs[p].q_base = nt;
+        nt += n_per_pair[p];
+    }
+    vicp_grid* g = new vicp_grid();
+    g->B = npairs;
+    g->qx = qx;
+    g->qy = qy;
+    g->qz = qz;
+    g->pad = pad_rings;
+    g->n_total = nt;
+    if (alloc) {
+        g->mem.a = *alloc;
+        g->mem.custom = true;
+    }
+    auto bail = [&](int rc) {
+        vicp_grid_free(g);
+        return rc;
+    };
+    // pass 1: bounding boxes (the one synchronisation of the build)
+    std::vector<int64_t> ncount(npairs);
+    for (int p = 0; p < npairs; ++p) ncount[p] = pairs[p].n;
+    std::vector<BlockJob> jq;
+    make_jobs(ncount, 256, jq, nullptr);
+    if (jq.size() > (size_t)INT32_MAX) return bail(fail(VICP_ERR_INVALID_ARG, "too many points"));
+    std::vector<PairDev> pd(npairs);
+    for (int p = 0; p < npairs; ++p) {
+        pd[p] = PairDev{};
+        pd[p].q_base = pairs[p].q_base;
+        pd[p].n = pairs[p].n;
+    }
+    g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned);
+    g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned);
+    uint32_t* box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * npairs, s, g->owned);
+    g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned);
+    if (!g->d_pd || !g->jobs_q || !box || !g->err) return bail(fail(VICP_ERR_OOM, "allocation failed"));
+    g->njobs_q = (int)jq.size();
+    if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g->jobs_q, jq.data(), sizeof(BlockJob) * jq.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(VICP_ERR_HIP, "upload failed"));
+    launch_box_init(box, npairs, s);
+    launch_fill_u32(g->err, 0u, 4, s);
+    {
+        ProfScope ps("aabb", s, false);
+        launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, 256, box, s);
+    }
+    std::vector<uint32_t> hbox(8 * npairs);
+    if (hipMemcpyAsync(hbox.data(), box, sizeof(uint32_t) * 8 * npairs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(VICP_ERR_HIP, std::string("bounding box: ") + hipGetErrorString(hipGetLastError())));
+    int64_t Vt = 0, words = 0;
+    for (int p = 0; p < npairs; ++p) {
+        const uint32_t* b = &hbox[8 * p];
+        if (b[6]) return bail(fail(VICP_ERR_NONFINITE, "non-finite target coordinates"));
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = unordered(b[a]);
+            hi[a] = unordered(b[3 + a]);
+        }
+        int rc = grid_spec(pairs[p], lo, hi, voxel_per_pair[p], pad_rings);
+        if (rc) return bail(rc);
+        pairs[p].v_base = Vt;
+        pairs[p].vm_base = words;
+        Vt += pairs[p].V;
+        words += pairs[p].n + 2 * pairs[p].V;
+    }
+    if (Vt >= ((int64_t)1 << 31) || words >= ((int64_t)1 << 32))
+        return bail(fail(VICP_ERR_GRID_TOO_LARGE, "batch exceeds 2^31 voxels or 2^32 index words"));
+    g->pairs = pairs;
+    g->V_total = Vt;
+    g->vm_words = words;
+    for (int p = 0; p < npairs; ++p) {
+        const PairHost& h = pairs[p];
+        PairDev& d = pd[p];
+        d.v_base = h.v_base;
+        d.V = h.V;
+        d.ox = h.origin[0];
+        d.oy = h.origin[1];
+        d.oz = h.origin[2];
+        d.inv = h.inv;
+        d.Dx = h.dims[0];
+        d.Dy = h.dims[1];
+        d.Dz = h.dims[2];
+        d.fDx = (float)h.dims[0];
+        d.fDy = (float)h.dims[1];
+        d.fDz = (float)h.dims[2];
+        d.pad = pad_rings;
+    }
+    std::vector<int64_t> vcount(npairs);
+    for (int p = 0; p < npairs; ++p) vcount[p] = pairs[p].V;
+    std::vector<BlockJob> jv;
+    make_jobs(vcount, 256, jv, nullptr);
+    // pass 2: counts, offsets, segments
+    g->hist = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->owned);
+    g->off = (uint32_t*)g->take(sizeof(uint32_t) * (Vt + 1), s, g->owned);
+    g->vm = (uint32_t*)g->take(sizeof(uint32_t) * words, s, g->owned);
+    g->qs4 = (float4*)g->take(sizeof(float4) * nt, s, g->owned);
+    g->jobs_v = (BlockJob*)g->take(sizeof(BlockJob) * jv.size(), s, g->owned);
+    const int tiles = scan_tiles(Vt);
+    std::vector<Buf> tmp;
+    uint32_t* vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
+    uint32_t* rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
+    uint32_t* slots = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
+    unsigned long long* status = (unsigned long long*)g->take(sizeof(unsigned long long) * tiles, s, tmp);
+    uint32_t* ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, tmp);
+    if (!g->hist || !g->off || !g->vm || !g->qs4 || !g->jobs_v || !vox || !rank || !slots || !status || !ticket) {
+        g->release(tmp, s);
+        return bail(fail(VICP_ERR_OOM, "grid allocation failed"));
+    }
+    g->njobs_v = (int)jv.size();
+    if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g->jobs_v, jv.data(), sizeof(BlockJob) * jv.size(), hipMemcpyHostToDevice, s) != hipSuccess) {
+        g->release(tmp, s);
+        return bail(fail(VICP_ERR_HIP, "upload failed"));
+    }
+    launch_fill_u32(g->hist, 0u, Vt, s);
+    launch_fill_u64(status, 0ull, tiles, s);
+    launch_fill_u32(ticket, 0u, 4, s);
+    {
+        ProfScope ps("count", s, false);
+        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, vox, rank, g->err, s);
+    }
+    {
+        ProfScope ps("scan", s, false);
+        launch_scan(g->hist, Vt, g->off, g->vm, status, ticket, s);
+    }
+    {
+        ProfScope ps("place", s, false);
+        launch_place(g->d_pd, g->jobs_q, g->njobs_q, vox, rank, g->off, slots, s);
+    }
+    {
+        ProfScope ps("rank_sort", s, false);
+        launch_rank_sort(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, vox, g->hist, g->off, slots, g->vm, g->qs4, s);
+    }
+    g->release(tmp, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bail(fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e)));
+    *out = g;
+    return VICP_OK;
+}
+
+int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n, float voxel, int32_t pad_rings,
+                    const vicp_allocator* alloc, hipStream_t s, vicp_grid** out)
+{
+    return vicp_build_grid_batched(qx, qy, qz, &n, 1, &voxel, pad_rings, alloc, s, out);
+}
+
+int vicp_grid_npairs(const vicp_grid* g) { return g ? g->B : 0; }
+
+int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (g->dilated) return fail(VICP_ERR_STATE, "grid already dilated");
+    if (rings < 0 || rings > g->pad) return fail(VICP_ERR_INVALID_ARG, "rings must be in [0, pad_rings]");
+    g->dilated = true;
+    g->rings_applied = rings;
+    if (rings == 0) return VICP_OK;
+    std::vector<Buf> tmp;
+    uint32_t* a = nullptr;
+    uint32_t* b = nullptr;
+    if (rings > 1) {
+        a = (uint32_t*)g->take(sizeof(uint32_t) * g->V_total, s, tmp);
+        b = (uint32_t*)g->take(sizeof(uint32_t) * g->V_total, s, tmp);
+        if (!a || !b) {
+            g->release(tmp, s);
+            return fail(VICP_ERR_OOM, "dilation state allocation failed");
+        }
+    }
+    const bool cap = capturing(s);
+    for (int r = 1; r <= rings; ++r) {
+        ProfScope ps("dilate_ring", s, cap);
+        launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, 256, g->hist, g->off, g->vm, r == 1 ? nullptr : a,
+                           r == rings ? nullptr : b, r == 1, r == rings, s);
+        std::swap(a, b);
+    }
+    g->release(tmp, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("dilate: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                     const float* Rt, int32_t* nn_idx, float* nn_d2, int32_t* n_fallback, hipStream_t s)
+{
+    vicp_grid* g = const_cast<vicp_grid*>(gc);
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!m_per_pair || !Rt) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    int64_t mt = 0;
+    for (int p = 0; p < g->B; ++p) mt += std::max<int64_t>(m_per_pair[p], 0);
+    if (mt == 0) {
+        if (n_fallback) {
+            std::vector<int32_t> z(g->B, 0);
+            upload(z.data(), sizeof(int32_t) * g->B, n_fallback, s);
+        }
+        return ensure_source(g, m_per_pair, 1, s);
+    }
+    if (!px || !py || !pz || !nn_idx || !nn_d2) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    rc = ensure_source(g, m_per_pair, 1, s);
+    if (rc) return rc;
+    const bool cap = capturing(s);
+    // poses: float32 for the search; the float64 field is not used here
+    std::vector<double> rt64(12 * g->B);
+    for (int i = 0; i < 12 * g->B; ++i) rt64[i] = (double)Rt[i];
+    upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
+    launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
+    queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap);
+    {
+        ProfScope ps("fb_finalize", s, cap);
+        launch_fb_finalize(g->d_pd, g->jobs_p[2], g->njobs_p[2], g->fb_key, nn_idx, nn_d2, g->flags, s);
+    }
+    if (n_fallback) launch_copy_fb(g->fb_count, n_fallback, g->B, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("nns: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_nns(const vicp_grid* g, const float* px, const float* py, const float* pz, int64_t m, const float Rt[12],
+             int32_t* nn_idx, float* nn_d2, int32_t* n_fallback, hipStream_t s)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (g->B != 1) return fail(VICP_ERR_INVALID_ARG, "vicp_nns needs a single-pair grid");
+    if (m < 0) return fail(VICP_ERR_INVALID_ARG, "m < 0");
+    return vicp_nns_batched(g, px, py, pz, &m, Rt, nn_idx, nn_d2, n_fallback, s);
+}
+
+int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz,
+                          const int64_t* m_per_pair, const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats,
+                          hipStream_t s)
+{
+    vicp_grid* g = const_cast<vicp_grid*>(gc);
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!m_per_pair || !o || !Rt_io) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    if (o->max_iter < 0 || o->max_iter > 100000) return fail(VICP_ERR_INVALID_ARG, "max_iter out of range");
+    if (!(o->rmse_eps >= 0.0)) return fail(VICP_ERR_INVALID_ARG, "rmse_eps must be >= 0");
+    const int B = g->B;
+    for (int i = 0; i < 12 * B; ++i)
+        if (!isfinite(Rt_io[i])) return fail(VICP_ERR_INVALID_ARG, "non-finite initial pose");
+    int64_t mt = 0;
+    for (int p = 0; p < B; ++p) mt += std::max<int64_t>(m_per_pair[p], 0);
+    if (stats)
+        for (int p = 0; p < B; ++p) {
+            stats[p].iters = 0;
+            stats[p].degenerate = 0;
+        }
+    const int K = o->max_iter;
+    if (mt == 0 || K == 0) return ensure_source(g, m_per_pair, 1, s);
+    if (!px || !py || !pz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    rc = ensure_source(g, m_per_pair, K, s);
+    if (rc) return rc;
+    const int early = o->early_stop ? 1 : 0;
+    const double eps = o->rmse_eps;
+    upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, s);
+    launch_fill_u32((uint32_t*)g->flags, 0u, B, s);
+    launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
+    if (o->use_graph) {
+        std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
+                                      (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid};
+        uint64_t eb;
+        memcpy(&eb, &eps, 8);
+        key.push_back((uintptr_t)eb);
+        if (!g->gexec || key != g->gkey) {
+            g->drop_graph();
+            if (!g->cap_stream) VICP_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true);
+            VICP_HIP(hipStreamEndCapture(g->cap_stream, &graph));
+            hipError_t e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                g->gexec = nullptr;
+                return fail(VICP_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            g->gkey = key;
+        }
+        ProfScope ps("icp_graph", s, false);
+        VICP_HIP(hipGraphLaunch(g->gexec, s));
+    } else {
+        const bool cap = capturing(s);
+        for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap);
+    }
+    std::vector<PairState> hst(B);
+    std::vector<double> hr((size_t)B * g->K_cap);
+    std::vector<int32_t> hf((size_t)B * g->K_cap), hd((size_t)B * g->K_cap), hflags(B);
+    VICP_HIP(hipMemcpyAsync(hst.data(), g->st, sizeof(PairState) * B, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(hr.data(), g->rmse_hist, sizeof(double) * B * K, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(hf.data(), g->fb_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(hd.data(), g->deg_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(hflags.data(), g->flags, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipStreamSynchronize(s));
+    bool nonfinite = false, degenerate = false, internal = false;
+    for (int p = 0; p < B; ++p) {
+        memcpy(Rt_io + 12 * p, hst[p].Rt, sizeof(double) * 12);
+        nonfinite |= (hflags[p] & 1) != 0;
+        internal |= (hflags[p] & 2) != 0;
+        degenerate |= hst[p].degenerate != 0;
+        if (stats) {
+            vicp_icp_stats& S = stats[p];
+            S.iters = hst[p].iters;
+            S.degenerate = hst[p].degenerate;
+            for (int k = 0; k < hst[p].iters && k < K; ++k) {
+                if (S.rmse) S.rmse[k] = hr[(size_t)p * K + k];
+                if (S.fallbacks) S.fallbacks[k] = hf[(size_t)p * K + k];
+            }
+        }
+    }
+    if (internal) return fail(VICP_ERR_HIP, "internal: unresolved global search");
+    if (nonfinite) return fail(VICP_ERR_NONFINITE, "non-finite source coordinates");
+    if (degenerate) return fail(VICP_ERR_DEGENERATE, "a solve kept the previous pose (rank < 2)");
+    return VICP_OK;
+}
+
+int vicp_register(const vicp_grid* g, const float* px, const float* py, const float* pz, int64_t m,
+                  const vicp_icp_opts* o, double Rt_io[12], vicp_icp_stats* stats, hipStream_t s)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (g->B != 1) return fail(VICP_ERR_INVALID_ARG, "vicp_register needs a single-pair grid");
+    if (m < 0) return fail(VICP_ERR_INVALID_ARG, "m < 0");
+    return vicp_register_batched(g, px, py, pz, &m, o, Rt_io, stats, s);
+}
+
+static int p2p_common(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                      const double* xi, hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!m_per_pair || !xi) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    rc = ensure_source(g, m_per_pair, 1, s);
+    if (rc) return rc;
+    if (g->m_total > 0 && (!px || !py || !pz)) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    const bool cap = capturing(s);
+    launch_se3(xi, g->B, g->st, g->jl6, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
+    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
+    return VICP_OK;
+}
+
+int vicp_p2p_loss_fwd(const vicp_grid* gc, const float* px, const float* py, const float* pz,
+                      const int64_t* m_per_pair, const double* xi, double* loss, hipStream_t s)
+{
+    vicp_grid* g = const_cast<vicp_grid*>(gc);
+    if (!loss) return fail(VICP_ERR_INVALID_ARG, "null loss");
+    int rc = p2p_common(g, px, py, pz, m_per_pair, xi, s);
+    if (rc) return rc;
+    const bool cap = capturing(s);
+    {
+        ProfScope ps("loss_terms", s, cap);
+        launch_loss_terms(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+                          g->nn_idx, nullptr, nullptr, nullptr, nullptr, g->part, g->flags, s);
+    }
+    launch_loss_finish(g->d_pd, g->B, g->job_begin, g->part, g->jl6, nullptr, loss, nullptr, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("loss fwd: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_p2p_loss_bwd(const vicp_grid* gc, const float* px, const float* py, const float* pz,
+                      const int64_t* m_per_pair, const double* xi, const double* gloss, float* dpx, float* dpy,
+                      float* dpz, double* dxi, hipStream_t s)
+{
+    vicp_grid* g = const_cast<vicp_grid*>(gc);
+    if (!gloss || !dxi) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    int rc = p2p_common(g, px, py, pz, m_per_pair, xi, s);
+    if (rc) return rc;
+    if (g->m_total > 0 && (!dpx || !dpy || !dpz)) return fail(VICP_ERR_INVALID_ARG, "null dP");
+    const bool cap = capturing(s);
+    {
+        ProfScope ps("loss_terms", s, cap);
+        launch_loss_terms(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+                          g->nn_idx, gloss, dpx, dpy, dpz, g->part, g->flags, s);
+    }
+    launch_loss_finish(g->d_pd, g->B, g->job_begin, g->part, g->jl6, gloss, nullptr, dxi, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("loss bwd: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!out || pair < 0 || pair >= g->B) return fail(VICP_ERR_INVALID_ARG, "bad pair or output");
+    const PairHost& h = g->pairs[pair];
+    memset(out, 0, sizeof(*out));
+    for (int a = 0; a < 3; ++a) {
+        out->origin[a] = h.origin[a];
+        out->dims[a] = h.dims[a];
+    }
+    out->inv = h.inv;
+    out->voxel = h.voxel;
+    out->V = h.V;
+    out->n = h.n;
+    out->pad_rings = g->pad;
+    out->rings_applied = g->rings_applied;
+    out->static_bytes = 8 * h.V;
+    out->dynamic_bytes = 4 * (h.n + 2 * h.V);
+    out->vanicp_bytes = 65536 * h.V;
+    // beyond the paper's accounting: the extra offset entry, the segment-
+    // ordered float4 copy of the target, and the work tables
+    out->extra_bytes = 4 + 16 * h.n;
+    hipStream_t s = nullptr;
+    VICP_HIP(hipDeviceSynchronize());
+    unsigned long long* cnt = nullptr;
+    VICP_HIP(hipMalloc(&cnt, sizeof(unsigned long long) * 4));
+    VICP_HIP(hipMemset(cnt, 0, sizeof(unsigned long long) * 4));
+    hipLaunchKernelGGL(k_grid_stats, dim3(std::max<int64_t>(1, std::min<int64_t>((h.V + 255) / 256, 2048))), dim3(256),
+                       0, s, g->hist + h.v_base, g->off + h.v_base, g->vm, h.V, cnt);
+    unsigned long long hc[4] = {0, 0, 0, 0};
+    uint32_t herr = 0;
+    hipError_t e1 = hipMemcpy(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost);
+    hipError_t e2 = hipMemcpy(&herr, g->err, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    (void)hipFree(cnt);
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(VICP_ERR_HIP, "describe readback failed");
+    out->occupied = (int64_t)hc[0];
+    out->dilated = (int64_t)hc[1];
+    out->max_count = (uint32_t)hc[2];
+    if (herr) return fail(VICP_ERR_HIP, "internal: a target point fell outside its grid");
+    return VICP_OK;
+}
+
+int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t* off, uint32_t* vm, hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (pair < 0 || pair >= g->B) return fail(VICP_ERR_INVALID_ARG, "bad pair");
+    const PairHost& h = g->pairs[pair];
+    if (hist) VICP_HIP(hipMemcpyAsync(hist, g->hist + h.v_base, sizeof(uint32_t) * h.V, hipMemcpyDeviceToDevice, s));
+    if (off)
+        hipLaunchKernelGGL(k_export_off, dim3((unsigned)std::min<int64_t>((h.V + 256) / 256, 4096)), dim3(256), 0, s,
+                           g->off + h.v_base, h.V + 1, (uint32_t)h.vm_base, off);
+    if (vm)
+        VICP_HIP(hipMemcpyAsync(vm, g->vm + h.vm_base, sizeof(uint32_t) * (h.n + 2 * h.V), hipMemcpyDeviceToDevice, s));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("export: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_grid_free(vicp_grid* g)
+{
+    if (!g) return VICP_OK;
+    (void)hipDeviceSynchronize();
+    g->drop_graph();
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->release(g->ws_bufs, nullptr);
+    g->release(g->owned, nullptr);
+    (void)hipDeviceSynchronize();
+    delete g;
+    return VICP_OK;
+}
+
+// The search schedule (lanes per block of the local search, blocks of the
+// global search) never changes a result; this times the candidates on the
+// caller's data at the identity pose and keeps the fastest.
+int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                  hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = ensure_source(g, m_per_pair, 1, s);
+    if (rc) return rc;
+    if (g->m_total == 0) return VICP_OK;
+    std::vector<double> rt(12 * g->B, 0.0);
+    for (int p = 0; p < g->B; ++p) rt[12 * p] = rt[12 * p + 4] = rt[12 * p + 8] = 1.0;
+    upload(rt.data(), sizeof(double) * 12 * g->B, g->staging, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
+    hipEvent_t a, b;
+    VICP_HIP(hipEventCreate(&a));
+    VICP_HIP(hipEventCreate(&b));
+    auto time_cfg = [&](int bs, int fg) -> float {
+        g->nns_block = bs;
+        g->fb_grid = fg;
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+            (void)hipEventRecord(a, s);
+            queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true);
+            (void)hipEventRecord(b, s);
+            (void)hipEventSynchronize(b);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (rep > 0) best = std::min(best, ms);
+        }
+        return best;
+    };
+    int best_bs = 256, best_fg = 512;
+    float best = 1e30f;
+    for (int bs : kBlockSizes) {
+        const float t = time_cfg(bs, best_fg);
+        if (t < best) {
+            best = t;
+            best_bs = bs;
+        }
+    }
+    for (int fg : {256, 512, 1024, 2048}) {
+        const float t = time_cfg(best_bs, fg);
+        if (t < best) {
+            best = t;
+            best_fg = fg;
+        }
+    }
+    g->nns_block = best_bs;
+    g->fb_grid = best_fg;
+    g->drop_graph();
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_prof_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return VICP_OK;
+}
+
+int vicp_prof_read(const char* kernel, int64_t* launches, double* total_ms)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    prof_flush_locked();
+    if (!kernel) return fail(VICP_ERR_INVALID_ARG, "null kernel name");
+    auto it = g_prof.acc.find(kernel);
+    if (launches) *launches = it == g_prof.acc.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == g_prof.acc.end() ? 0.0 : it->second.second;
+    return VICP_OK;
+}
+
+int vicp_prof_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    prof_flush_locked();
+    g_prof.acc.clear();
+    return VICP_OK;
+}
+
+}  // extern "C"

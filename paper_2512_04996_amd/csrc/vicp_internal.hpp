@@ -1,0 +1,124 @@
+// vicp_internal.hpp -- device-side data layout and kernel launchers of libvicp.
+//
+// Layout in HBM (all pairs of a batch share each array, concatenated in pair
+// order; a single-pair grid is a batch of one):
+//   qx, qy, qz   caller's target points (float32 SoA)            n_total
+//   hist         per-voxel count (Alg. 1 VoxelHist)               V_total
+//   off          per-voxel segment offset, exclusive scan of
+//                count + 2 (Alg. 1 AddrOffset), one extra entry   V_total + 1
+//   vm           dilated voxel index (Alg. 2/3 VoxelMem):
+//                segment [0, count | Mask(root), indices...]      n_total + 2 V_total
+//   qs4          the target points in segment order as float4
+//                (x, y, z, index bits): one coalesced 16-byte
+//                load per candidate in the local search          n_total
+// Segment v of pair p starts at off[v_base + v] (a global word offset);
+// its points sit in qs4 from off[g] - 2 g (g = v_base + v), because every
+// voxel before g contributes exactly two header words to off[g].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vicp {
+
+constexpr uint32_t kMask = 0x80000000u;   // Mask(root) of Alg. 3
+constexpr uint32_t kNone = 0xFFFFFFFFu;   // no root (dilation state)
+constexpr int kMoments = 17;              // sum p (3), sum q (3), sum p q^T (9), sum d (1), count (1)
+constexpr int kGradTerms = 8;             // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
+
+// One pair: where its data lives and its grid (Sec. II.A Step 1).
+struct PairDev {
+    int64_t q_base;   // first target point (also first qs4 slot)
+    int64_t n;        // target points
+    int64_t v_base;   // first voxel in hist/off
+    int64_t V;        // voxels
+    int64_t p_base;   // first source point
+    int64_t m;        // source points
+    float ox, oy, oz, inv;  // origin and 1/voxel
+    float fDx, fDy, fDz;    // dims as float32, for the inside test
+    int32_t Dx, Dy, Dz;     // dims
+    int32_t pad;
+};
+
+// A block's work: the pair it serves and its first item within the pair.
+struct BlockJob {
+    int32_t pair;
+    int32_t start;
+};
+
+// Per-pair ICP state on the device.
+struct PairState {
+    double Rt[12];      // float64 pose, R row-major then t
+    float Rtf[12];      // the pose rounded to float32, used by the search
+    double prev_rmse;
+    int32_t done;       // early stop reached (or nothing to do)
+    int32_t iters;
+    int32_t degenerate;
+    int32_t status;     // latched device faults (bit 0: non-finite source)
+};
+
+// --------------------------------------------------------------------------
+// kernel launchers (one translation unit each; all asynchronous)
+// --------------------------------------------------------------------------
+
+// grid build
+void launch_box_init(uint32_t* box, int npairs, hipStream_t s);
+void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                 const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
+void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                  const BlockJob* jobs, int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank,
+                  uint32_t* err, hipStream_t s);
+int scan_tiles(int64_t total);
+void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm,
+                 unsigned long long* status, uint32_t* ticket, hipStream_t s);
+void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox,
+                  const uint32_t* rank, const uint32_t* off, uint32_t* tmp, hipStream_t s);
+void launch_rank_sort(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                      const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* hist,
+                      const uint32_t* off, const uint32_t* tmp, uint32_t* vm, float4* qs4,
+                      hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t s);
+
+// dilation
+void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
+                        const uint32_t* hist, const uint32_t* off, uint32_t* vm,
+                        const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
+
+// search and moments
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
+                      const float* px, const float* py, const float* pz, const PairState* st,
+                      const uint32_t* off, const uint32_t* vm, const float4* qs4,
+                      int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
+                      unsigned long long* fb_key, hipStream_t s);
+void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy,
+                     const float* qz, const float* px, const float* py, const float* pz,
+                     const PairState* st, const int32_t* fb_count, const uint32_t* fb_list,
+                     unsigned long long* fb_key, hipStream_t s);
+void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs,
+                        const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2,
+                        int32_t* flags, hipStream_t s);
+void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px,
+                    const float* py, const float* pz, const float* qx, const float* qy,
+                    const float* qz, const PairState* st, const unsigned long long* fb_key,
+                    int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags, hipStream_t s);
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
+                  PairState* st, int32_t* fb_count, double* rmse_hist, int32_t* fb_hist,
+                  int32_t* deg_hist, int k, int K, int early_stop, double eps, hipStream_t s);
+void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
+void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                         const float* pz, int32_t* flags, hipStream_t s);
+void launch_copy_fb(const int32_t* fb_count, int32_t* out, int npairs, hipStream_t s);
+
+// differentiable loss
+void launch_se3(const double* xi, int npairs, PairState* st, double* jl6, hipStream_t s);
+void launch_loss_terms(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px,
+                       const float* py, const float* pz, const float* qx, const float* qy,
+                       const float* qz, const PairState* st, const unsigned long long* fb_key,
+                       int32_t* nn_idx, const double* gloss, float* dpx, float* dpy, float* dpz,
+                       double* part, int32_t* flags, hipStream_t s);
+void launch_loss_finish(const PairDev* pd, int npairs, const int32_t* job_begin,
+                        const double* part, const double* jl6, const double* gloss,
+                        double* loss, double* dxi, hipStream_t s);
+
+}  // namespace vicp

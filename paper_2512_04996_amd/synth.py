@@ -136,6 +136,8 @@ _BUMPY_BOUND = math.sqrt(1.1 ** 2 + 0.5 ** 2) * math.sqrt(1.1 ** 2 + 0.4 ** 2)
 
 
 def _bumpy_points(rng, k: int, noise: float) -> np.ndarray:
+    if k == 0:
+        return np.zeros((0, 3))
     out = []
     have = 0
     while have < k:
@@ -193,6 +195,8 @@ def _room_points(rng, faces, k: int, noise: float) -> np.ndarray:
     hi2 = np.stack([f[3] for f in faces])
     o0 = np.where(ax == 0, 1, 0)
     o1 = np.where(ax == 2, 1, 2)
+    if k == 0:
+        return np.zeros((0, 3))
     out = []
     have = 0
     while have < k:

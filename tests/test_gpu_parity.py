@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact for counts, offsets, segment contents, dilation roots, NN indices
+and float32 distances (the same float32 expressions decide them on both
+sides); the final pose within 1e-5 rad in rotation and 1e-6 x extent in
+translation (the tolerance of the float64 solve after float32 correspondence
+search).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_04996_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():   # collected on CPU machines, skipped there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2512_04996_amd._lib import ERR_DEGENERATE, ERR_INVALID_ARG, ERR_NONFINITE, ERR_STATE, VicpError  # noqa: E402
+from paper_2512_04996_amd.api import build_grid, build_grid_batched  # noqa: E402
+
+ROT_TOL = 1e-5
+T_TOL = 1e-6
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rot_angle(R1, R2):
+    return float(np.arccos(np.clip((np.trace(np.asarray(R1).reshape(3, 3).T @ np.asarray(R2).reshape(3, 3)) - 1) / 2,
+                                   -1.0, 1.0)))
+
+
+def tiny(seed, n, m, voxel, L, scale=1.0):
+    q = synth.tiny_cloud(seed, n, dup=n // 20)
+    p = synth.tiny_cloud(seed + 1000, m, scale=scale)
+    return q, p, voxel, L
+
+
+GRID_CASES = {
+    "tiny_300": lambda: tiny(1, 300, 200, 0.2, 2),
+    "tiny_onevoxel": lambda: tiny(2, 257, 129, 10.0, 0, scale=0.3),
+    "tiny_dense": lambda: tiny(3, 5000, 700, 0.5, 3),
+    "sphere_2k": lambda: (lambda P: (P.q, P.p, P.voxel, P.rings))(synth.config("sphere_2k")),
+    "bumpy_40k": lambda: (lambda P: (P.q, P.p, P.voxel, P.rings))(synth.config("bumpy_40k")),
+    "room_226k": lambda: (lambda P: (P.q, P.p, P.voxel, P.rings))(synth.config("room_226k")),
+}
+
+
+def check_grid(g, og):
+    d = g.describe()
+    assert np.array_equal(d["dims"], og.dims) and d["V"] == og.V
+    assert np.array_equal(d["origin"], og.origin) and d["inv"] == og.inv
+    hist, off, vm = g.export()
+    assert np.array_equal(hist, og.hist), "hist"
+    assert np.array_equal(off, og.off), "off"
+    assert np.array_equal(vm, og.vm), "vm"
+    return d
+
+
+@pytest.mark.parametrize("case", list(GRID_CASES))
+def test_build_and_dilate_bit_exact(case):
+    q, p, voxel, L = GRID_CASES[case]()
+    g = build_grid(dev(q), voxel, L)
+    og = oracle.build_grid(q, voxel, L)
+    check_grid(g, og)                      # Alg. 1 + Alg. 2
+    g.dilate(L)
+    oracle.dilate(og, L)
+    d = check_grid(g, og)                  # Alg. 3
+    assert d["occupied"] == int((og.hist > 0).sum())
+    assert d["dilated"] == int(((og.vm[og.off[:-1] + 1] & np.uint32(0x80000000)) != 0).sum())
+    assert d["max_count"] == int(og.hist.max())
+    assert d["dynamic_bytes"] == 4 * (og.n + 2 * og.V) and d["static_bytes"] == 8 * og.V
+
+
+@pytest.mark.parametrize("rings", [0, 1, 3])
+def test_partial_dilation(rings):
+    q, p, voxel, L = tiny(4, 400, 10, 0.15, 3)
+    g = build_grid(dev(q), voxel, L).dilate(rings)
+    og = oracle.dilate(oracle.build_grid(q, voxel, L), rings)
+    check_grid(g, og)
+
+
+def random_pose(seed, deg, t):
+    rng = np.random.default_rng(seed)
+    R = synth.random_rotation(rng.standard_normal(3), math.radians(deg))
+    Rt = np.concatenate([R.reshape(9), rng.standard_normal(3) * t]).astype(np.float32)
+    return Rt
+
+
+@pytest.mark.parametrize("case", list(GRID_CASES))
+@pytest.mark.parametrize("pose", [0, 1])
+def test_nns_bit_exact(case, pose):
+    q, p, voxel, L = GRID_CASES[case]()
+    Rt = random_pose(pose, 0.0 if pose == 0 else 4.0, 0.0 if pose == 0 else 0.03)
+    g = build_grid(dev(q), voxel, L).dilate(L)
+    og = oracle.dilate(oracle.build_grid(q, voxel, L), L)
+    idx, d2, fb = g.nns(dev(p), Rt)
+    ridx, rd2, rF, _ = oracle.nns(og, q, p, Rt)
+    assert int(fb.cpu()[0]) == rF
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(d2.cpu().numpy().view(np.uint32), rd2.view(np.uint32))
+
+
+def test_nns_all_fallback_and_ties():
+    q = synth.tiny_cloud(5, 3000)
+    q = np.concatenate([q, q[:, :300]], axis=1)           # exact duplicates: the lower index must win
+    p = synth.tiny_cloud(6, 1000) + np.float32(4.0)        # every query outside the grid
+    g = build_grid(dev(q), 0.1, 1).dilate(1)
+    og = oracle.dilate(oracle.build_grid(q, 0.1, 1), 1)
+    Rt = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, -4, -4, -4.0], np.float32)   # brings half of them back inside
+    for pose in (np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32), Rt):
+        idx, d2, fb = g.nns(dev(p), pose)
+        ridx, rd2, rF, _ = oracle.nns(og, q, p, pose)
+        assert int(fb.cpu()[0]) == rF
+        assert np.array_equal(idx.cpu().numpy(), ridx)
+        assert np.array_equal(d2.cpu().numpy(), rd2)
+    assert (idx.cpu().numpy() < 3000).all()
+
+
+REG_CASES = ["sphere_2k", "bumpy_40k", "room_226k"]
+
+
+@pytest.mark.parametrize("case", REG_CASES)
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_register_matches_oracle(case, use_graph):
+    P = synth.config(case)
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    res = g.register(dev(P.p), P.iters, use_graph=use_graph)
+    ref = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters)
+    assert res.iters[0] == ref.iters
+    assert list(res.fallbacks[0]) == list(ref.fallbacks)
+    np.testing.assert_allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
+    assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+    assert np.linalg.norm(res.Rt[9:] - ref.Rt[9:]) <= T_TOL * P.extent
+
+
+def test_register_deterministic_and_graph_equals_eager():
+    P = synth.config("bumpy_40k")
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    a = g.register(p, 12, use_graph=False)
+    b = g.register(p, 12, use_graph=True)
+    torch.cuda.synchronize()
+    c = g.register(p, 12, use_graph=True)    # replay of the cached graph
+    for r in (b, c):
+        assert np.array_equal(a.Rt, r.Rt)
+        assert np.array_equal(a.rmse[0], r.rmse[0])
+        assert np.array_equal(a.fallbacks[0], r.fallbacks[0])
+
+
+def test_register_early_stop_matches_oracle():
+    P = synth.config("bumpy_40k")
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    res = g.register(dev(P.p), P.iters, rmse_eps=1e-4, early_stop=True)
+    ref = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters, rmse_eps=1e-4, early_stop=True)
+    assert res.iters[0] == ref.iters < P.iters
+    assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+
+
+def test_register_initial_pose_and_rigid_copy():
+    # source = target under a known motion; one voxel holds everything, so the
+    # search is exact and ICP must return the inverse motion
+    P = synth.bumpy_pair(seed=70, n=3000, m=3000, voxel=0.08, rings=2)
+    R = synth.random_rotation(np.array([1.0, 2.0, 2.0]), math.radians(3))
+    t = np.array([0.01, -0.015, 0.02])
+    p = (R @ P.q.astype(np.float64) + t[:, None]).astype(np.float32)
+    g = build_grid(dev(P.q), 10.0, 0).dilate(0)
+    res = g.register(dev(p), 15)
+    assert np.abs(res.Rt[:9].reshape(3, 3) - R.T).max() < 1e-8
+    assert np.abs(res.Rt[9:] + R.T @ t).max() < 1e-8
+    # warm start from the answer: a fixed point
+    res2 = g.register(dev(p), 2, Rt0=res.Rt)
+    assert np.abs(res2.Rt - res.Rt).max() < 1e-12
+
+
+def test_degenerate_keeps_pose():
+    q = np.zeros((3, 64), np.float32)
+    q[0] = np.linspace(-1, 1, 64)                          # collinear target and source
+    g = build_grid(dev(q), 0.1, 1).dilate(1)
+    res = g.register(dev(q.copy()), 3)
+    assert res.status == ERR_DEGENERATE and res.degenerate[0] == 3
+    assert np.array_equal(res.Rt, np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float64))
+    with pytest.raises(VicpError) as e:
+        g.register(dev(q.copy()), 1, raise_degenerate=True)
+    assert e.value.code == ERR_DEGENERATE
+
+
+def test_errors_and_empty_inputs():
+    q = synth.tiny_cloud(7, 100)
+    with pytest.raises(VicpError) as e:
+        build_grid(dev(q), 0.0, 1)
+    assert e.value.code == ERR_INVALID_ARG
+    bad = q.copy()
+    bad[2, 17] = np.inf
+    with pytest.raises(VicpError) as e:
+        build_grid(dev(bad), 0.1, 1)
+    assert e.value.code == ERR_NONFINITE
+    with pytest.raises(VicpError):
+        build_grid(dev(q), 1e-6, 1)                       # too many voxels
+    g = build_grid(dev(q), 0.2, 1)
+    with pytest.raises(VicpError) as e:
+        g.dilate(2)                                        # more rings than padding
+    assert e.value.code == ERR_INVALID_ARG
+    g.dilate(1)
+    with pytest.raises(VicpError) as e:
+        g.dilate(1)
+    assert e.value.code == ERR_STATE
+    empty = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
+    idx, d2, fb = g.nns(empty, np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32))
+    assert idx.numel() == 0 and int(fb.cpu()[0]) == 0
+    res = g.register(empty, 5)
+    assert res.iters[0] == 0
+    pn = synth.tiny_cloud(8, 50)
+    pn[0, 3] = np.nan
+    with pytest.raises(VicpError) as e:
+        g.register(dev(pn), 2)
+    assert e.value.code == ERR_NONFINITE
+
+
+def test_batched_equals_single_and_oracle():
+    pairs = [synth.bumpy_pair(seed=s, n=n, m=m, voxel=v, rings=2, iters=10)
+             for s, n, m, v in ((11, 3000, 2500, 0.06), (12, 9000, 9100, 0.04), (13, 500, 0, 0.1), (14, 1, 40, 0.2))]
+    pairs += [synth.room_pair(seed=15, n=20000, m=15000, voxel=0.1, rings=2, iters=10)]
+    qcat = np.concatenate([P.q for P in pairs], axis=1)
+    pcat = np.concatenate([P.p for P in pairs], axis=1)
+    ns = [P.n for P in pairs]
+    ms = [P.m for P in pairs]
+    gb = build_grid_batched(dev(qcat), ns, [P.voxel for P in pairs], 2).dilate(2)
+    rb = gb.register(dev(pcat), 10, m_per_pair=ms)
+    for b, P in enumerate(pairs):
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
+        hist, off, vm = gb.export(b)
+        assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm)
+        gs = build_grid(dev(P.q), P.voxel, 2).dilate(2)
+        rs = gs.register(dev(P.p), 10)
+        assert np.array_equal(rb.Rt[b], rs.Rt), b          # bit-identical to the single-pair run
+        assert rb.iters[b] == rs.iters[0]
+        if P.m:
+            ref = oracle.register(P.q, P.p, P.voxel, 2, 10)
+            assert list(rb.fallbacks[b]) == list(ref.fallbacks)
+            assert rot_angle(rb.Rt[b][:9], ref.Rt[:9]) <= ROT_TOL
+        else:
+            assert rb.iters[b] == 0
+
+
+def test_autotune_is_result_invariant():
+    P = synth.config("bumpy_40k")
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    Rt = random_pose(3, 5.0, 0.05)
+    i0, d0, f0 = (t.cpu().numpy() for t in g.nns(p, Rt))
+    r0 = g.register(p, 8)
+    g.autotune(p)
+    i1, d1, f1 = (t.cpu().numpy() for t in g.nns(p, Rt))
+    r1 = g.register(p, 8)
+    assert np.array_equal(i0, i1) and np.array_equal(d0, d1) and np.array_equal(f0, f1)
+    assert np.array_equal(r0.Rt, r1.Rt)
