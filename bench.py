@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Benchmark of the dilation-based ICP hot path on one MI355X.
+
+A step is one pass of the whole hot path over the indoor-scene workload
+(226,000 target / 200,000 source points, voxel 0.05 m, 3 dilation rings,
+30 ICP iterations): voxelise + count, offset scan, scatter + order, dilation,
+then 30 x (local/global search, moments, float64 solve).  Inputs are
+resident in HBM before the timed region.  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Extra figures on the same line: ICP iterations/s, the dilation-buffer bytes
+of every workload against the fixed 64 KiB-per-voxel allocation, the
+batched (64 pairs) and differentiable (16 x 40k forward + backward) forms,
+per-kernel times from HIP events, the roofline of the dominant kernel and the
+CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NNS queries/s + ICP iters/s at 226K pts; dilation buffer bytes; fwd+bwd pairs/s"
+HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "nns_local_room_226k_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2512_04996_amd", "csrc", "k_nns.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="room_226k")
+    ap.add_argument("--graph", type=int, default=0, help="replay the ICP iterations from a hipGraph")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
+    ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
+    return ap.parse_args()
+
+
+def nns_local_bytes(m, F, cand, dil):
+    """Algorithmic bytes of one local-search launch (each logical access once):
+    per query 12 (p) + 4 (off[v]) + 4 (count word); +8 (off[root] + count
+    word) when the voxel is dilated; 16 per candidate (float4 x, y, z, index);
+    8 out (index + distance) for a local search, or 16 (index marker, list
+    slot, 64-bit key) for a query sent to the global search."""
+    return m * 20 + (m - F) * 8 + F * 16 + 8 * dil + 16 * cand
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2512_04996_amd import _lib, api, synth
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+
+    P = synth.config(a.workload)
+    q = torch.from_numpy(P.q).to(dev)
+    p = torch.from_numpy(P.p).to(dev)
+    torch.cuda.synchronize()
+
+    def step():
+        g = api.build_grid(q, P.voxel, P.rings)
+        g.dilate(P.rings)
+        r = g.register(p, P.iters, use_graph=bool(a.graph))
+        g.free()
+        return r
+
+    log(f"[bench] workload {P.name}: n={P.n} m={P.m} voxel={P.voxel} rings={P.rings} iters={P.iters}")
+    for _ in range(a.warmup):
+        res = step()
+    log("[bench] warmup done")
+    prof = not a.no_prof
+    if prof:
+        api.prof_reset()
+        api.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if prof:
+        api.prof_enable(False)
+    log("[bench] timed region done")
+    ms = (t1 - t0) * 1e3 / a.steps
+    K = int(res.iters[0])
+    queries_per_s = K * P.m / (ms * 1e-3)
+    kernels = {}
+    if prof:
+        for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "nns_local", "fallback",
+                     "moments", "solve"):
+            n_launch, tot = api.prof_read(name)
+            if n_launch:
+                kernels[name] = {"launches_per_step": n_launch / a.steps, "avg_us": 1e3 * tot / n_launch,
+                                 "ms_per_step": tot / a.steps}
+
+    F = np.asarray(res.fallbacks[0], np.int64)
+    cand = np.asarray(res.candidates[0], np.int64)
+    dil = np.asarray(res.dilated_lookups[0], np.int64)
+    per_launch = [nns_local_bytes(P.m, int(F[k]), int(cand[k]), int(dil[k])) for k in range(K)]
+    bytes_per_launch = float(np.mean(per_launch))
+    roofline = None
+    if "nns_local" in kernels:
+        dur_s = kernels["nns_local"]["avg_us"] * 1e-6
+        achieved = bytes_per_launch / dur_s / 1e9
+        traffic = None
+        if os.path.exists(PROFILE_PMC):
+            pmc = json.load(open(PROFILE_PMC))
+            src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+            if pmc.get("kernel_source_sha256") == src_hash:
+                traffic = pmc.get("hbm_bytes_per_launch")
+        roofline = {"kernel": "k_nns_local", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                    "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3)}
+
+    desc = None
+    g = api.build_grid(q, P.voxel, P.rings)
+    g.dilate(P.rings)
+    desc = g.describe()
+    g.free()
+    dil_bytes = {"workload": P.name, "V": desc["V"], "occupied": desc["occupied"], "dilated": desc["dilated"],
+                 "dynamic_bytes": desc["dynamic_bytes"], "static_bytes": desc["static_bytes"],
+                 "vanicp_fixed_bytes": desc["vanicp_bytes"],
+                 "saving": round(1.0 - (desc["dynamic_bytes"] + desc["static_bytes"]) / desc["vanicp_bytes"], 6),
+                 "extra_device_bytes": desc["extra_bytes"]}
+
+    out = {
+        "metric": METRIC, "value": round(queries_per_s, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": P.name, "n_target": P.n, "n_source": P.m, "voxel": P.voxel, "rings": P.rings,
+                   "iters": P.iters, "step": "grid build + dilation + 30 ICP iterations",
+                   "icp_mode": "graph" if a.graph else "eager"},
+        "icp_iters_per_s": round(K / (ms * 1e-3), 2),
+        "roofline": roofline,
+        "kernels": kernels,
+        "dilation_buffer": dil_bytes,
+    }
+    log(f"[bench] {ms:.3f} ms/step, {queries_per_s:.3e} queries/s")
+
+    if not a.no_extra:
+        out["extra"] = extra_figures(api, synth, torch, dev, np)
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(P)
+
+    print(json.dumps(out), flush=True)
+
+
+def extra_figures(api, synth, torch, dev, np):
+    """Batched and differentiable forms and the buffer bytes of every workload."""
+    from paper_2512_04996_amd.autograd import p2p_loss
+    ex = {}
+    # dilation-buffer bytes of the other workloads
+    sizes = {}
+    for name in ("sphere_2k", "bumpy_40k"):
+        Pw = synth.config(name)
+        g = api.build_grid(torch.from_numpy(Pw.q).to(dev), Pw.voxel, Pw.rings)
+        g.dilate(Pw.rings)
+        d = g.describe()
+        g.free()
+        sizes[name] = {"V": d["V"], "dynamic_bytes": d["dynamic_bytes"], "static_bytes": d["static_bytes"],
+                       "vanicp_fixed_bytes": d["vanicp_bytes"],
+                       "saving": round(1 - (d["dynamic_bytes"] + d["static_bytes"]) / d["vanicp_bytes"], 6)}
+    # batched: 64 uneven pairs in one launch sequence, against a loop of single-pair runs
+    log("[bench] batched workload")
+    pairs = synth.config("batched_64")
+    qc = torch.from_numpy(np.concatenate([x.q for x in pairs], 1)).to(dev)
+    pc = torch.from_numpy(np.concatenate([x.p for x in pairs], 1)).to(dev)
+    ns = [x.n for x in pairs]
+    ms_ = [x.m for x in pairs]
+    vox = [x.voxel for x in pairs]
+    iters = pairs[0].iters
+
+    def batched():
+        g = api.build_grid_batched(qc, ns, vox, 3)
+        g.dilate(3)
+        r = g.register(pc, iters, m_per_pair=ms_, use_graph=True)
+        V = sum(g.describe(b)["V"] for b in range(len(pairs))) if not hasattr(batched, "V") else batched.V
+        batched.V = V
+        g.free()
+        return r
+
+    qs = [torch.from_numpy(x.q).to(dev) for x in pairs]
+    ps = [torch.from_numpy(x.p).to(dev) for x in pairs]
+
+    def looped():
+        out = []
+        for b, x in enumerate(pairs):
+            g = api.build_grid(qs[b], x.voxel, 3)
+            g.dilate(3)
+            out.append(g.register(ps[b], iters, use_graph=False))
+            g.free()
+        return out
+
+    rb = batched()
+    looped()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        rb = batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / 3
+    t0 = time.perf_counter()
+    rl = looped()
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    same = all(np.array_equal(rb.Rt[b], rl[b].Rt) for b in range(len(pairs)))
+    ex["batched_64"] = {"pairs": len(pairs), "points": int(sum(ns)), "V_total": int(batched.V),
+                        "ms": round(tb * 1e3, 3), "pairs_per_s": round(len(pairs) / tb, 2),
+                        "pair_iters_per_s": round(len(pairs) * iters / tb, 1),
+                        "looped_single_ms": round(tl * 1e3, 3), "speedup_vs_looped": round(tl / tb, 3),
+                        "bit_identical_to_looped": bool(same),
+                        "vanicp_fixed_bytes": int(65536 * batched.V)}
+    # differentiable: 16 x 40k forward + backward
+    log("[bench] differentiable workload")
+    dpairs, xi = synth.config("diff_16x40k")
+    B = len(dpairs)
+    qd = torch.from_numpy(np.concatenate([x.q for x in dpairs], 1)).to(dev)
+    P3 = torch.from_numpy(np.stack([x.p.T for x in dpairs])).to(dev)       # (16, 40000, 3)
+    g = api.build_grid_batched(qd, [x.n for x in dpairs], [x.voxel for x in dpairs], 2)
+    g.dilate(2)
+    xit = torch.from_numpy(xi).to(dev)
+
+    def fwd_bwd():
+        Pg = P3.detach().requires_grad_(True)
+        xg = xit.detach().requires_grad_(True)
+        L = p2p_loss(g, Pg, xg).sum()
+        L.backward()
+        return Pg.grad, xg.grad
+
+    for _ in range(3):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrep = 20
+    for _ in range(nrep):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    td = (time.perf_counter() - t0) / nrep
+    g.free()
+    ex["diff_16x40k"] = {"pairs": B, "points_per_pair": dpairs[0].m, "ms_fwd_bwd": round(td * 1e3, 3),
+                         "fwd_bwd_pairs_per_s": round(B / td, 1)}
+    ex["dilation_buffer_other"] = sizes
+    return ex
+
+
+def cpu_baseline(P):
+    """The CPU oracle as it stands, single-threaded, on the same workload:
+    whole registrations (grid, dilation, 30 iterations) repeated until about
+    10 s of CPU time have been spent."""
+    import oracle
+    log("[bench] cpu baseline (oracle)")
+    oracle.lib()
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or reps >= 8:
+            break
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(reps * r.iters * P.m / el, 1), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full registrations of {P.name} (grid + dilation + {P.iters} iterations), "
+                      f"{el:.1f} s, single thread",
+            "icp_iters_per_s": round(reps * r.iters / el, 3), "cpu": cpu}
+
+
+if __name__ == "__main__":
+    main()

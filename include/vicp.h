@@ -101,10 +101,12 @@ typedef struct vicp_icp_opts {
 /* Per-pair registration statistics.  The arrays are caller-owned HOST arrays
  * of max_iter entries and may be NULL. */
 typedef struct vicp_icp_stats {
-    int32_t iters;          /* iterations run */
-    int32_t degenerate;     /* iterations whose solve kept the previous pose */
-    double* rmse;           /* RMSE_k = sqrt(mean nn_d2) of iteration k */
-    int64_t* fallbacks;     /* queries that took the global search in iteration k */
+    int32_t iters;            /* iterations run */
+    int32_t degenerate;       /* iterations whose solve kept the previous pose */
+    double* rmse;             /* RMSE_k = sqrt(mean nn_d2) of iteration k */
+    int64_t* fallbacks;       /* queries that took the global search in iteration k */
+    int64_t* candidates;      /* target points scanned by local searches in iteration k */
+    int64_t* dilated_lookups; /* local searches redirected through Mask(root) in iteration k */
 } vicp_icp_stats;
 
 /* ---- build (Alg. 1 and Alg. 2) --------------------------------------------

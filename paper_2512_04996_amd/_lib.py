@@ -45,7 +45,8 @@ class IcpOpts(C.Structure):
 
 class IcpStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("degenerate", C.c_int32), ("rmse", C.POINTER(C.c_double)),
-                ("fallbacks", C.POINTER(C.c_int64))]
+                ("fallbacks", C.POINTER(C.c_int64)), ("candidates", C.POINTER(C.c_int64)),
+                ("dilated_lookups", C.POINTER(C.c_int64))]
 
 
 SYMBOLS = {

@@ -53,6 +53,8 @@ class IcpResult:
     degenerate: np.ndarray    # (B,)
     rmse: list                # per pair, float64[iters]
     fallbacks: list           # per pair, int64[iters]
+    candidates: list          # per pair, int64[iters]: target points scanned by local searches
+    dilated_lookups: list     # per pair, int64[iters]: local searches sent to a root voxel
     status: int
 
 
@@ -132,10 +134,14 @@ class Grid:
         K = int(max_iter)
         rm = np.zeros((B, max(K, 1)), np.float64)
         fbk = np.zeros((B, max(K, 1)), np.int64)
+        cnd = np.zeros((B, max(K, 1)), np.int64)
+        dil = np.zeros((B, max(K, 1)), np.int64)
         stats = (IcpStats * B)()
         for b in range(B):
             stats[b].rmse = rm[b].ctypes.data_as(C.POINTER(C.c_double))
             stats[b].fallbacks = fbk[b].ctypes.data_as(C.POINTER(C.c_int64))
+            stats[b].candidates = cnd[b].ctypes.data_as(C.POINTER(C.c_int64))
+            stats[b].dilated_lookups = dil[b].ctypes.data_as(C.POINTER(C.c_int64))
         opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)))
         px, py, pz = _ptrs(p)
         rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
@@ -146,7 +152,9 @@ class Grid:
         deg = np.array([stats[b].degenerate for b in range(B)])
         return IcpResult(rt.reshape(B, 12) if B > 1 else rt, iters, deg,
                          [rm[b, :iters[b]].copy() for b in range(B)],
-                         [fbk[b, :iters[b]].copy() for b in range(B)], rc)
+                         [fbk[b, :iters[b]].copy() for b in range(B)],
+                         [cnd[b, :iters[b]].copy() for b in range(B)],
+                         [dil[b, :iters[b]].copy() for b in range(B)], rc)
 
     # -- helpers
     def describe(self, pair: int = 0) -> dict:

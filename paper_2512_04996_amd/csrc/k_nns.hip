@@ -44,58 +44,73 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   const uint32_t* __restrict__ off, const uint32_t* __restrict__ vm,
                                                   const float4* __restrict__ qs4, int32_t* __restrict__ nn_idx,
                                                   float* __restrict__ nn_d2, int32_t* __restrict__ fb_count,
-                                                  uint32_t* __restrict__ fb_list, unsigned long long* __restrict__ fb_key)
+                                                  uint32_t* __restrict__ fb_list, unsigned long long* __restrict__ fb_key,
+                                                  unsigned long long* __restrict__ ctr)
 {
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
-    if (S.done) return;
+    if (S.done) return;   // uniform over the block
     const int64_t i = (int64_t)job.start + threadIdx.x;
-    if (i >= P.m) return;
+    const bool active = i < P.m;
     const int64_t gp = P.p_base + i;
-    float sx, sy, sz;
-    transform(S.Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
-    const float fx = (sx - P.ox) * P.inv;
-    const float fy = (sy - P.oy) * P.inv;
-    const float fz = (sz - P.oz) * P.inv;
-    const bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     uint32_t c = 0;
     int64_t cs = 0;
-    if (in) {
-        const uint32_t v = (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
-        const int64_t g = P.v_base + v;
-        const uint32_t og = off[g];
-        const uint32_t h = vm[(int64_t)og + 1];
-        if (h & kMask) {
-            const int64_t gr = P.v_base + (h & ~kMask);
-            const uint32_t ogr = off[gr];
-            c = vm[(int64_t)ogr + 1];
-            cs = (int64_t)ogr - 2 * gr;
+    bool dil = false;
+    if (active) {
+        transform(S.Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
+        const float fx = (sx - P.ox) * P.inv;
+        const float fy = (sy - P.oy) * P.inv;
+        const float fz = (sz - P.oz) * P.inv;
+        const bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
+        if (in) {
+            const uint32_t v =
+                (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
+            const int64_t g = P.v_base + v;
+            const uint32_t og = off[g];
+            const uint32_t h = vm[(int64_t)og + 1];
+            if (h & kMask) {
+                // dilated: follow Mask(root) to the root voxel's segment
+                const int64_t gr = P.v_base + (h & ~kMask);
+                const uint32_t ogr = off[gr];
+                c = vm[(int64_t)ogr + 1];
+                cs = (int64_t)ogr - 2 * gr;
+                dil = true;
+            } else {
+                c = h;
+                cs = (int64_t)og - 2 * g;
+            }
+        }
+        if (c == 0) {
+            const int32_t pos = atomicAdd(&fb_count[job.pair], 1);
+            fb_list[P.p_base + pos] = (uint32_t)i;
+            fb_key[P.p_base + pos] = ~0ull;
+            nn_idx[gp] = -1 - pos;
         } else {
-            c = h;
-            cs = (int64_t)og - 2 * g;
+            float bd = INFINITY;
+            uint32_t bj = 0;
+            const float4* seg = qs4 + cs;
+            for (uint32_t t = 0; t < c; ++t) {
+                const float4 q = seg[t];
+                const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
+                if (d < bd) {
+                    bd = d;
+                    bj = __float_as_uint(q.w);
+                }
+            }
+            nn_idx[gp] = (int32_t)bj;
+            nn_d2[gp] = bd;
         }
     }
-    if (c == 0) {
-        const int32_t pos = atomicAdd(&fb_count[job.pair], 1);
-        fb_list[P.p_base + pos] = (uint32_t)i;
-        fb_key[P.p_base + pos] = ~0ull;
-        nn_idx[gp] = -1 - pos;
-        return;
+    // telemetry: candidates scanned and dilated lookups, one atomic per wave
+    unsigned long long cw = c;
+    for (int d = kWave / 2; d > 0; d >>= 1) cw += __shfl_xor(cw, d, kWave);
+    const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil));
+    if ((threadIdx.x & (kWave - 1)) == 0 && (cw | dw)) {
+        atomicAdd(&ctr[2 * job.pair], cw);
+        atomicAdd(&ctr[2 * job.pair + 1], dw);
     }
-    float bd = INFINITY;
-    uint32_t bj = 0;
-    const float4* seg = qs4 + cs;
-    for (uint32_t t = 0; t < c; ++t) {
-        const float4 q = seg[t];
-        const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-        if (d < bd) {
-            bd = d;
-            bj = __float_as_uint(q.w);
-        }
-    }
-    nn_idx[gp] = (int32_t)bj;
-    nn_d2[gp] = bd;
 }
 
 // Global search.  Work item = (pair, chunk of kFbQ listed queries, tile of
@@ -277,12 +292,12 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, const float* px, const float* py,
                       const float* pz, const PairState* st, const uint32_t* off, const uint32_t* vm, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
-                      unsigned long long* fb_key, hipStream_t s)
+                      unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s)
 {
     if (njobs <= 0) return;
 #define VICP_NNS(BS)                                                                                                  \
     hipLaunchKernelGGL(k_nns_local<BS>, dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, st, off, vm, qs4, nn_idx, \
-                       nn_d2, fb_count, fb_list, fb_key)
+                       nn_d2, fb_count, fb_list, fb_key, ctr)
     switch (block) {
     case 64: VICP_NNS(64); break;
     case 128: VICP_NNS(128); break;

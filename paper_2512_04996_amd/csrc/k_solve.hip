@@ -116,9 +116,11 @@ __device__ bool kabsch(const double* mom, double Rt[12])
 
 __global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin,
                                                     const double* __restrict__ part, PairState* __restrict__ st,
-                                                    int32_t* __restrict__ fb_count, double* __restrict__ rmse_hist,
-                                                    int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist, int k,
-                                                    int K, int early_stop, double eps)
+                                                    int32_t* __restrict__ fb_count, unsigned long long* __restrict__ ctr,
+                                                    double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
+                                                    int32_t* __restrict__ deg_hist,
+                                                    unsigned long long* __restrict__ ctr_hist, int k, int K,
+                                                    int early_stop, double eps)
 {
     __shared__ double red[kMoments][kThreads];
     __shared__ double tot[kMoments];
@@ -163,6 +165,10 @@ __global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ 
     fb_hist[(int64_t)pair * K + k] = fb_count[pair];
     deg_hist[(int64_t)pair * K + k] = ok ? 0 : 1;
     fb_count[pair] = 0;
+    ctr_hist[2 * ((int64_t)pair * K + k)] = ctr[2 * pair];
+    ctr_hist[2 * ((int64_t)pair * K + k) + 1] = ctr[2 * pair + 1];
+    ctr[2 * pair] = 0;
+    ctr[2 * pair + 1] = 0;
     S.iters = k + 1;
     if (early_stop && k >= 1 && fabs(rmse - S.prev_rmse) < eps) S.done = 1;
     S.prev_rmse = rmse;
@@ -190,12 +196,12 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 }  // namespace
 
 void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st,
-                  int32_t* fb_count, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist, int k, int K,
-                  int early_stop, double eps, hipStream_t s)
+                  int32_t* fb_count, unsigned long long* ctr, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist,
+                  unsigned long long* ctr_hist, int k, int K, int early_stop, double eps, hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, rmse_hist,
-                       fb_hist, deg_hist, k, K, early_stop, eps);
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, ctr, rmse_hist,
+                       fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
 }
 
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)

@@ -264,6 +264,8 @@ struct vicp_grid {
     double* rmse_hist = nullptr;
     int32_t* fb_hist = nullptr;
     int32_t* deg_hist = nullptr;
+    unsigned long long* ctr = nullptr;        // per pair: candidates scanned, dilated lookups
+    unsigned long long* ctr_hist = nullptr;   // the same per iteration
     std::vector<Buf> ws_bufs;
 
     // captured registration
@@ -363,11 +365,13 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L);
     g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
     g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * B, s, L);
+    g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L);
     for (int k = 0; k < 4; ++k) {
         g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L);
         g->njobs_p[k] = (int)jobs[k].size();
     }
-    if (L.size() != 18) {
+    if (L.size() != 20) {
         g->release(g->ws_bufs, s);
         g->m.clear();
         g->K_cap = 0;
@@ -400,7 +404,7 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
     {
         ProfScope ps("nns_local", s, cap);
         launch_nns_local(g->d_pd, g->jobs_p[slot], g->njobs_p[slot], g->nns_block, px, py, pz, g->st, g->off, g->vm,
-                         g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, s);
+                         g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr, s);
     }
     {
         ProfScope ps("fallback", s, cap);
@@ -420,8 +424,8 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
     }
     {
         ProfScope ps("solve", s, cap);
-        launch_solve(g->d_pd, g->B, g->job_begin, g->part, g->st, g->fb_count, g->rmse_hist, g->fb_hist, g->deg_hist,
-                     k, K, early, eps, s);
+        launch_solve(g->d_pd, g->B, g->job_begin, g->part, g->st, g->fb_count, g->ctr, g->rmse_hist, g->fb_hist,
+                     g->deg_hist, g->ctr_hist, k, K, early, eps, s);
     }
 }
 
@@ -707,6 +711,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
     queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap);
@@ -761,6 +766,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     launch_fill_u32((uint32_t*)g->flags, 0u, B, s);
     launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
+    launch_fill_u64(g->ctr, 0ull, 2 * B, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid};
@@ -791,11 +797,13 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     std::vector<PairState> hst(B);
     std::vector<double> hr((size_t)B * g->K_cap);
     std::vector<int32_t> hf((size_t)B * g->K_cap), hd((size_t)B * g->K_cap), hflags(B);
+    std::vector<unsigned long long> hc(2 * (size_t)B * g->K_cap);
     VICP_HIP(hipMemcpyAsync(hst.data(), g->st, sizeof(PairState) * B, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hr.data(), g->rmse_hist, sizeof(double) * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hf.data(), g->fb_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hd.data(), g->deg_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hflags.data(), g->flags, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(hc.data(), g->ctr_hist, sizeof(unsigned long long) * 2 * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
     bool nonfinite = false, degenerate = false, internal = false;
     for (int p = 0; p < B; ++p) {
@@ -810,6 +818,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
             for (int k = 0; k < hst[p].iters && k < K; ++k) {
                 if (S.rmse) S.rmse[k] = hr[(size_t)p * K + k];
                 if (S.fallbacks) S.fallbacks[k] = hf[(size_t)p * K + k];
+                if (S.candidates) S.candidates[k] = (int64_t)hc[2 * ((size_t)p * K + k)];
+                if (S.dilated_lookups) S.dilated_lookups[k] = (int64_t)hc[2 * ((size_t)p * K + k) + 1];
             }
         }
     }
@@ -840,6 +850,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     const bool cap = capturing(s);
     launch_se3(xi, g->B, g->st, g->jl6, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
     return VICP_OK;

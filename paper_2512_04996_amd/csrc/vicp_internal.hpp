@@ -90,7 +90,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const PairState* st,
                       const uint32_t* off, const uint32_t* vm, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
-                      unsigned long long* fb_key, hipStream_t s);
+                      unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s);
 void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy,
                      const float* qz, const float* px, const float* py, const float* pz,
                      const PairState* st, const int32_t* fb_count, const uint32_t* fb_list,
@@ -103,8 +103,9 @@ void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const fl
                     const float* qz, const PairState* st, const unsigned long long* fb_key,
                     int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags, hipStream_t s);
 void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
-                  PairState* st, int32_t* fb_count, double* rmse_hist, int32_t* fb_hist,
-                  int32_t* deg_hist, int k, int K, int early_stop, double eps, hipStream_t s);
+                  PairState* st, int32_t* fb_count, unsigned long long* ctr, double* rmse_hist,
+                  int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K,
+                  int early_stop, double eps, hipStream_t s);
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                          const float* pz, int32_t* flags, hipStream_t s);
