@@ -129,6 +129,16 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz,
                             const vicp_allocator* alloc, hipStream_t stream,
                             vicp_grid** out);
 
+/* Refills an existing grid from a new target with the same per-pair point
+ * counts (e.g. the next frame of a stream): the bounding box, grid
+ * specification, counts, offsets and segments are recomputed exactly as by
+ * vicp_build_grid, while allocations, work tables and captured graphs are
+ * reused when the voxel counts are unchanged.  The grid is left undilated:
+ * call vicp_dilate again.  Synchronises the stream once (bounding box).
+ * Errors as vicp_build_grid; STATE for a grid that was never built. */
+int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz,
+                      hipStream_t stream);
+
 /* ---- dilation (Alg. 3) ----------------------------------------------------
  * Applies `rings` synchronous dilation rings (0 <= rings <= pad_rings) to every
  * pair: an empty voxel within L1 distance `rings` of an occupied voxel gets
@@ -200,11 +210,20 @@ int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t*
 /* Releases the grid and everything it owns (after its queued work). */
 int vicp_grid_free(vicp_grid* g);
 
-/* Autotuning: times the result-invariant launch schedules of the NNS and
- * dilation kernels on this grid and source and keeps the fastest in the grid.
- * Results never depend on the schedule.  Synchronises the stream. */
+/* Autotuning: times the result-invariant schedules of the search (see
+ * vicp_get_schedule) on this grid and source at the identity pose and keeps the
+ * fastest in the grid.  Results never depend on the schedule.  Synchronises the
+ * stream. */
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz,
                   const int64_t* m_per_pair, hipStream_t stream);
+
+/* The current search schedule of a grid: lanes per block of the local search
+ * (64, 128, 256 or 512), whether the source is bucketed by target voxel before
+ * searching (0/1), and the number of blocks of the global search.  Setting it
+ * never changes a result.  INVALID_ARG for an unsupported value. */
+int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* sort_source,
+                      int32_t* fallback_grid);
+int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t sort_source, int32_t fallback_grid);
 
 /* Per-kernel timing with HIP events on the launch stream (0 = off).  While on,
  * every launch of a named kernel is bracketed by events; vicp_prof_read gives

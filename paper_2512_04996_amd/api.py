@@ -87,6 +87,27 @@ class Grid:
             raise VicpError(_lib.ERR_STATE, "grid", "freed")
         return self._h
 
+    def rebuild(self, q: torch.Tensor):
+        """Refill the grid from a new target with the same per-pair point counts."""
+        q = _soa(q, "q")
+        if q.shape[1] != sum(self.n_per_pair):
+            raise ValueError("rebuild needs the same number of target points")
+        qx, qy, qz = _ptrs(q)
+        check(lib().vicp_grid_rebuild(self.handle, qx, qy, qz, _stream()), "vicp_grid_rebuild")
+        self.q = q
+        return self
+
+    @property
+    def schedule(self) -> dict:
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(b), C.byref(c)), "vicp_get_schedule")
+        return {"nns_block": a.value, "sort_source": bool(b.value), "fallback_grid": c.value}
+
+    def set_schedule(self, nns_block: int = 256, sort_source: bool = True, fallback_grid: int = 256):
+        check(lib().vicp_set_schedule(self.handle, int(nns_block), int(bool(sort_source)), int(fallback_grid)),
+              "vicp_set_schedule")
+        return self
+
     # -- Alg. 3
     def dilate(self, rings: int):
         check(lib().vicp_dilate(self.handle, int(rings), _stream()), "vicp_dilate")

@@ -160,8 +160,10 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
 
 // --------------------------------------------------------------------------
 // offsets: off[g] = sum_{u<g} (hist[u] + 2), off[total] = n + 2V, and the
-// segment headers vm[off[g]] = 0, vm[off[g] + 1] = hist[g].  Single pass,
-// decoupled look-back (tile ids from a ticket so predecessors are resident).
+// segment headers vm[off[g]] = 0, vm[off[g] + 1] = hist[g] (kSeg), or a
+// plain exclusive scan of hist (!kSeg, for bucketing source points).  Single
+// pass, decoupled look-back (tile ids from a ticket so predecessors are
+// resident when a tile waits on them).
 // --------------------------------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
@@ -178,6 +180,7 @@ __device__ __forceinline__ void st_status(unsigned long long* p, unsigned long l
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <bool kSeg>
 __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ hist, int64_t total,
                                                    uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
                                                    unsigned long long* status, uint32_t* ticket)
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t g = base + k;
         h[k] = (g < total) ? hist[g] : 0u;
-        sum += (g < total) ? h[k] + 2u : 0u;
+        sum += (g < total) ? h[k] + (kSeg ? 2u : 0u) : 0u;
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t incl = sum;
@@ -253,9 +256,11 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
         const int64_t g = base + k;
         if (g < total) {
             off[g] = run;
-            vm[run] = 0u;
-            vm[run + 1] = h[k];
-            run += h[k] + 2u;
+            if (kSeg) {
+                vm[run] = 0u;
+                vm[run + 1] = h[k];
+            }
+            run += h[k] + (kSeg ? 2u : 0u);
             if (g == total - 1) off[total] = run;
         }
     }
@@ -348,7 +353,10 @@ void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* v
 {
     const int tiles = scan_tiles(total);
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
+    if (vm)
+        hipLaunchKernelGGL(k_scan<true>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
+    else
+        hipLaunchKernelGGL(k_scan<false>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
 }
 
 void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* rank,

@@ -1,12 +1,20 @@
-// k_nns.hip -- correspondence search (Alg. 4) and the moments of Eq. 1.
+// k_nns.hip -- correspondence search (Alg. 4).
 //
 // Local search: one lane per source point.  The transformed point's voxel is
 // found by the same float32 quantisation as the targets; its count word is
 // read through the offsets; a Mask(root) word redirects to the root voxel's
 // segment (indirect addressing, no replicated points).  Candidates are read
 // as float4 (x, y, z, index) from the segment-ordered copy of the target, one
-// coalesced 16-byte load each; segments are in ascending index order, so a
-// strict "<" keeps the lowest index among equal distances.
+// 16-byte load each, four in flight; segments are in ascending index order,
+// so a strict "<" keeps the lowest index among equal distances.
+//
+// Query order: lanes of a wave that look up different voxels diverge (the
+// wave runs the longest segment) and gather from unrelated cache lines.  The
+// search can therefore run over a copy of the source bucketed by target
+// voxel at the current pose (a counting sort: LDS-hashed bucket counts, a
+// plain scan, a placement pass), so neighbouring lanes share segments.
+// Results are written back by original index, so the order never changes a
+// result.
 //
 // Global search (empty undilated voxel or outside the grid): the query is
 // appended to a per-pair list and an exact brute force over all targets
@@ -37,36 +45,66 @@ __device__ __forceinline__ float dist2(float sx, float sy, float sz, float qx, f
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
-template <int BS>
+// Voxel of a transformed point, or false when it is outside the grid.
+__device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, float sz, uint32_t& v)
+{
+    const float fx = (sx - P.ox) * P.inv;
+    const float fy = (sy - P.oy) * P.inv;
+    const float fz = (sz - P.oz) * P.inv;
+    const bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
+    if (in) v = (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
+    return in;
+}
+
+__device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj)
+{
+    const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
+    if (d < bd) {
+        bd = d;
+        bj = __float_as_uint(q.w);
+    }
+}
+
+template <int BS, bool kSorted>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
-                                                  const float* __restrict__ pz, const PairState* __restrict__ st,
-                                                  const uint32_t* __restrict__ off, const uint32_t* __restrict__ vm,
-                                                  const float4* __restrict__ qs4, int32_t* __restrict__ nn_idx,
-                                                  float* __restrict__ nn_d2, int32_t* __restrict__ fb_count,
-                                                  uint32_t* __restrict__ fb_list, unsigned long long* __restrict__ fb_key,
+                                                  const float* __restrict__ pz, const float4* __restrict__ ps4,
+                                                  const PairState* __restrict__ st, const uint32_t* __restrict__ off,
+                                                  const uint32_t* __restrict__ vm, const float4* __restrict__ qs4,
+                                                  int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
+                                                  int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
+                                                  unsigned long long* __restrict__ fb_key,
                                                   unsigned long long* __restrict__ ctr)
 {
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
     if (S.done) return;   // uniform over the block
-    const int64_t i = (int64_t)job.start + threadIdx.x;
-    const bool active = i < P.m;
-    const int64_t gp = P.p_base + i;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    const int64_t t = (int64_t)job.start + threadIdx.x;
+    const bool active = t < P.m;
     uint32_t c = 0;
-    int64_t cs = 0;
     bool dil = false;
     if (active) {
-        transform(S.Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
-        const float fx = (sx - P.ox) * P.inv;
-        const float fy = (sy - P.oy) * P.inv;
-        const float fz = (sz - P.oz) * P.inv;
-        const bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
-        if (in) {
-            const uint32_t v =
-                (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
+        float x, y, z;
+        uint32_t i;
+        if (kSorted) {
+            const float4 pp = ps4[P.p_base + t];
+            x = pp.x;
+            y = pp.y;
+            z = pp.z;
+            i = __float_as_uint(pp.w);
+        } else {
+            x = px[P.p_base + t];
+            y = py[P.p_base + t];
+            z = pz[P.p_base + t];
+            i = (uint32_t)t;
+        }
+        const int64_t gp = P.p_base + i;
+        float sx, sy, sz;
+        transform(S.Rtf, x, y, z, sx, sy, sz);
+        uint32_t v;
+        int64_t cs = 0;
+        if (voxel_of(P, sx, sy, sz, v)) {
             const int64_t g = P.v_base + v;
             const uint32_t og = off[g];
             const uint32_t h = vm[(int64_t)og + 1];
@@ -84,21 +122,22 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         }
         if (c == 0) {
             const int32_t pos = atomicAdd(&fb_count[job.pair], 1);
-            fb_list[P.p_base + pos] = (uint32_t)i;
+            fb_list[P.p_base + pos] = i;
             fb_key[P.p_base + pos] = ~0ull;
             nn_idx[gp] = -1 - pos;
         } else {
             float bd = INFINITY;
             uint32_t bj = 0;
             const float4* seg = qs4 + cs;
-            for (uint32_t t = 0; t < c; ++t) {
-                const float4 q = seg[t];
-                const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-                if (d < bd) {
-                    bd = d;
-                    bj = __float_as_uint(q.w);
-                }
+            uint32_t k = 0;
+            for (; k + 4 <= c; k += 4) {
+                const float4 a = seg[k], b = seg[k + 1], e = seg[k + 2], f = seg[k + 3];
+                consider(a, sx, sy, sz, bd, bj);
+                consider(b, sx, sy, sz, bd, bj);
+                consider(e, sx, sy, sz, bd, bj);
+                consider(f, sx, sy, sz, bd, bj);
             }
+            for (; k < c; ++k) consider(seg[k], sx, sy, sz, bd, bj);
             nn_idx[gp] = (int32_t)bj;
             nn_d2[gp] = bd;
         }
@@ -111,6 +150,76 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         atomicAdd(&ctr[2 * job.pair], cw);
         atomicAdd(&ctr[2 * job.pair + 1], dw);
     }
+}
+
+// --------------------------------------------------------------------------
+// source bucketing by target voxel at the current pose (outside -> bucket V)
+// --------------------------------------------------------------------------
+constexpr int kBThreads = 256;
+constexpr int kBSlots = 2 * kBThreads;
+
+__global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restrict__ pd,
+                                                          const BlockJob* __restrict__ jobs,
+                                                          const float* __restrict__ px, const float* __restrict__ py,
+                                                          const float* __restrict__ pz,
+                                                          const PairState* __restrict__ st, uint32_t* __restrict__ sh,
+                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank)
+{
+    __shared__ uint32_t key_[kBSlots];
+    __shared__ uint32_t cnt_[kBSlots];
+    __shared__ uint32_t base_[kBSlots];
+    for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
+        key_[s] = kNone;
+        cnt_[s] = 0;
+    }
+    __syncthreads();
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    const bool valid = i < P.m;
+    uint32_t key = 0, slot = 0, lr = 0;
+    if (valid) {
+        const int64_t gp = P.p_base + i;
+        float sx, sy, sz;
+        transform(st[job.pair].Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
+        uint32_t v;
+        if (!voxel_of(P, sx, sy, sz, v)) v = (uint32_t)P.V;
+        key = (uint32_t)(P.v_base + job.pair) + v;   // pair p owns buckets [v_base + p, v_base + p + V]
+        slot = (key * 2654435761u) >> 23;
+        while (true) {
+            const uint32_t prev = atomicCAS(&key_[slot], kNone, key);
+            if (prev == kNone || prev == key) break;
+            slot = (slot + 1) & (kBSlots - 1);
+        }
+        lr = atomicAdd(&cnt_[slot], 1u);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
+        const uint32_t k = key_[s];
+        if (k != kNone) base_[s] = atomicAdd(&sh[k], cnt_[s]);
+    }
+    __syncthreads();
+    if (valid) {
+        skey[P.p_base + i] = key;
+        srank[P.p_base + i] = base_[slot] + lr;
+    }
+}
+
+// Places each source point at its bucket position (a global position inside
+// the pair's range, because buckets are concatenated in pair order).
+__global__ __launch_bounds__(256) void k_src_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                   const float* __restrict__ px, const float* __restrict__ py,
+                                                   const float* __restrict__ pz, const uint32_t* __restrict__ skey,
+                                                   const uint32_t* __restrict__ srank,
+                                                   const uint32_t* __restrict__ soff, float4* __restrict__ ps4)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.m) return;
+    const int64_t gp = P.p_base + i;
+    const int64_t pos = (int64_t)soff[skey[gp]] + srank[gp];
+    ps4[pos] = make_float4(px[gp], py[gp], pz[gp], __uint_as_float((uint32_t)i));
 }
 
 // Global search.  Work item = (pair, chunk of kFbQ listed queries, tile of
@@ -212,75 +321,6 @@ __global__ __launch_bounds__(256) void k_fb_finalize(const PairDev* __restrict__
     nn_d2[gp] = __uint_as_float((uint32_t)(key >> 32));
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-// Moments of the correspondences in float64 (sum p, sum q, sum p q^T,
-// sum d, count), one partial per block, reduced in a fixed order.
-__global__ __launch_bounds__(256) void k_moments(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
-                                                 const float* __restrict__ px, const float* __restrict__ py,
-                                                 const float* __restrict__ pz, const float* __restrict__ qx,
-                                                 const float* __restrict__ qy, const float* __restrict__ qz,
-                                                 const PairState* __restrict__ st,
-                                                 const unsigned long long* __restrict__ fb_key,
-                                                 int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
-                                                 double* __restrict__ part, int32_t* __restrict__ flags)
-{
-    __shared__ double red[kMoments][256 / kWave];
-    const BlockJob job = jobs[blockIdx.x];
-    const PairDev& P = pd[job.pair];
-    double a[kMoments];
-#pragma unroll
-    for (int k = 0; k < kMoments; ++k) a[k] = 0.0;
-    const int64_t i = (int64_t)job.start + threadIdx.x;
-    if (!st[job.pair].done && i < P.m) {
-        const int64_t gp = P.p_base + i;
-        int32_t j = nn_idx[gp];
-        float d;
-        if (j < 0) {
-            const unsigned long long key = fb_key[P.p_base + (-1 - j)];
-            j = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
-            d = __uint_as_float((uint32_t)(key >> 32));
-            nn_idx[gp] = j;
-            nn_d2[gp] = d;
-        } else {
-            d = nn_d2[gp];
-        }
-        if ((uint32_t)j >= (uint64_t)P.n) {   // unresolved global search (never expected): flag, do not read
-            atomicOr(&flags[job.pair], 2);
-            j = 0;
-        }
-        const int64_t gq = P.q_base + j;
-        const double p[3] = {px[gp], py[gp], pz[gp]};
-        const double q[3] = {qx[gq], qy[gq], qz[gq]};
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            a[r] = p[r];
-            a[3 + r] = q[r];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] = p[r] * q[c];
-        }
-        a[15] = (double)d;
-        a[16] = 1.0;
-    }
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-    for (int k = 0; k < kMoments; ++k) {
-        const double s = wave_sum(a[k]);
-        if (lane == 0) red[k][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < kMoments) {
-        double s = red[threadIdx.x][0];
-#pragma unroll
-        for (int k = 1; k < 256 / kWave; ++k) s += red[threadIdx.x][k];
-        part[(int64_t)blockIdx.x * kMoments + threadIdx.x] = s;
-    }
-}
-
 __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restrict__ out, int npairs)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,22 +329,45 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 
 }  // namespace
 
-void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, const float* px, const float* py,
-                      const float* pz, const PairState* st, const uint32_t* off, const uint32_t* vm, const float4* qs4,
-                      int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
-                      unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s)
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, bool sorted, const float* px,
+                      const float* py, const float* pz, const float4* ps4, const PairState* st, const uint32_t* off,
+                      const uint32_t* vm, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
+                      uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s)
 {
     if (njobs <= 0) return;
-#define VICP_NNS(BS)                                                                                                  \
-    hipLaunchKernelGGL(k_nns_local<BS>, dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, st, off, vm, qs4, nn_idx, \
-                       nn_d2, fb_count, fb_list, fb_key, ctr)
-    switch (block) {
-    case 64: VICP_NNS(64); break;
-    case 128: VICP_NNS(128); break;
-    case 512: VICP_NNS(512); break;
-    default: VICP_NNS(256); break;
+#define VICP_NNS(BS, SORTED)                                                                                         \
+    hipLaunchKernelGGL((k_nns_local<BS, SORTED>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4, st, off,  \
+                       vm, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
+#define VICP_NNS_BS(SORTED)                          \
+    switch (block) {                                 \
+    case 64: VICP_NNS(64, SORTED); break;            \
+    case 128: VICP_NNS(128, SORTED); break;          \
+    case 512: VICP_NNS(512, SORTED); break;          \
+    default: VICP_NNS(256, SORTED); break;           \
     }
+    if (sorted) {
+        VICP_NNS_BS(true)
+    } else {
+        VICP_NNS_BS(false)
+    }
+#undef VICP_NNS_BS
 #undef VICP_NNS
+}
+
+void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                       const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
+                       hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank);
+}
+
+void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                      const float* pz, const uint32_t* skey, const uint32_t* srank, const uint32_t* soff,
+                      float4* ps4, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_place, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, srank, soff, ps4);
 }
 
 void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
@@ -321,16 +384,6 @@ void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs, cons
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_fb_finalize, dim3(njobs), dim3(256), 0, s, pd, jobs, fb_key, nn_idx, nn_d2, flags);
-}
-
-void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                    const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
-                    const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
-                    hipStream_t s)
-{
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_moments, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, qx, qy, qz, st, fb_key, nn_idx,
-                       nn_d2, part, flags);
 }
 
 void launch_copy_fb(const int32_t* fb_count, int32_t* out, int npairs, hipStream_t s)

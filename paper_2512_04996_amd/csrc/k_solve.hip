@@ -114,20 +114,95 @@ __device__ bool kabsch(const double* mom, double Rt[12])
     return true;
 }
 
-__global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin,
-                                                    const double* __restrict__ part, PairState* __restrict__ st,
-                                                    int32_t* __restrict__ fb_count, unsigned long long* __restrict__ ctr,
-                                                    double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
-                                                    int32_t* __restrict__ deg_hist,
-                                                    unsigned long long* __restrict__ ctr_hist, int k, int K,
-                                                    int early_stop, double eps)
+constexpr int kWave = 64;
+constexpr int kMomItems = 4;   // correspondences per lane
+
+__device__ __forceinline__ double wave_sum(double v)
 {
-    __shared__ double red[kMoments][kThreads];
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Moments of the correspondences in float64 (sum p, sum q, sum p q^T,
+// sum d, count): each lane adds kMomItems correspondences in a fixed order,
+// the block reduces in a fixed order and writes one partial.  The last block
+// of a pair to arrive (an atomic ticket) reduces that pair's partials in
+// block order and solves Eq. 1, so the result does not depend on which block
+// arrives last.
+__global__ __launch_bounds__(kThreads) void k_moments_solve(
+    const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs, const int32_t* __restrict__ job_begin,
+    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+    PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
+    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags, uint32_t* __restrict__ arrive,
+    int32_t* __restrict__ fb_count, unsigned long long* __restrict__ ctr, double* __restrict__ rmse_hist,
+    int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k,
+    int K, int early_stop, double eps)
+{
+    __shared__ double red[kMoments][kThreads / kWave];
     __shared__ double tot[kMoments];
-    const int pair = blockIdx.x;
+    __shared__ int s_last;
+    const BlockJob job = jobs[blockIdx.x];
+    const int pair = job.pair;
+    const PairDev& P = pd[pair];
     PairState& S = st[pair];
-    if (S.done) return;
+    if (S.done) return;   // uniform over the block
+    double a[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) a[j] = 0.0;
+    for (int it = 0; it < kMomItems; ++it) {
+        const int64_t i = (int64_t)job.start + threadIdx.x + it * kThreads;
+        if (i >= P.m) break;
+        const int64_t gp = P.p_base + i;
+        int32_t j = nn_idx[gp];
+        float d;
+        if (j < 0) {
+            const unsigned long long key = fb_key[P.p_base + (-1 - j)];
+            j = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
+            d = __uint_as_float((uint32_t)(key >> 32));
+            nn_idx[gp] = j;
+            nn_d2[gp] = d;
+        } else {
+            d = nn_d2[gp];
+        }
+        if ((uint32_t)j >= (uint64_t)P.n) {   // unresolved global search (never expected): flag, do not read
+            atomicOr(&flags[pair], 2);
+            j = 0;
+        }
+        const int64_t gq = P.q_base + j;
+        const double p[3] = {px[gp], py[gp], pz[gp]};
+        const double q[3] = {qx[gq], qy[gq], qz[gq]};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            a[r] += p[r];
+            a[3 + r] += q[r];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] += p[r] * q[c];
+        }
+        a[15] += (double)d;
+        a[16] += 1.0;
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        const double sm = wave_sum(a[j]);
+        if (lane == 0) red[j][w] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMoments) {
+        double sm = red[threadIdx.x][0];
+#pragma unroll
+        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
+        part[(int64_t)blockIdx.x * kMoments + threadIdx.x] = sm;
+    }
+    __threadfence();
+    __syncthreads();
     const int32_t b0 = job_begin[pair], b1 = job_begin[pair + 1];
+    if (threadIdx.x == 0) s_last = (atomicAdd(&arrive[pair], 1u) == (uint32_t)(b1 - b0 - 1));
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // the pair's partials in block order: lane t sums blocks b0+t, b0+t+256, ...
     double acc[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
@@ -136,18 +211,20 @@ __global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ 
         for (int j = 0; j < kMoments; ++j) acc[j] += part[(int64_t)b * kMoments + j];
     }
 #pragma unroll
-    for (int j = 0; j < kMoments; ++j) red[j][threadIdx.x] = acc[j];
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int j = 0; j < kMoments; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
-        }
-        __syncthreads();
+    for (int j = 0; j < kMoments; ++j) {
+        const double sm = wave_sum(acc[j]);
+        if (lane == 0) red[j][w] = sm;
     }
-    if (threadIdx.x < kMoments) tot[threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < kMoments) {
+        double sm = red[threadIdx.x][0];
+#pragma unroll
+        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
+        tot[threadIdx.x] = sm;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    arrive[pair] = 0u;
     const double m = tot[16];
     const double rmse = m > 0.0 ? sqrt(tot[15] / m) : 0.0;
     double Rt[12];
@@ -161,12 +238,13 @@ __global__ __launch_bounds__(kThreads) void k_solve(const PairDev* __restrict__ 
     } else {
         S.degenerate += 1;
     }
-    rmse_hist[(int64_t)pair * K + k] = rmse;
-    fb_hist[(int64_t)pair * K + k] = fb_count[pair];
-    deg_hist[(int64_t)pair * K + k] = ok ? 0 : 1;
+    const int64_t h = (int64_t)pair * K + k;
+    rmse_hist[h] = rmse;
+    fb_hist[h] = fb_count[pair];
+    deg_hist[h] = ok ? 0 : 1;
+    ctr_hist[2 * h] = ctr[2 * pair];
+    ctr_hist[2 * h + 1] = ctr[2 * pair + 1];
     fb_count[pair] = 0;
-    ctr_hist[2 * ((int64_t)pair * K + k)] = ctr[2 * pair];
-    ctr_hist[2 * ((int64_t)pair * K + k) + 1] = ctr[2 * pair + 1];
     ctr[2 * pair] = 0;
     ctr[2 * pair + 1] = 0;
     S.iters = k + 1;
@@ -195,14 +273,20 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 
 }  // namespace
 
-void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st,
-                  int32_t* fb_count, unsigned long long* ctr, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist,
-                  unsigned long long* ctr_hist, int k, int K, int early_stop, double eps, hipStream_t s)
+void launch_moments_solve(const PairDev* pd, const BlockJob* jobs, int njobs, const int32_t* job_begin,
+                          const float* px, const float* py, const float* pz, const float* qx, const float* qy,
+                          const float* qz, PairState* st, const unsigned long long* fb_key, int32_t* nn_idx,
+                          float* nn_d2, double* part, int32_t* flags, uint32_t* arrive, int32_t* fb_count,
+                          unsigned long long* ctr, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist,
+                          unsigned long long* ctr_hist, int k, int K, int early_stop, double eps, hipStream_t s)
 {
-    if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, ctr, rmse_hist,
-                       fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_moments_solve, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, job_begin, px, py, pz, qx, qy, qz,
+                       st, fb_key, nn_idx, nn_d2, part, flags, arrive, fb_count, ctr, rmse_hist, fb_hist, deg_hist,
+                       ctr_hist, k, K, early_stop, eps);
 }
+
+int moments_items_per_block() { return kThreads * kMomItems; }
 
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)
 {

@@ -227,26 +227,36 @@ struct vicp_grid {
     int32_t pad = 0, rings_applied = 0;
     bool dilated = false;
     std::vector<PairHost> pairs;
+    std::vector<float> voxels;
     Mem mem;
-    std::vector<Buf> owned;
+    std::vector<Buf> owned;     // sized by the target point counts (fixed for the grid)
+    std::vector<Buf> vbufs;     // sized by the voxel counts (change when a rebuild changes V)
 
     PairDev* d_pd = nullptr;
-    uint32_t *hist = nullptr, *off = nullptr, *vm = nullptr;
-    float4* qs4 = nullptr;
-    BlockJob* jobs_q = nullptr;
+    uint32_t* box = nullptr;
+    uint32_t* err = nullptr;
+    BlockJob* jobs_q = nullptr;      // 256 target points per block
     int njobs_q = 0;
+    BlockJob* jobs_q8 = nullptr;     // 2048 target points per block (bounding box)
+    int njobs_q8 = 0;
+    uint32_t *vox = nullptr, *rank = nullptr, *slots = nullptr;
+    float4* qs4 = nullptr;
+    uint32_t *hist = nullptr, *off = nullptr, *vm = nullptr;
     BlockJob* jobs_v = nullptr;
     int njobs_v = 0;
-    uint32_t* err = nullptr;
+    unsigned long long* scan_status = nullptr;
+    uint32_t* scan_ticket = nullptr;
+    uint32_t *dil_a = nullptr, *dil_b = nullptr;
 
-    // tuning choices (result-invariant)
+    // schedule choices (never change a result)
     int nns_block = 256;
-    int fb_grid = 512;
-    int dil_block = 256;
+    int fb_grid = 256;
+    bool sort_src = true;
 
     // source workspace
     std::vector<int64_t> m;   // source layout currently in d_pd / tables
     int64_t m_total = -1;
+    int64_t ws_V = -1;
     int K_cap = 0;
     PairState* st = nullptr;
     void* staging = nullptr;
@@ -256,9 +266,13 @@ struct vicp_grid {
     int32_t* nn_idx = nullptr;
     float* nn_d2 = nullptr;
     double* part = nullptr;
-    int32_t* job_begin = nullptr;
+    int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table
+    int32_t* job_begin_mom = nullptr;   // per pair, blocks of the moments table
     BlockJob* jobs_p[4] = {nullptr, nullptr, nullptr, nullptr};
     int njobs_p[4] = {0, 0, 0, 0};
+    BlockJob* jobs_mom = nullptr;
+    int njobs_mom = 0;
+    uint32_t* arrive = nullptr;
     int32_t* flags = nullptr;
     double* jl6 = nullptr;
     double* rmse_hist = nullptr;
@@ -266,6 +280,10 @@ struct vicp_grid {
     int32_t* deg_hist = nullptr;
     unsigned long long* ctr = nullptr;        // per pair: candidates scanned, dilated lookups
     unsigned long long* ctr_hist = nullptr;   // the same per iteration
+    uint32_t *sh = nullptr, *soff = nullptr, *skey = nullptr, *srank = nullptr;
+    float4* ps4 = nullptr;
+    unsigned long long* s_status = nullptr;
+    uint32_t* s_ticket = nullptr;
     std::vector<Buf> ws_bufs;
 
     // captured registration
@@ -273,12 +291,13 @@ struct vicp_grid {
     hipStream_t cap_stream = nullptr;
     std::vector<uintptr_t> gkey;
 
-    int32_t latched = 0;   // device faults seen at the last sync
-
-    void* take(size_t bytes, hipStream_t s, std::vector<Buf>& list)
+    void* take(size_t bytes, hipStream_t s, std::vector<Buf>& list, bool& ok)
     {
         void* p = mem.get(bytes, s);
-        if (p) list.push_back({p, bytes});
+        if (p)
+            list.push_back({p, bytes});
+        else
+            ok = false;
         return p;
     }
     void release(std::vector<Buf>& list, hipStream_t s)
@@ -292,6 +311,15 @@ struct vicp_grid {
         gexec = nullptr;
         gkey.clear();
     }
+    int64_t extra_bytes() const
+    {
+        int64_t b = 0;
+        for (auto& x : owned) b += (int64_t)x.bytes;
+        for (auto& x : vbufs) b += (int64_t)x.bytes;
+        for (auto& x : ws_bufs) b += (int64_t)x.bytes;
+        // the paper's accounting: histogram + offsets (8 V) and the dilated voxel index (4 (n + 2V))
+        return b - 8 * V_total - 4 * (n_total + 2 * V_total);
+    }
 };
 
 namespace {
@@ -303,35 +331,17 @@ bool capturing(hipStream_t s)
     return cs == hipStreamCaptureStatusActive;
 }
 
-// (Re)build the source-side device state for a per-pair source layout.
-// Synchronises when the layout changes (rare), so that host staging can be
-// released safely.
-int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
+void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
 {
-    std::vector<int64_t> m(m_per_pair, m_per_pair + g->B);
-    for (auto v : m)
-        if (v < 0 || v > (int64_t)INT32_MAX) return fail(VICP_ERR_INVALID_ARG, "source size out of range");
-    const bool same = (m == g->m);
-    if (same && K <= g->K_cap) return VICP_OK;
-    VICP_HIP(hipStreamSynchronize(s));
-    g->drop_graph();
-    g->release(g->ws_bufs, s);
-    const int B = g->B;
-    int64_t mt = 0;
-    for (auto v : m) mt += v;
-    const int Kc = std::max(K, std::max(g->K_cap, 1));
-    // device pair table with the source fields
-    std::vector<PairDev> pd(B);
+    pd.assign(g->B, PairDev{});
     int64_t pb = 0;
-    for (int p = 0; p < B; ++p) {
+    for (int p = 0; p < g->B; ++p) {
         const PairHost& h = g->pairs[p];
         PairDev& d = pd[p];
         d.q_base = h.q_base;
         d.n = h.n;
         d.v_base = h.v_base;
         d.V = h.V;
-        d.p_base = pb;
-        d.m = m[p];
         d.ox = h.origin[0];
         d.oy = h.origin[1];
         d.oz = h.origin[2];
@@ -343,49 +353,96 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
         d.fDy = (float)h.dims[1];
         d.fDz = (float)h.dims[2];
         d.pad = g->pad;
-        pb += m[p];
+        if ((int)g->m.size() == g->B) {
+            d.p_base = pb;
+            d.m = g->m[p];
+            pb += g->m[p];
+        }
     }
-    VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
-    std::vector<BlockJob> jobs[4];
-    std::vector<int32_t> begin;
+}
+
+// (Re)build the source-side device state for a per-pair source layout.
+// Synchronises when the layout changes (rare), so that host staging can be
+// released safely.
+int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
+{
+    std::vector<int64_t> m(m_per_pair, m_per_pair + g->B);
+    for (auto v : m)
+        if (v < 0 || v > (int64_t)INT32_MAX) return fail(VICP_ERR_INVALID_ARG, "source size out of range");
+    if (m == g->m && K <= g->K_cap && g->ws_V == g->V_total) return VICP_OK;
+    VICP_HIP(hipStreamSynchronize(s));
+    g->drop_graph();
+    g->release(g->ws_bufs, s);
+    g->m.clear();
+    g->K_cap = 0;
+    g->ws_V = -1;
+    const int B = g->B;
+    int64_t mt = 0;
+    for (auto v : m) mt += v;
+    const int Kc = std::max(K, 1);
+    std::vector<BlockJob> jobs[4], jm;
+    std::vector<int32_t> begin, begin_m;
     for (int k = 0; k < 4; ++k) make_jobs(m, kBlockSizes[k], jobs[k], k == 2 ? &begin : nullptr);
+    make_jobs(m, moments_items_per_block(), jm, &begin_m);
+    const int64_t nb = g->V_total + B;   // source buckets: V per pair plus one for "outside"
+    const int stiles = scan_tiles(nb);
     auto& L = g->ws_bufs;
+    bool ok = true;
     const size_t mt1 = (size_t)std::max<int64_t>(mt, 1);
-    g->st = (PairState*)g->take(sizeof(PairState) * B, s, L);
-    g->staging = g->take(sizeof(double) * 12 * B, s, L);
-    g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L);
-    g->flags = (int32_t*)g->take(sizeof(int32_t) * B, s, L);
-    g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L);
-    g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L);
-    g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L);
-    g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L);
-    g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[2].size(), 1), s, L);
-    g->job_begin = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L);
-    g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L);
-    g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L);
-    g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
-    g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L);
-    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * B, s, L);
-    g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L);
+    g->st = (PairState*)g->take(sizeof(PairState) * B, s, L, ok);
+    g->staging = g->take(sizeof(double) * 12 * B, s, L, ok);
+    g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
+    g->flags = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
+    g->arrive = (uint32_t*)g->take(sizeof(uint32_t) * B, s, L, ok);
+    g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L, ok);
+    g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L, ok);
+    g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L, ok);
+    g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[2].size(), 1), s, L, ok);
+    g->job_begin = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
+    g->job_begin_mom = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
+    g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L, ok);
+    g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L, ok);
+    g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
+    g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * B, s, L, ok);
+    g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L, ok);
+    g->sh = (uint32_t*)g->take(sizeof(uint32_t) * nb, s, L, ok);
+    g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
+    g->skey = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->srank = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->ps4 = (float4*)g->take(sizeof(float4) * mt1, s, L, ok);
+    g->s_status = (unsigned long long*)g->take(sizeof(unsigned long long) * std::max(stiles, 1), s, L, ok);
+    g->s_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, L, ok);
     for (int k = 0; k < 4; ++k) {
-        g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L);
+        g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L, ok);
         g->njobs_p[k] = (int)jobs[k].size();
     }
-    if (L.size() != 20) {
+    g->jobs_mom = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jm.size(), 1), s, L, ok);
+    g->njobs_mom = (int)jm.size();
+    if (!ok) {
         g->release(g->ws_bufs, s);
-        g->m.clear();
-        g->K_cap = 0;
         return fail(VICP_ERR_OOM, "workspace allocation failed");
     }
+    g->m = m;
+    std::vector<PairDev> pd;
+    fill_pairdev(g, pd);
+    VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
     for (int k = 0; k < 4; ++k)
         if (!jobs[k].empty())
             VICP_HIP(hipMemcpyAsync(g->jobs_p[k], jobs[k].data(), sizeof(BlockJob) * jobs[k].size(),
                                     hipMemcpyHostToDevice, s));
+    if (!jm.empty())
+        VICP_HIP(hipMemcpyAsync(g->jobs_mom, jm.data(), sizeof(BlockJob) * jm.size(), hipMemcpyHostToDevice, s));
     VICP_HIP(hipMemcpyAsync(g->job_begin, begin.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    VICP_HIP(hipMemcpyAsync(g->job_begin_mom, begin_m.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    launch_fill_u32(g->arrive, 0u, B, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
+    launch_fill_u64(g->ctr, 0ull, 2 * B, s);
     VICP_HIP(hipStreamSynchronize(s));
-    g->m = m;
     g->m_total = mt;
     g->K_cap = Kc;
+    g->ws_V = g->V_total;
     return VICP_OK;
 }
 
@@ -396,6 +453,20 @@ int check_grid(const vicp_grid* g)
     return VICP_OK;
 }
 
+// Bucket the source by target voxel at the pose now in g->st (a counting
+// sort into g->ps4), so that the search's neighbouring lanes share segments.
+void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz, hipStream_t s, bool cap)
+{
+    ProfScope ps("src_plan", s, cap);
+    const int64_t nb = g->V_total + g->B;
+    launch_fill_u32(g->sh, 0u, nb, s);
+    launch_fill_u64(g->s_status, 0ull, scan_tiles(nb), s);
+    launch_fill_u32(g->s_ticket, 0u, 4, s);
+    launch_src_bucket(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->st, g->sh, g->skey, g->srank, s);
+    launch_scan(g->sh, nb, g->soff, nullptr, g->s_status, g->s_ticket, s);
+    launch_src_place(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->skey, g->srank, g->soff, g->ps4, s);
+}
+
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
 void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
                   hipStream_t s, bool cap)
@@ -403,8 +474,8 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
     const int slot = block_slot(g->nns_block);
     {
         ProfScope ps("nns_local", s, cap);
-        launch_nns_local(g->d_pd, g->jobs_p[slot], g->njobs_p[slot], g->nns_block, px, py, pz, g->st, g->off, g->vm,
-                         g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr, s);
+        launch_nns_local(g->d_pd, g->jobs_p[slot], g->njobs_p[slot], g->nns_block, g->sort_src, px, py, pz, g->ps4,
+                         g->st, g->off, g->vm, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr, s);
     }
     {
         ProfScope ps("fallback", s, cap);
@@ -417,16 +488,10 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
                      double eps, hipStream_t s, bool cap)
 {
     queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
-    {
-        ProfScope ps("moments", s, cap);
-        launch_moments(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
-                       g->nn_idx, g->nn_d2, g->part, g->flags, s);
-    }
-    {
-        ProfScope ps("solve", s, cap);
-        launch_solve(g->d_pd, g->B, g->job_begin, g->part, g->st, g->fb_count, g->ctr, g->rmse_hist, g->fb_hist,
-                     g->deg_hist, g->ctr_hist, k, K, early, eps, s);
-    }
+    ProfScope ps("moments_solve", s, cap);
+    launch_moments_solve(g->d_pd, g->jobs_mom, g->njobs_mom, g->job_begin_mom, px, py, pz, g->qx, g->qy, g->qz, g->st,
+                         g->fb_key, g->nn_idx, g->nn_d2, g->part, g->flags, g->arrive, g->fb_count, g->ctr,
+                         g->rmse_hist, g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
 }
 
 // float32 grid specification of one pair from its bounding box (host code,
@@ -461,13 +526,115 @@ float unordered(uint32_t k)
     return f;
 }
 
+// Fills (or refills) a grid from target coordinates: bounding box (the one
+// synchronisation), grid specification, then counts, offsets, segments.
+int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
+{
+    const int B = g->B;
+    launch_box_init(g->box, B, s);
+    launch_fill_u32(g->err, 0u, 4, s);
+    {
+        ProfScope ps("aabb", s, false);
+        launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
+    }
+    std::vector<uint32_t> hbox(8 * B);
+    VICP_HIP(hipMemcpyAsync(hbox.data(), g->box, sizeof(uint32_t) * 8 * B, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipStreamSynchronize(s));
+    std::vector<PairHost> pairs = g->pairs;
+    int64_t Vt = 0, words = 0;
+    for (int p = 0; p < B; ++p) {
+        const uint32_t* b = &hbox[8 * p];
+        if (b[6]) return fail(VICP_ERR_NONFINITE, "non-finite target coordinates");
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = unordered(b[a]);
+            hi[a] = unordered(b[3 + a]);
+        }
+        int rc = grid_spec(pairs[p], lo, hi, g->voxels[p], g->pad);
+        if (rc) return rc;
+        pairs[p].v_base = Vt;
+        pairs[p].vm_base = words;
+        Vt += pairs[p].V;
+        words += pairs[p].n + 2 * pairs[p].V;
+    }
+    if (Vt >= ((int64_t)1 << 31) || words >= ((int64_t)1 << 32))
+        return fail(VICP_ERR_GRID_TOO_LARGE, "batch exceeds 2^31 voxels or 2^32 index words");
+    bool same_shape = g->hist != nullptr && Vt == g->V_total;
+    for (int p = 0; p < B && same_shape; ++p) same_shape = pairs[p].V == g->pairs[p].V;
+    g->qx = qx;
+    g->qy = qy;
+    g->qz = qz;
+    g->pairs = pairs;
+    g->dilated = false;
+    g->rings_applied = 0;
+    if (!same_shape) {
+        // voxel-sized buffers follow the new grid; captured work referring to
+        // the old ones is dropped, the source workspace is rebuilt on demand
+        VICP_HIP(hipStreamSynchronize(s));
+        g->drop_graph();
+        g->release(g->ws_bufs, s);
+        g->m.clear();
+        g->ws_V = -1;
+        g->release(g->vbufs, s);
+        g->V_total = Vt;
+        g->vm_words = words;
+        std::vector<int64_t> vcount(B);
+        for (int p = 0; p < B; ++p) vcount[p] = pairs[p].V;
+        std::vector<BlockJob> jv;
+        make_jobs(vcount, 256, jv, nullptr);
+        const int tiles = scan_tiles(Vt);
+        bool ok = true;
+        g->hist = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
+        g->off = (uint32_t*)g->take(sizeof(uint32_t) * (Vt + 1), s, g->vbufs, ok);
+        g->vm = (uint32_t*)g->take(sizeof(uint32_t) * words, s, g->vbufs, ok);
+        g->jobs_v = (BlockJob*)g->take(sizeof(BlockJob) * jv.size(), s, g->vbufs, ok);
+        g->scan_status = (unsigned long long*)g->take(sizeof(unsigned long long) * tiles, s, g->vbufs, ok);
+        g->scan_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->vbufs, ok);
+        g->dil_a = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
+        g->dil_b = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
+        if (!ok) {
+            g->release(g->vbufs, s);
+            g->hist = nullptr;
+            return fail(VICP_ERR_OOM, "grid allocation failed");
+        }
+        g->njobs_v = (int)jv.size();
+        VICP_HIP(hipMemcpyAsync(g->jobs_v, jv.data(), sizeof(BlockJob) * jv.size(), hipMemcpyHostToDevice, s));
+    }
+    std::vector<PairDev> pd;
+    fill_pairdev(g, pd);
+    VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
+    launch_fill_u32(g->hist, 0u, Vt, s);
+    launch_fill_u64(g->scan_status, 0ull, scan_tiles(Vt), s);
+    launch_fill_u32(g->scan_ticket, 0u, 4, s);
+    {
+        ProfScope ps("count", s, false);
+        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, s);
+    }
+    {
+        ProfScope ps("scan", s, false);
+        launch_scan(g->hist, Vt, g->off, g->vm, g->scan_status, g->scan_ticket, s);
+    }
+    {
+        ProfScope ps("place", s, false);
+        launch_place(g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->rank, g->off, g->slots, s);
+    }
+    {
+        ProfScope ps("rank_sort", s, false);
+        launch_rank_sort(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots, g->vm,
+                         g->qs4, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
 
 extern "C" {
 
-const char* vicp_version(void) { return "vicp 0.1 (gfx950)"; }
+const char* vicp_version(void) { return "vicp 0.2 (gfx950)"; }
 
 const char* vicp_last_error(void) { return g_err.c_str(); }
 
@@ -507,139 +674,49 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, c
         pairs[p].q_base = nt;
         nt += n_per_pair[p];
     }
+    if (nt >= ((int64_t)1 << 32)) return fail(VICP_ERR_INVALID_ARG, "too many target points");
     vicp_grid* g = new vicp_grid();
     g->B = npairs;
-    g->qx = qx;
-    g->qy = qy;
-    g->qz = qz;
     g->pad = pad_rings;
     g->n_total = nt;
+    g->pairs = pairs;
+    g->voxels.assign(voxel_per_pair, voxel_per_pair + npairs);
     if (alloc) {
         g->mem.a = *alloc;
         g->mem.custom = true;
     }
     auto bail = [&](int rc) {
+        std::string msg = g_err;
         vicp_grid_free(g);
+        g_err = msg;
         return rc;
     };
-    // pass 1: bounding boxes (the one synchronisation of the build)
     std::vector<int64_t> ncount(npairs);
     for (int p = 0; p < npairs; ++p) ncount[p] = pairs[p].n;
-    std::vector<BlockJob> jq;
+    std::vector<BlockJob> jq, jq8;
     make_jobs(ncount, 256, jq, nullptr);
-    if (jq.size() > (size_t)INT32_MAX) return bail(fail(VICP_ERR_INVALID_ARG, "too many points"));
-    std::vector<PairDev> pd(npairs);
-    for (int p = 0; p < npairs; ++p) {
-        pd[p] = PairDev{};
-        pd[p].q_base = pairs[p].q_base;
-        pd[p].n = pairs[p].n;
-    }
-    g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned);
-    g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned);
-    uint32_t* box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * npairs, s, g->owned);
-    g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned);
-    if (!g->d_pd || !g->jobs_q || !box || !g->err) return bail(fail(VICP_ERR_OOM, "allocation failed"));
+    make_jobs(ncount, 2048, jq8, nullptr);
+    bool ok = true;
+    g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned, ok);
+    g->box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * npairs, s, g->owned, ok);
+    g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned, ok);
+    g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned, ok);
+    g->jobs_q8 = (BlockJob*)g->take(sizeof(BlockJob) * jq8.size(), s, g->owned, ok);
+    g->vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
+    g->rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
+    g->slots = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
+    g->qs4 = (float4*)g->take(sizeof(float4) * nt, s, g->owned, ok);
+    if (!ok) return bail(fail(VICP_ERR_OOM, "allocation failed"));
     g->njobs_q = (int)jq.size();
+    g->njobs_q8 = (int)jq8.size();
+    std::vector<PairDev> pd;
+    fill_pairdev(g, pd);   // target fields only; the grid fields follow the bounding box
     if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g->jobs_q, jq.data(), sizeof(BlockJob) * jq.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(g->jobs_q, jq.data(), sizeof(BlockJob) * jq.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g->jobs_q8, jq8.data(), sizeof(BlockJob) * jq8.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(VICP_ERR_HIP, "upload failed"));
-    launch_box_init(box, npairs, s);
-    launch_fill_u32(g->err, 0u, 4, s);
-    {
-        ProfScope ps("aabb", s, false);
-        launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, 256, box, s);
-    }
-    std::vector<uint32_t> hbox(8 * npairs);
-    if (hipMemcpyAsync(hbox.data(), box, sizeof(uint32_t) * 8 * npairs, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return bail(fail(VICP_ERR_HIP, std::string("bounding box: ") + hipGetErrorString(hipGetLastError())));
-    int64_t Vt = 0, words = 0;
-    for (int p = 0; p < npairs; ++p) {
-        const uint32_t* b = &hbox[8 * p];
-        if (b[6]) return bail(fail(VICP_ERR_NONFINITE, "non-finite target coordinates"));
-        float lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = unordered(b[a]);
-            hi[a] = unordered(b[3 + a]);
-        }
-        int rc = grid_spec(pairs[p], lo, hi, voxel_per_pair[p], pad_rings);
-        if (rc) return bail(rc);
-        pairs[p].v_base = Vt;
-        pairs[p].vm_base = words;
-        Vt += pairs[p].V;
-        words += pairs[p].n + 2 * pairs[p].V;
-    }
-    if (Vt >= ((int64_t)1 << 31) || words >= ((int64_t)1 << 32))
-        return bail(fail(VICP_ERR_GRID_TOO_LARGE, "batch exceeds 2^31 voxels or 2^32 index words"));
-    g->pairs = pairs;
-    g->V_total = Vt;
-    g->vm_words = words;
-    for (int p = 0; p < npairs; ++p) {
-        const PairHost& h = pairs[p];
-        PairDev& d = pd[p];
-        d.v_base = h.v_base;
-        d.V = h.V;
-        d.ox = h.origin[0];
-        d.oy = h.origin[1];
-        d.oz = h.origin[2];
-        d.inv = h.inv;
-        d.Dx = h.dims[0];
-        d.Dy = h.dims[1];
-        d.Dz = h.dims[2];
-        d.fDx = (float)h.dims[0];
-        d.fDy = (float)h.dims[1];
-        d.fDz = (float)h.dims[2];
-        d.pad = pad_rings;
-    }
-    std::vector<int64_t> vcount(npairs);
-    for (int p = 0; p < npairs; ++p) vcount[p] = pairs[p].V;
-    std::vector<BlockJob> jv;
-    make_jobs(vcount, 256, jv, nullptr);
-    // pass 2: counts, offsets, segments
-    g->hist = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->owned);
-    g->off = (uint32_t*)g->take(sizeof(uint32_t) * (Vt + 1), s, g->owned);
-    g->vm = (uint32_t*)g->take(sizeof(uint32_t) * words, s, g->owned);
-    g->qs4 = (float4*)g->take(sizeof(float4) * nt, s, g->owned);
-    g->jobs_v = (BlockJob*)g->take(sizeof(BlockJob) * jv.size(), s, g->owned);
-    const int tiles = scan_tiles(Vt);
-    std::vector<Buf> tmp;
-    uint32_t* vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
-    uint32_t* rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
-    uint32_t* slots = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, tmp);
-    unsigned long long* status = (unsigned long long*)g->take(sizeof(unsigned long long) * tiles, s, tmp);
-    uint32_t* ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, tmp);
-    if (!g->hist || !g->off || !g->vm || !g->qs4 || !g->jobs_v || !vox || !rank || !slots || !status || !ticket) {
-        g->release(tmp, s);
-        return bail(fail(VICP_ERR_OOM, "grid allocation failed"));
-    }
-    g->njobs_v = (int)jv.size();
-    if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g->jobs_v, jv.data(), sizeof(BlockJob) * jv.size(), hipMemcpyHostToDevice, s) != hipSuccess) {
-        g->release(tmp, s);
-        return bail(fail(VICP_ERR_HIP, "upload failed"));
-    }
-    launch_fill_u32(g->hist, 0u, Vt, s);
-    launch_fill_u64(status, 0ull, tiles, s);
-    launch_fill_u32(ticket, 0u, 4, s);
-    {
-        ProfScope ps("count", s, false);
-        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, vox, rank, g->err, s);
-    }
-    {
-        ProfScope ps("scan", s, false);
-        launch_scan(g->hist, Vt, g->off, g->vm, status, ticket, s);
-    }
-    {
-        ProfScope ps("place", s, false);
-        launch_place(g->d_pd, g->jobs_q, g->njobs_q, vox, rank, g->off, slots, s);
-    }
-    {
-        ProfScope ps("rank_sort", s, false);
-        launch_rank_sort(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, vox, g->hist, g->off, slots, g->vm, g->qs4, s);
-    }
-    g->release(tmp, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return bail(fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e)));
+    int rc = grid_fill(g, qx, qy, qz, s);
+    if (rc) return bail(rc);
     *out = g;
     return VICP_OK;
 }
@@ -648,6 +725,14 @@ int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n
                     const vicp_allocator* alloc, hipStream_t s, vicp_grid** out)
 {
     return vicp_build_grid_batched(qx, qy, qz, &n, 1, &voxel, pad_rings, alloc, s, out);
+}
+
+int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!qx || !qy || !qz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    return grid_fill(g, qx, qy, qz, s);
 }
 
 int vicp_grid_npairs(const vicp_grid* g) { return g ? g->B : 0; }
@@ -660,18 +745,8 @@ int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
     if (rings < 0 || rings > g->pad) return fail(VICP_ERR_INVALID_ARG, "rings must be in [0, pad_rings]");
     g->dilated = true;
     g->rings_applied = rings;
-    if (rings == 0) return VICP_OK;
-    std::vector<Buf> tmp;
-    uint32_t* a = nullptr;
-    uint32_t* b = nullptr;
-    if (rings > 1) {
-        a = (uint32_t*)g->take(sizeof(uint32_t) * g->V_total, s, tmp);
-        b = (uint32_t*)g->take(sizeof(uint32_t) * g->V_total, s, tmp);
-        if (!a || !b) {
-            g->release(tmp, s);
-            return fail(VICP_ERR_OOM, "dilation state allocation failed");
-        }
-    }
+    uint32_t* a = g->dil_a;
+    uint32_t* b = g->dil_b;
     const bool cap = capturing(s);
     for (int r = 1; r <= rings; ++r) {
         ProfScope ps("dilate_ring", s, cap);
@@ -679,7 +754,6 @@ int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
                            r == rings ? nullptr : b, r == 1, r == rings, s);
         std::swap(a, b);
     }
-    g->release(tmp, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("dilate: ") + hipGetErrorString(e));
     return VICP_OK;
@@ -694,18 +768,16 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     if (!m_per_pair || !Rt) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     int64_t mt = 0;
     for (int p = 0; p < g->B; ++p) mt += std::max<int64_t>(m_per_pair[p], 0);
-    if (mt == 0) {
-        if (n_fallback) {
-            std::vector<int32_t> z(g->B, 0);
-            upload(z.data(), sizeof(int32_t) * g->B, n_fallback, s);
-        }
-        return ensure_source(g, m_per_pair, 1, s);
-    }
-    if (!px || !py || !pz || !nn_idx || !nn_d2) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     rc = ensure_source(g, m_per_pair, 1, s);
     if (rc) return rc;
+    if (mt == 0) {
+        if (n_fallback) launch_fill_u32((uint32_t*)n_fallback, 0u, g->B, s);
+        return VICP_OK;
+    }
+    if (!px || !py || !pz || !nn_idx || !nn_d2) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    for (int i = 0; i < 12 * g->B; ++i)
+        if (!isfinite(Rt[i])) return fail(VICP_ERR_INVALID_ARG, "non-finite pose");
     const bool cap = capturing(s);
-    // poses: float32 for the search; the float64 field is not used here
     std::vector<double> rt64(12 * g->B);
     for (int i = 0; i < 12 * g->B; ++i) rt64[i] = (double)Rt[i];
     upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
@@ -714,6 +786,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
+    if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap);
     {
         ProfScope ps("fb_finalize", s, cap);
@@ -769,7 +842,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     launch_fill_u64(g->ctr, 0ull, 2 * B, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
-                                      (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid};
+                                      (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid, (uintptr_t)g->sort_src,
+                                      (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
         uint64_t eb;
         memcpy(&eb, &eps, 8);
         key.push_back((uintptr_t)eb);
@@ -778,6 +852,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
             if (!g->cap_stream) VICP_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
             hipGraph_t graph = nullptr;
             VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+            if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
             for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true);
             VICP_HIP(hipStreamEndCapture(g->cap_stream, &graph));
             hipError_t e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
@@ -792,12 +867,13 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
         VICP_HIP(hipGraphLaunch(g->gexec, s));
     } else {
         const bool cap = capturing(s);
+        if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
         for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap);
     }
     std::vector<PairState> hst(B);
-    std::vector<double> hr((size_t)B * g->K_cap);
-    std::vector<int32_t> hf((size_t)B * g->K_cap), hd((size_t)B * g->K_cap), hflags(B);
-    std::vector<unsigned long long> hc(2 * (size_t)B * g->K_cap);
+    std::vector<double> hr((size_t)B * K);
+    std::vector<int32_t> hf((size_t)B * K), hd((size_t)B * K), hflags(B);
+    std::vector<unsigned long long> hc(2 * (size_t)B * K);
     VICP_HIP(hipMemcpyAsync(hst.data(), g->st, sizeof(PairState) * B, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hr.data(), g->rmse_hist, sizeof(double) * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hf.data(), g->fb_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
@@ -816,10 +892,11 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
             S.iters = hst[p].iters;
             S.degenerate = hst[p].degenerate;
             for (int k = 0; k < hst[p].iters && k < K; ++k) {
-                if (S.rmse) S.rmse[k] = hr[(size_t)p * K + k];
-                if (S.fallbacks) S.fallbacks[k] = hf[(size_t)p * K + k];
-                if (S.candidates) S.candidates[k] = (int64_t)hc[2 * ((size_t)p * K + k)];
-                if (S.dilated_lookups) S.dilated_lookups[k] = (int64_t)hc[2 * ((size_t)p * K + k) + 1];
+                const size_t h = (size_t)p * K + k;
+                if (S.rmse) S.rmse[k] = hr[h];
+                if (S.fallbacks) S.fallbacks[k] = hf[h];
+                if (S.candidates) S.candidates[k] = (int64_t)hc[2 * h];
+                if (S.dilated_lookups) S.dilated_lookups[k] = (int64_t)hc[2 * h + 1];
             }
         }
     }
@@ -852,6 +929,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
     launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
+    if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
     return VICP_OK;
 }
@@ -916,16 +994,13 @@ int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out)
     out->static_bytes = 8 * h.V;
     out->dynamic_bytes = 4 * (h.n + 2 * h.V);
     out->vanicp_bytes = 65536 * h.V;
-    // beyond the paper's accounting: the extra offset entry, the segment-
-    // ordered float4 copy of the target, and the work tables
-    out->extra_bytes = 4 + 16 * h.n;
-    hipStream_t s = nullptr;
+    out->extra_bytes = g->extra_bytes();
     VICP_HIP(hipDeviceSynchronize());
     unsigned long long* cnt = nullptr;
     VICP_HIP(hipMalloc(&cnt, sizeof(unsigned long long) * 4));
     VICP_HIP(hipMemset(cnt, 0, sizeof(unsigned long long) * 4));
     hipLaunchKernelGGL(k_grid_stats, dim3(std::max<int64_t>(1, std::min<int64_t>((h.V + 255) / 256, 2048))), dim3(256),
-                       0, s, g->hist + h.v_base, g->off + h.v_base, g->vm, h.V, cnt);
+                       0, nullptr, g->hist + h.v_base, g->off + h.v_base, g->vm, h.V, cnt);
     unsigned long long hc[4] = {0, 0, 0, 0};
     uint32_t herr = 0;
     hipError_t e1 = hipMemcpy(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost);
@@ -963,23 +1038,26 @@ int vicp_grid_free(vicp_grid* g)
     g->drop_graph();
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->release(g->ws_bufs, nullptr);
+    g->release(g->vbufs, nullptr);
     g->release(g->owned, nullptr);
     (void)hipDeviceSynchronize();
     delete g;
     return VICP_OK;
 }
 
-// The search schedule (lanes per block of the local search, blocks of the
-// global search) never changes a result; this times the candidates on the
-// caller's data at the identity pose and keeps the fastest.
+// The search schedule (lanes per block, source bucketing on or off, blocks of
+// the global search) never changes a result; this times the candidates on
+// the caller's data at the identity pose and keeps the fastest.
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
                   hipStream_t s)
 {
     int rc = check_grid(g);
     if (rc) return rc;
+    if (!m_per_pair) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     rc = ensure_source(g, m_per_pair, 1, s);
     if (rc) return rc;
     if (g->m_total == 0) return VICP_OK;
+    if (!px || !py || !pz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     std::vector<double> rt(12 * g->B, 0.0);
     for (int p = 0; p < g->B; ++p) rt[12 * p] = rt[12 * p + 4] = rt[12 * p + 8] = 1.0;
     upload(rt.data(), sizeof(double) * 12 * g->B, g->staging, s);
@@ -987,13 +1065,16 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     hipEvent_t a, b;
     VICP_HIP(hipEventCreate(&a));
     VICP_HIP(hipEventCreate(&b));
-    auto time_cfg = [&](int bs, int fg) -> float {
+    auto time_cfg = [&](int bs, bool sorted, int fg) -> float {
         g->nns_block = bs;
+        g->sort_src = sorted;
         g->fb_grid = fg;
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+            launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
             (void)hipEventRecord(a, s);
+            if (sorted) queue_plan(g, px, py, pz, s, true);
             queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true);
             (void)hipEventRecord(b, s);
             (void)hipEventSynchronize(b);
@@ -1003,29 +1084,57 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
         }
         return best;
     };
-    int best_bs = 256, best_fg = 512;
+    int best_bs = 256, best_fg = 256;
+    bool best_sorted = true;
     float best = 1e30f;
-    for (int bs : kBlockSizes) {
-        const float t = time_cfg(bs, best_fg);
-        if (t < best) {
-            best = t;
-            best_bs = bs;
+    for (int sorted = 0; sorted < 2; ++sorted)
+        for (int bs : kBlockSizes) {
+            const float t = time_cfg(bs, sorted != 0, best_fg);
+            if (t < best) {
+                best = t;
+                best_bs = bs;
+                best_sorted = sorted != 0;
+            }
         }
-    }
-    for (int fg : {256, 512, 1024, 2048}) {
-        const float t = time_cfg(best_bs, fg);
+    for (int fg : {128, 256, 512, 1024}) {
+        const float t = time_cfg(best_bs, best_sorted, fg);
         if (t < best) {
             best = t;
             best_fg = fg;
         }
     }
     g->nns_block = best_bs;
+    g->sort_src = best_sorted;
     g->fb_grid = best_fg;
     g->drop_graph();
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+    return VICP_OK;
+}
+
+int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* sort_source, int32_t* fallback_grid)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (nns_block) *nns_block = g->nns_block;
+    if (sort_source) *sort_source = g->sort_src ? 1 : 0;
+    if (fallback_grid) *fallback_grid = g->fb_grid;
+    return VICP_OK;
+}
+
+int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t sort_source, int32_t fallback_grid)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (nns_block != 64 && nns_block != 128 && nns_block != 256 && nns_block != 512)
+        return fail(VICP_ERR_INVALID_ARG, "nns_block must be 64, 128, 256 or 512");
+    if (fallback_grid < 1 || fallback_grid > 65536) return fail(VICP_ERR_INVALID_ARG, "fallback_grid out of range");
+    g->nns_block = nns_block;
+    g->sort_src = sort_source != 0;
+    g->fb_grid = fallback_grid;
+    g->drop_graph();
     return VICP_OK;
 }
 

@@ -261,3 +261,41 @@ def test_autotune_is_result_invariant():
     r1 = g.register(p, 8)
     assert np.array_equal(i0, i1) and np.array_equal(d0, d1) and np.array_equal(f0, f1)
     assert np.array_equal(r0.Rt, r1.Rt)
+
+
+def test_rebuild_equals_fresh_build():
+    P = synth.config("bumpy_40k")
+    q2 = synth.bumpy_pair(seed=99, n=P.n, m=10, voxel=P.voxel).q        # same size, other shape
+    q3 = (P.q * np.float32(1.3)).astype(np.float32)                        # more voxels
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    r0 = g.register(p, 5)
+    for qn in (q2, q3, P.q):
+        g.rebuild(dev(qn)).dilate(P.rings)
+        og = oracle.dilate(oracle.build_grid(qn, P.voxel, P.rings), P.rings)
+        check_grid(g, og)
+        r = g.register(p, 5)
+        ref = oracle.register(qn, P.p, P.voxel, P.rings, 5)
+        assert list(r.fallbacks[0]) == list(ref.fallbacks)
+        assert rot_angle(r.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+    assert np.array_equal(r.Rt, r0.Rt)                                      # back on the first target
+
+
+@pytest.mark.parametrize("sort_source", [False, True])
+@pytest.mark.parametrize("nns_block", [64, 512])
+def test_schedules_are_result_invariant(sort_source, nns_block):
+    P = synth.config("room_226k")
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    Rt = random_pose(5, 3.0, 0.08)
+    ref_idx, ref_d2, ref_F, _ = oracle.nns(oracle.dilate(oracle.build_grid(P.q, P.voxel, P.rings), P.rings),
+                                           P.q, P.p, Rt)
+    g.set_schedule(nns_block, sort_source, 128)
+    assert g.schedule == {"nns_block": nns_block, "sort_source": sort_source, "fallback_grid": 128}
+    idx, d2, fb = g.nns(p, Rt)
+    assert np.array_equal(idx.cpu().numpy(), ref_idx) and np.array_equal(d2.cpu().numpy(), ref_d2)
+    assert int(fb.cpu()[0]) == ref_F
+    r = g.register(p, 6)
+    g.set_schedule(256, True, 256)
+    r2 = g.register(p, 6)
+    assert np.array_equal(r.Rt, r2.Rt) and np.array_equal(r.rmse[0], r2.rmse[0])
