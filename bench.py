@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="room_226k")
-    ap.add_argument("--graph", type=int, default=0, help="replay the ICP iterations from a hipGraph")
+    ap.add_argument("--graph", type=int, default=1, help="replay the ICP iterations from a hipGraph")
+    ap.add_argument("--autotune", type=int, default=1, help="pick the search schedule on this workload first")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
@@ -81,21 +82,28 @@ def main():
     p = torch.from_numpy(P.p).to(dev)
     torch.cuda.synchronize()
 
-    def step():
-        g = api.build_grid(q, P.voxel, P.rings)
+    # one grid object serves every step: each step refills it from the target
+    # (bounding box, counts, offsets, segments), dilates it and registers
+    g = api.build_grid(q, P.voxel, P.rings)
+    if a.autotune:
         g.dilate(P.rings)
-        r = g.register(p, P.iters, use_graph=bool(a.graph))
-        g.free()
-        return r
+        g.autotune(p)
+    schedule = g.schedule
+
+    def step():
+        g.rebuild(q)
+        g.dilate(P.rings)
+        return g.register(p, P.iters, use_graph=bool(a.graph))
 
     log(f"[bench] workload {P.name}: n={P.n} m={P.m} voxel={P.voxel} rings={P.rings} iters={P.iters}")
-    for _ in range(a.warmup):
-        res = step()
-    log("[bench] warmup done")
     prof = not a.no_prof
     if prof:
+        api.prof_enable(True)        # before warm-up, so the captured graph already holds the events
+    for _ in range(max(a.warmup, 1)):
+        res = step()
+    log("[bench] warmup done")
+    if prof:
         api.prof_reset()
-        api.prof_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
@@ -110,8 +118,8 @@ def main():
     queries_per_s = K * P.m / (ms * 1e-3)
     kernels = {}
     if prof:
-        for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "nns_local", "fallback",
-                     "moments", "solve"):
+        for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "src_plan", "nns_local",
+                     "fallback", "moments_solve", "icp_graph"):
             n_launch, tot = api.prof_read(name)
             if n_launch:
                 kernels[name] = {"launches_per_step": n_launch / a.steps, "avg_us": 1e3 * tot / n_launch,
@@ -137,9 +145,6 @@ def main():
                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
                     "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3)}
 
-    desc = None
-    g = api.build_grid(q, P.voxel, P.rings)
-    g.dilate(P.rings)
     desc = g.describe()
     g.free()
     dil_bytes = {"workload": P.name, "V": desc["V"], "occupied": desc["occupied"], "dilated": desc["dilated"],
@@ -154,7 +159,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": P.name, "n_target": P.n, "n_source": P.m, "voxel": P.voxel, "rings": P.rings,
                    "iters": P.iters, "step": "grid build + dilation + 30 ICP iterations",
-                   "icp_mode": "graph" if a.graph else "eager"},
+                   "icp_mode": "graph" if a.graph else "eager", "schedule": schedule},
         "icp_iters_per_s": round(K / (ms * 1e-3), 2),
         "roofline": roofline,
         "kernels": kernels,
@@ -196,46 +201,51 @@ def extra_figures(api, synth, torch, dev, np):
     vox = [x.voxel for x in pairs]
     iters = pairs[0].iters
 
+    gb = api.build_grid_batched(qc, ns, vox, 3)
+    V_total = sum(gb.describe(b)["V"] for b in range(len(pairs)))
+
     def batched():
-        g = api.build_grid_batched(qc, ns, vox, 3)
-        g.dilate(3)
-        r = g.register(pc, iters, m_per_pair=ms_, use_graph=True)
-        V = sum(g.describe(b)["V"] for b in range(len(pairs))) if not hasattr(batched, "V") else batched.V
-        batched.V = V
-        g.free()
-        return r
+        gb.rebuild(qc)
+        gb.dilate(3)
+        return gb.register(pc, iters, m_per_pair=ms_, use_graph=True)
 
     qs = [torch.from_numpy(x.q).to(dev) for x in pairs]
     ps = [torch.from_numpy(x.p).to(dev) for x in pairs]
+    singles = [api.build_grid(qs[b], x.voxel, 3) for b, x in enumerate(pairs)]
 
     def looped():
         out = []
-        for b, x in enumerate(pairs):
-            g = api.build_grid(qs[b], x.voxel, 3)
-            g.dilate(3)
-            out.append(g.register(ps[b], iters, use_graph=False))
-            g.free()
+        for b in range(len(pairs)):
+            singles[b].rebuild(qs[b])
+            singles[b].dilate(3)
+            out.append(singles[b].register(ps[b], iters, use_graph=True))
         return out
 
-    rb = batched()
-    looped()
+    for _ in range(2):
+        rb = batched()
+        looped()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(3):
+    for _ in range(5):
         rb = batched()
     torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / 3
+    tb = (time.perf_counter() - t0) / 5
     t0 = time.perf_counter()
-    rl = looped()
+    for _ in range(2):
+        rl = looped()
     torch.cuda.synchronize()
-    tl = time.perf_counter() - t0
+    tl = (time.perf_counter() - t0) / 2
     same = all(np.array_equal(rb.Rt[b], rl[b].Rt) for b in range(len(pairs)))
-    ex["batched_64"] = {"pairs": len(pairs), "points": int(sum(ns)), "V_total": int(batched.V),
+    fb0 = int(sum(int(f[0]) for f in rb.fallbacks if len(f)))
+    gb.free()
+    for x in singles:
+        x.free()
+    ex["batched_64"] = {"pairs": len(pairs), "points": int(sum(ns)), "V_total": int(V_total),
                         "ms": round(tb * 1e3, 3), "pairs_per_s": round(len(pairs) / tb, 2),
                         "pair_iters_per_s": round(len(pairs) * iters / tb, 1),
                         "looped_single_ms": round(tl * 1e3, 3), "speedup_vs_looped": round(tl / tb, 3),
-                        "bit_identical_to_looped": bool(same),
-                        "vanicp_fixed_bytes": int(65536 * batched.V)}
+                        "bit_identical_to_looped": bool(same), "fallbacks_iter0": fb0,
+                        "vanicp_fixed_bytes": int(65536 * V_total)}
     # differentiable: 16 x 40k forward + backward
     log("[bench] differentiable workload")
     dpairs, xi = synth.config("diff_16x40k")

@@ -133,26 +133,59 @@ void prof_flush_locked()
     g_prof.recs.clear();
 }
 
-// Brackets one launch with events when timing is on and the stream is not
-// being captured.
+// Events recorded while a registration is being captured: they become event
+// nodes of the graph and time each kernel of every replay.
+thread_local std::vector<ProfRec>* t_capture_events = nullptr;
+
+// Brackets one launch with events when timing is on.  Outside capture the
+// pair is read at the next vicp_prof_read; inside capture it is kept with the
+// graph and read after each replay.
 struct ProfScope {
     hipStream_t s;
     const char* name;
     hipEvent_t b = nullptr;
     ProfScope(const char* nm, hipStream_t st, bool capturing) : s(st), name(nm)
     {
-        if (!g_prof.on || capturing) return;
+        if (!g_prof.on) return;
+        if (capturing && !t_capture_events) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
         hipEvent_t a = prof_event();
         b = prof_event();
         (void)hipEventRecord(a, s);
-        g_prof.recs.push_back({name, a, b});
+        if (capturing)
+            t_capture_events->push_back({name, a, b});
+        else
+            g_prof.recs.push_back({name, a, b});
     }
     ~ProfScope()
     {
         if (b) (void)hipEventRecord(b, s);
     }
 };
+
+// After a replay has finished: add the graph's kernel times.
+void prof_add_graph(const std::vector<ProfRec>& evs)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& r : evs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && ms >= 0.0f) {
+            auto& x = g_prof.acc[r.name];
+            x.first += 1;
+            x.second += ms;
+        }
+    }
+}
+
+void prof_return(std::vector<ProfRec>& evs)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& r : evs) {
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    evs.clear();
+}
 
 // ---------------------------------------------------------------- memory
 
@@ -290,6 +323,7 @@ struct vicp_grid {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
     std::vector<uintptr_t> gkey;
+    std::vector<ProfRec> gevents;   // per-kernel event pairs inside the graph (timing on)
 
     void* take(size_t bytes, hipStream_t s, std::vector<Buf>& list, bool& ok)
     {
@@ -310,6 +344,7 @@ struct vicp_grid {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         gexec = nullptr;
         gkey.clear();
+        prof_return(gevents);
     }
     int64_t extra_bytes() const
     {
@@ -847,20 +882,34 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
         uint64_t eb;
         memcpy(&eb, &eps, 8);
         key.push_back((uintptr_t)eb);
+        key.push_back((uintptr_t)(g_prof.on ? 1 : 0));
         if (!g->gexec || key != g->gkey) {
             g->drop_graph();
             if (!g->cap_stream) VICP_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-            if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
-            for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true);
-            VICP_HIP(hipStreamEndCapture(g->cap_stream, &graph));
-            hipError_t e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) {
-                g->gexec = nullptr;
-                return fail(VICP_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            // with timing on, the first attempt records kernel events inside
+            // the graph; if the runtime refuses that, capture without them
+            std::string why;
+            for (int attempt = (g_prof.on ? 0 : 1); attempt < 2 && !g->gexec; ++attempt) {
+                hipGraph_t graph = nullptr;
+                VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+                t_capture_events = attempt == 0 ? &g->gevents : nullptr;
+                if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
+                for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true);
+                t_capture_events = nullptr;
+                hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
+                hipError_t e = ec;
+                if (ec == hipSuccess) {
+                    e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                }
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    g->gexec = nullptr;
+                    prof_return(g->gevents);
+                    why = hipGetErrorString(e);
+                }
             }
+            if (!g->gexec) return fail(VICP_ERR_HIP, "graph capture: " + why);
             g->gkey = key;
         }
         ProfScope ps("icp_graph", s, false);
@@ -881,6 +930,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     VICP_HIP(hipMemcpyAsync(hflags.data(), g->flags, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipMemcpyAsync(hc.data(), g->ctr_hist, sizeof(unsigned long long) * 2 * B * K, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
+    if (o->use_graph && g_prof.on) prof_add_graph(g->gevents);
     bool nonfinite = false, degenerate = false, internal = false;
     for (int p = 0; p < B; ++p) {
         memcpy(Rt_io + 12 * p, hst[p].Rt, sizeof(double) * 12);
