@@ -163,7 +163,9 @@ struct ProfScope {
     }
 };
 
-// After a replay has finished: add the graph's kernel times.
+// After a replay has finished: add the graph's kernel times.  Runtimes that
+// cannot time events recorded by a graph report an error here; it is cleared
+// and the graph's kernels simply go untimed.
 void prof_add_graph(const std::vector<ProfRec>& evs)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -173,6 +175,9 @@ void prof_add_graph(const std::vector<ProfRec>& evs)
             auto& x = g_prof.acc[r.name];
             x.first += 1;
             x.second += ms;
+        } else {
+            (void)hipGetLastError();
+            g_prof.acc["graph_untimed"].first += 1;
         }
     }
 }
@@ -692,6 +697,7 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, c
                             const float* voxel_per_pair, int32_t pad_rings, const vicp_allocator* alloc,
                             hipStream_t s, vicp_grid** out)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     if (!out) return fail(VICP_ERR_INVALID_ARG, "null output");
     *out = nullptr;
     if (!qx || !qy || !qz || !n_per_pair || !voxel_per_pair) return fail(VICP_ERR_INVALID_ARG, "null pointer");
@@ -764,6 +770,7 @@ int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n
 
 int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (!qx || !qy || !qz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
@@ -774,6 +781,7 @@ int vicp_grid_npairs(const vicp_grid* g) { return g ? g->B : 0; }
 
 int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (g->dilated) return fail(VICP_ERR_STATE, "grid already dilated");
@@ -797,6 +805,7 @@ int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
 int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
                      const float* Rt, int32_t* nn_idx, float* nn_d2, int32_t* n_fallback, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     vicp_grid* g = const_cast<vicp_grid*>(gc);
     int rc = check_grid(g);
     if (rc) return rc;
@@ -846,6 +855,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                           const int64_t* m_per_pair, const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats,
                           hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     vicp_grid* g = const_cast<vicp_grid*>(gc);
     int rc = check_grid(g);
     if (rc) return rc;
@@ -987,6 +997,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
 int vicp_p2p_loss_fwd(const vicp_grid* gc, const float* px, const float* py, const float* pz,
                       const int64_t* m_per_pair, const double* xi, double* loss, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     vicp_grid* g = const_cast<vicp_grid*>(gc);
     if (!loss) return fail(VICP_ERR_INVALID_ARG, "null loss");
     int rc = p2p_common(g, px, py, pz, m_per_pair, xi, s);
@@ -1007,6 +1018,7 @@ int vicp_p2p_loss_bwd(const vicp_grid* gc, const float* px, const float* py, con
                       const int64_t* m_per_pair, const double* xi, const double* gloss, float* dpx, float* dpy,
                       float* dpz, double* dxi, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     vicp_grid* g = const_cast<vicp_grid*>(gc);
     if (!gloss || !dxi) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     int rc = p2p_common(g, px, py, pz, m_per_pair, xi, s);
@@ -1026,6 +1038,7 @@ int vicp_p2p_loss_bwd(const vicp_grid* gc, const float* px, const float* py, con
 
 int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (!out || pair < 0 || pair >= g->B) return fail(VICP_ERR_INVALID_ARG, "bad pair or output");
@@ -1066,6 +1079,7 @@ int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out)
 
 int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t* off, uint32_t* vm, hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (pair < 0 || pair >= g->B) return fail(VICP_ERR_INVALID_ARG, "bad pair");
@@ -1101,6 +1115,7 @@ int vicp_grid_free(vicp_grid* g)
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
                   hipStream_t s)
 {
+    (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (!m_per_pair) return fail(VICP_ERR_INVALID_ARG, "null pointer");
