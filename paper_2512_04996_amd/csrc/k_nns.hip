@@ -82,11 +82,13 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     if (S.done) return;   // uniform over the block
     const int64_t t = (int64_t)job.start + threadIdx.x;
     const bool active = t < P.m;
-    uint32_t c = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t c = 0, i = 0;
+    int64_t cs = 0;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     bool dil = false;
     if (active) {
         float x, y, z;
-        uint32_t i;
         if (kSorted) {
             const float4 pp = ps4[P.p_base + t];
             x = pp.x;
@@ -99,11 +101,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             z = pz[P.p_base + t];
             i = (uint32_t)t;
         }
-        const int64_t gp = P.p_base + i;
-        float sx, sy, sz;
         transform(S.Rtf, x, y, z, sx, sy, sz);
         uint32_t v;
-        int64_t cs = 0;
         if (voxel_of(P, sx, sy, sz, v)) {
             const int64_t g = P.v_base + v;
             const uint32_t og = off[g];
@@ -120,35 +119,55 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                 cs = (int64_t)og - 2 * g;
             }
         }
-        if (c == 0) {
-            const int32_t pos = atomicAdd(&fb_count[job.pair], 1);
+    }
+    const int64_t gp = P.p_base + i;
+    // queries for the global search: one list append per wave, each lane at
+    // its rank among the wave's misses
+    const bool miss = active && c == 0;
+    const unsigned long long mmask = __ballot(miss);
+    if (mmask) {
+        const int leader = __ffsll((long long)mmask) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&fb_count[job.pair], (int32_t)__popcll(mmask));
+        base = __shfl(base, leader, kWave);
+        if (miss) {
+            const int32_t pos = base + (int32_t)__popcll(mmask & ((1ull << lane) - 1ull));
             fb_list[P.p_base + pos] = i;
             fb_key[P.p_base + pos] = ~0ull;
             nn_idx[gp] = -1 - pos;
-        } else {
-            float bd = INFINITY;
-            uint32_t bj = 0;
-            const float4* seg = qs4 + cs;
-            uint32_t k = 0;
-            for (; k + 4 <= c; k += 4) {
-                const float4 a = seg[k], b = seg[k + 1], e = seg[k + 2], f = seg[k + 3];
-                consider(a, sx, sy, sz, bd, bj);
-                consider(b, sx, sy, sz, bd, bj);
-                consider(e, sx, sy, sz, bd, bj);
-                consider(f, sx, sy, sz, bd, bj);
-            }
-            for (; k < c; ++k) consider(seg[k], sx, sy, sz, bd, bj);
-            nn_idx[gp] = (int32_t)bj;
-            nn_d2[gp] = bd;
         }
     }
-    // telemetry: candidates scanned and dilated lookups, one atomic per wave
+    if (active && c > 0) {
+        float bd = INFINITY;
+        uint32_t bj = 0;
+        const float4* seg = qs4 + cs;
+        uint32_t k = 0;
+        for (; k + 4 <= c; k += 4) {
+            const float4 a = seg[k], b = seg[k + 1], e = seg[k + 2], f = seg[k + 3];
+            consider(a, sx, sy, sz, bd, bj);
+            consider(b, sx, sy, sz, bd, bj);
+            consider(e, sx, sy, sz, bd, bj);
+            consider(f, sx, sy, sz, bd, bj);
+        }
+        for (; k < c; ++k) consider(seg[k], sx, sy, sz, bd, bj);
+        nn_idx[gp] = (int32_t)bj;
+        nn_d2[gp] = bd;
+    }
+    // telemetry without atomics: one partial per block (candidates scanned,
+    // dilated lookups), summed per pair by the solve
+    __shared__ unsigned long long red[2][BS / kWave];
     unsigned long long cw = c;
     for (int d = kWave / 2; d > 0; d >>= 1) cw += __shfl_xor(cw, d, kWave);
     const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil));
-    if ((threadIdx.x & (kWave - 1)) == 0 && (cw | dw)) {
-        atomicAdd(&ctr[2 * job.pair], cw);
-        atomicAdd(&ctr[2 * job.pair + 1], dw);
+    if (lane == 0) {
+        red[0][threadIdx.x / kWave] = cw;
+        red[1][threadIdx.x / kWave] = dw;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long sm = 0;
+        for (int w = 0; w < BS / kWave; ++w) sm += red[threadIdx.x][w];
+        ctr[2 * (int64_t)blockIdx.x + threadIdx.x] = sm;
     }
 }
 

@@ -135,9 +135,9 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
     const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
     PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
     float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags, uint32_t* __restrict__ arrive,
-    int32_t* __restrict__ fb_count, unsigned long long* __restrict__ ctr, double* __restrict__ rmse_hist,
-    int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k,
-    int K, int early_stop, double eps)
+    int32_t* __restrict__ fb_count, const unsigned long long* __restrict__ ctr,
+    const int32_t* __restrict__ nns_begin, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
+    int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
 {
     __shared__ double red[kMoments][kThreads / kWave];
     __shared__ double tot[kMoments];
@@ -150,36 +150,57 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
     double a[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) a[j] = 0.0;
+    // every load of the lane's correspondences is issued before any is used
+    int32_t jj[kMomItems];
+    float dd[kMomItems];
+    bool ok_[kMomItems];
+#pragma unroll
     for (int it = 0; it < kMomItems; ++it) {
         const int64_t i = (int64_t)job.start + threadIdx.x + it * kThreads;
-        if (i >= P.m) break;
-        const int64_t gp = P.p_base + i;
-        int32_t j = nn_idx[gp];
-        float d;
-        if (j < 0) {
-            const unsigned long long key = fb_key[P.p_base + (-1 - j)];
-            j = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
-            d = __uint_as_float((uint32_t)(key >> 32));
-            nn_idx[gp] = j;
-            nn_d2[gp] = d;
-        } else {
-            d = nn_d2[gp];
+        ok_[it] = i < P.m;
+        jj[it] = ok_[it] ? nn_idx[P.p_base + i] : 0;
+        dd[it] = ok_[it] ? nn_d2[P.p_base + i] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kMomItems; ++it) {
+        if (ok_[it] && jj[it] < 0) {
+            const int64_t gp = P.p_base + job.start + threadIdx.x + it * kThreads;
+            const unsigned long long key = fb_key[P.p_base + (-1 - jj[it])];
+            jj[it] = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
+            dd[it] = __uint_as_float((uint32_t)(key >> 32));
+            nn_idx[gp] = jj[it];
+            nn_d2[gp] = dd[it];
         }
-        if ((uint32_t)j >= (uint64_t)P.n) {   // unresolved global search (never expected): flag, do not read
+        if (ok_[it] && (uint32_t)jj[it] >= (uint64_t)P.n) {   // unresolved global search (never expected)
             atomicOr(&flags[pair], 2);
-            j = 0;
+            jj[it] = 0;
         }
-        const int64_t gq = P.q_base + j;
-        const double p[3] = {px[gp], py[gp], pz[gp]};
-        const double q[3] = {qx[gq], qy[gq], qz[gq]};
+    }
+    float pv[kMomItems][3], qv[kMomItems][3];
+#pragma unroll
+    for (int it = 0; it < kMomItems; ++it) {
+        const int64_t gp = P.p_base + job.start + threadIdx.x + it * kThreads;
+        const int64_t gq = P.q_base + (ok_[it] ? jj[it] : 0);
+        pv[it][0] = ok_[it] ? px[gp] : 0.0f;
+        pv[it][1] = ok_[it] ? py[gp] : 0.0f;
+        pv[it][2] = ok_[it] ? pz[gp] : 0.0f;
+        qv[it][0] = ok_[it] ? qx[gq] : 0.0f;
+        qv[it][1] = ok_[it] ? qy[gq] : 0.0f;
+        qv[it][2] = ok_[it] ? qz[gq] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kMomItems; ++it) {
+        if (!ok_[it]) continue;
+        const double p[3] = {pv[it][0], pv[it][1], pv[it][2]};
+        const double q[3] = {qv[it][0], qv[it][1], qv[it][2]};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             a[r] += p[r];
             a[3 + r] += q[r];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] += p[r] * q[c];
+            for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] += p[r] * q[cc];
         }
-        a[15] += (double)d;
+        a[15] += (double)dd[it];
         a[16] += 1.0;
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -222,8 +243,27 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
         for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
         tot[threadIdx.x] = sm;
     }
+    // the search's per-block counters of this pair
+    __shared__ unsigned long long cred[2][kThreads / kWave];
+    unsigned long long c0 = 0, c1 = 0;
+    for (int32_t b = nns_begin[pair] + threadIdx.x; b < nns_begin[pair + 1]; b += kThreads) {
+        c0 += ctr[2 * (int64_t)b];
+        c1 += ctr[2 * (int64_t)b + 1];
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        c0 += __shfl_xor(c0, d, kWave);
+        c1 += __shfl_xor(c1, d, kWave);
+    }
+    if (lane == 0) {
+        cred[0][w] = c0;
+        cred[1][w] = c1;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    for (int q = 1; q < kThreads / kWave; ++q) {
+        cred[0][0] += cred[0][q];
+        cred[1][0] += cred[1][q];
+    }
     arrive[pair] = 0u;
     const double m = tot[16];
     const double rmse = m > 0.0 ? sqrt(tot[15] / m) : 0.0;
@@ -242,11 +282,9 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
     rmse_hist[h] = rmse;
     fb_hist[h] = fb_count[pair];
     deg_hist[h] = ok ? 0 : 1;
-    ctr_hist[2 * h] = ctr[2 * pair];
-    ctr_hist[2 * h + 1] = ctr[2 * pair + 1];
+    ctr_hist[2 * h] = cred[0][0];
+    ctr_hist[2 * h + 1] = cred[1][0];
     fb_count[pair] = 0;
-    ctr[2 * pair] = 0;
-    ctr[2 * pair + 1] = 0;
     S.iters = k + 1;
     if (early_stop && k >= 1 && fabs(rmse - S.prev_rmse) < eps) S.done = 1;
     S.prev_rmse = rmse;
@@ -277,13 +315,14 @@ void launch_moments_solve(const PairDev* pd, const BlockJob* jobs, int njobs, co
                           const float* px, const float* py, const float* pz, const float* qx, const float* qy,
                           const float* qz, PairState* st, const unsigned long long* fb_key, int32_t* nn_idx,
                           float* nn_d2, double* part, int32_t* flags, uint32_t* arrive, int32_t* fb_count,
-                          unsigned long long* ctr, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist,
-                          unsigned long long* ctr_hist, int k, int K, int early_stop, double eps, hipStream_t s)
+                          const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist,
+                          int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K,
+                          int early_stop, double eps, hipStream_t s)
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_moments_solve, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, job_begin, px, py, pz, qx, qy, qz,
-                       st, fb_key, nn_idx, nn_d2, part, flags, arrive, fb_count, ctr, rmse_hist, fb_hist, deg_hist,
-                       ctr_hist, k, K, early_stop, eps);
+                       st, fb_key, nn_idx, nn_d2, part, flags, arrive, fb_count, ctr, nns_begin, rmse_hist, fb_hist,
+                       deg_hist, ctr_hist, k, K, early_stop, eps);
 }
 
 int moments_items_per_block() { return kThreads * kMomItems; }

@@ -304,7 +304,8 @@ struct vicp_grid {
     int32_t* nn_idx = nullptr;
     float* nn_d2 = nullptr;
     double* part = nullptr;
-    int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table
+    int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table (inside job_begin4)
+    int32_t* job_begin4 = nullptr;      // per pair, blocks of each of the four search tables
     int32_t* job_begin_mom = nullptr;   // per pair, blocks of the moments table
     BlockJob* jobs_p[4] = {nullptr, nullptr, nullptr, nullptr};
     int njobs_p[4] = {0, 0, 0, 0};
@@ -316,7 +317,7 @@ struct vicp_grid {
     double* rmse_hist = nullptr;
     int32_t* fb_hist = nullptr;
     int32_t* deg_hist = nullptr;
-    unsigned long long* ctr = nullptr;        // per pair: candidates scanned, dilated lookups
+    unsigned long long* ctr = nullptr;        // per search block: candidates scanned, dilated lookups
     unsigned long long* ctr_hist = nullptr;   // the same per iteration
     uint32_t *sh = nullptr, *soff = nullptr, *skey = nullptr, *srank = nullptr;
     float4* ps4 = nullptr;
@@ -422,7 +423,11 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     const int Kc = std::max(K, 1);
     std::vector<BlockJob> jobs[4], jm;
     std::vector<int32_t> begin, begin_m;
-    for (int k = 0; k < 4; ++k) make_jobs(m, kBlockSizes[k], jobs[k], k == 2 ? &begin : nullptr);
+    std::vector<int32_t> begin4;
+    for (int k = 0; k < 4; ++k) {
+        make_jobs(m, kBlockSizes[k], jobs[k], &begin);
+        begin4.insert(begin4.end(), begin.begin(), begin.end());
+    }
     make_jobs(m, moments_items_per_block(), jm, &begin_m);
     const int64_t nb = g->V_total + B;   // source buckets: V per pair plus one for "outside"
     const int stiles = scan_tiles(nb);
@@ -439,13 +444,13 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L, ok);
     g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L, ok);
     g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[2].size(), 1), s, L, ok);
-    g->job_begin = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
+    g->job_begin4 = (int32_t*)g->take(sizeof(int32_t) * 4 * (B + 1), s, L, ok);
     g->job_begin_mom = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
     g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L, ok);
     g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L, ok);
     g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
     g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
-    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * B, s, L, ok);
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(jobs[0].size(), 1), s, L, ok);
     g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L, ok);
     g->sh = (uint32_t*)g->take(sizeof(uint32_t) * nb, s, L, ok);
     g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
@@ -474,11 +479,11 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
                                     hipMemcpyHostToDevice, s));
     if (!jm.empty())
         VICP_HIP(hipMemcpyAsync(g->jobs_mom, jm.data(), sizeof(BlockJob) * jm.size(), hipMemcpyHostToDevice, s));
-    VICP_HIP(hipMemcpyAsync(g->job_begin, begin.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    VICP_HIP(hipMemcpyAsync(g->job_begin4, begin4.data(), sizeof(int32_t) * 4 * (B + 1), hipMemcpyHostToDevice, s));
+    g->job_begin = g->job_begin4 + 2 * (B + 1);
     VICP_HIP(hipMemcpyAsync(g->job_begin_mom, begin_m.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
     launch_fill_u32(g->arrive, 0u, B, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
-    launch_fill_u64(g->ctr, 0ull, 2 * B, s);
     VICP_HIP(hipStreamSynchronize(s));
     g->m_total = mt;
     g->K_cap = Kc;
@@ -531,7 +536,8 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
     ProfScope ps("moments_solve", s, cap);
     launch_moments_solve(g->d_pd, g->jobs_mom, g->njobs_mom, g->job_begin_mom, px, py, pz, g->qx, g->qy, g->qz, g->st,
                          g->fb_key, g->nn_idx, g->nn_d2, g->part, g->flags, g->arrive, g->fb_count, g->ctr,
-                         g->rmse_hist, g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
+                         g->job_begin4 + block_slot(g->nns_block) * (g->B + 1), g->rmse_hist, g->fb_hist,
+                         g->deg_hist, g->ctr_hist, k, K, early, eps, s);
 }
 
 // float32 grid specification of one pair from its bounding box (host code,
@@ -827,7 +833,6 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
@@ -884,7 +889,6 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     launch_fill_u32((uint32_t*)g->flags, 0u, B, s);
     launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
-    launch_fill_u64(g->ctr, 0ull, 2 * B, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid, (uintptr_t)g->sort_src,
@@ -987,7 +991,6 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     const bool cap = capturing(s);
     launch_se3(xi, g->B, g->st, g->jl6, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
@@ -1137,8 +1140,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-            launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
-            (void)hipEventRecord(a, s);
+                    (void)hipEventRecord(a, s);
             if (sorted) queue_plan(g, px, py, pz, s, true);
             queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true);
             (void)hipEventRecord(b, s);
@@ -1161,7 +1163,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
                 best_sorted = sorted != 0;
             }
         }
-    for (int fg : {128, 256, 512, 1024}) {
+    for (int fg : {64, 128, 256, 512, 1024}) {
         const float t = time_cfg(best_bs, best_sorted, fg);
         if (t < best) {
             best = t;
@@ -1175,7 +1177,6 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-    launch_fill_u64(g->ctr, 0ull, 2 * g->B, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
     return VICP_OK;

@@ -108,8 +108,9 @@ void launch_moments_solve(const PairDev* pd, const BlockJob* jobs, int njobs, co
                           const float* px, const float* py, const float* pz, const float* qx, const float* qy,
                           const float* qz, PairState* st, const unsigned long long* fb_key, int32_t* nn_idx,
                           float* nn_d2, double* part, int32_t* flags, uint32_t* arrive, int32_t* fb_count,
-                          unsigned long long* ctr, double* rmse_hist, int32_t* fb_hist, int32_t* deg_hist,
-                          unsigned long long* ctr_hist, int k, int K, int early_stop, double eps, hipStream_t s);
+                          const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist,
+                          int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K,
+                          int early_stop, double eps, hipStream_t s);
 int moments_items_per_block();
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
