@@ -87,7 +87,7 @@ def main():
     g = api.build_grid(q, P.voxel, P.rings)
     if a.autotune:
         g.dilate(P.rings)
-        g.autotune(p)
+        g.autotune(p, searches_per_plan=P.iters)
     schedule = g.schedule
 
     def step():
@@ -137,7 +137,7 @@ def main():
         prof = True
     if prof:
         for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "src_plan", "nns_local",
-                     "fallback", "moments_solve", "icp_graph"):
+                     "fallback", "moments", "solve", "icp_graph"):
             n_launch, tot = api.prof_read(name)
             if n_launch:
                 kernels[name] = {"launches_per_step": n_launch / a.steps, "avg_us": 1e3 * tot / n_launch,

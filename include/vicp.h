@@ -212,18 +212,22 @@ int vicp_grid_free(vicp_grid* g);
 
 /* Autotuning: times the result-invariant schedules of the search (see
  * vicp_get_schedule) on this grid and source at the identity pose and keeps the
- * fastest in the grid.  Results never depend on the schedule.  Synchronises the
- * stream. */
+ * fastest in the grid.  The source-bucketing pass serves `searches_per_plan`
+ * searches (1 for vicp_nns, the iteration count for vicp_register) and is
+ * charged at that rate.  Results never depend on the schedule.  Synchronises
+ * the stream. */
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz,
-                  const int64_t* m_per_pair, hipStream_t stream);
+                  const int64_t* m_per_pair, int32_t searches_per_plan, hipStream_t stream);
 
-/* The current search schedule of a grid: lanes per block of the local search
- * (64, 128, 256 or 512), whether the source is bucketed by target voxel before
- * searching (0/1), and the number of blocks of the global search.  Setting it
- * never changes a result.  INVALID_ARG for an unsupported value. */
-int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* sort_source,
-                      int32_t* fallback_grid);
-int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t sort_source, int32_t fallback_grid);
+/* The current search schedule of a grid: threads per block of the local
+ * search (128, 256 or 512), lanes cooperating on one query (1, 2, 4 or 8),
+ * whether the source is bucketed by target voxel before searching (0/1), and
+ * the number of blocks of the global search.  Setting it never changes a
+ * result.  INVALID_ARG for an unsupported value. */
+int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per_query,
+                      int32_t* sort_source, int32_t* fallback_grid);
+int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, int32_t sort_source,
+                      int32_t fallback_grid);
 
 /* Per-kernel timing with HIP events on the launch stream (0 = off).  While on,
  * every launch of a named kernel is bracketed by events; vicp_prof_read gives

@@ -99,13 +99,16 @@ class Grid:
 
     @property
     def schedule(self) -> dict:
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(b), C.byref(c)), "vicp_get_schedule")
-        return {"nns_block": a.value, "sort_source": bool(b.value), "fallback_grid": c.value}
+        a, l, b, c = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(l), C.byref(b), C.byref(c)),
+              "vicp_get_schedule")
+        return {"nns_block": a.value, "lanes_per_query": l.value, "sort_source": bool(b.value),
+                "fallback_grid": c.value}
 
-    def set_schedule(self, nns_block: int = 256, sort_source: bool = True, fallback_grid: int = 256):
-        check(lib().vicp_set_schedule(self.handle, int(nns_block), int(bool(sort_source)), int(fallback_grid)),
-              "vicp_set_schedule")
+    def set_schedule(self, nns_block: int = 256, lanes_per_query: int = 4, sort_source: bool = True,
+                     fallback_grid: int = 128):
+        check(lib().vicp_set_schedule(self.handle, int(nns_block), int(lanes_per_query), int(bool(sort_source)),
+                                      int(fallback_grid)), "vicp_set_schedule")
         return self
 
     # -- Alg. 3
@@ -203,12 +206,14 @@ class Grid:
         u = lambda t: t.cpu().numpy().view(np.uint32)
         return u(hist), u(off), u(vm)
 
-    def autotune(self, p: torch.Tensor, m_per_pair=None):
+    def autotune(self, p: torch.Tensor, m_per_pair=None, searches_per_plan: int = 1):
+        """Pick the fastest result-invariant search schedule for this source."""
         p = _soa(p, "p")
         if m_per_pair is None:
             m_per_pair = [p.shape[1]]
         px, py, pz = _ptrs(p)
-        check(lib().vicp_autotune(self.handle, px, py, pz, _i64(m_per_pair), _stream()), "vicp_autotune")
+        check(lib().vicp_autotune(self.handle, px, py, pz, _i64(m_per_pair), int(searches_per_plan), _stream()),
+              "vicp_autotune")
         return self
 
 

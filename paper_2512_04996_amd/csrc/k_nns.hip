@@ -65,7 +65,12 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
     }
 }
 
-template <int BS, bool kSorted>
+// LPQ lanes cooperate on one query: each scans every LPQ-th candidate of the
+// segment in ascending order (so it keeps the lowest index among its equal
+// distances), then the lanes combine by the lexicographic minimum of
+// (distance, index) -- the same result as one lane scanning everything, with
+// LPQ times more waves in flight to hide the load latency.
+template <int BS, int LPQ, bool kSorted>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -76,11 +81,14 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   unsigned long long* __restrict__ fb_key,
                                                   unsigned long long* __restrict__ ctr)
 {
+    static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
+    constexpr int QPB = BS / LPQ;   // queries per block
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
     if (S.done) return;   // uniform over the block
-    const int64_t t = (int64_t)job.start + threadIdx.x;
+    const int sub = threadIdx.x % LPQ;
+    const int64_t t = (int64_t)job.start + threadIdx.x / LPQ;
     const bool active = t < P.m;
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t c = 0, i = 0;
@@ -121,9 +129,9 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         }
     }
     const int64_t gp = P.p_base + i;
-    // queries for the global search: one list append per wave, each lane at
-    // its rank among the wave's misses
-    const bool miss = active && c == 0;
+    // queries for the global search: one list append per wave, each query at
+    // its rank among the wave's misses (counted on its first lane)
+    const bool miss = active && c == 0 && sub == 0;
     const unsigned long long mmask = __ballot(miss);
     if (mmask) {
         const int leader = __ffsll((long long)mmask) - 1;
@@ -137,28 +145,41 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             nn_idx[gp] = -1 - pos;
         }
     }
+    float bd = INFINITY;
+    uint32_t bj = 0xFFFFFFFFu;
     if (active && c > 0) {
-        float bd = INFINITY;
-        uint32_t bj = 0;
         const float4* seg = qs4 + cs;
-        uint32_t k = 0;
-        for (; k + 4 <= c; k += 4) {
-            const float4 a = seg[k], b = seg[k + 1], e = seg[k + 2], f = seg[k + 3];
+        uint32_t k = sub;
+        for (; k + 3 * LPQ < c; k += 4 * LPQ) {
+            const float4 a = seg[k], b = seg[k + LPQ], e = seg[k + 2 * LPQ], f = seg[k + 3 * LPQ];
             consider(a, sx, sy, sz, bd, bj);
             consider(b, sx, sy, sz, bd, bj);
             consider(e, sx, sy, sz, bd, bj);
             consider(f, sx, sy, sz, bd, bj);
         }
-        for (; k < c; ++k) consider(seg[k], sx, sy, sz, bd, bj);
+        for (; k < c; k += LPQ) consider(seg[k], sx, sy, sz, bd, bj);
+    }
+    if (LPQ > 1) {
+#pragma unroll
+        for (int d = 1; d < LPQ; d <<= 1) {
+            const float od = __shfl_xor(bd, d, kWave);
+            const uint32_t oj = (uint32_t)__shfl_xor((int)bj, d, kWave);
+            if (od < bd || (od == bd && oj < bj)) {
+                bd = od;
+                bj = oj;
+            }
+        }
+    }
+    if (active && c > 0 && sub == 0) {
         nn_idx[gp] = (int32_t)bj;
         nn_d2[gp] = bd;
     }
     // telemetry without atomics: one partial per block (candidates scanned,
     // dilated lookups), summed per pair by the solve
     __shared__ unsigned long long red[2][BS / kWave];
-    unsigned long long cw = c;
+    unsigned long long cw = (sub == 0) ? c : 0u;
     for (int d = kWave / 2; d > 0; d >>= 1) cw += __shfl_xor(cw, d, kWave);
-    const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil));
+    const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil && sub == 0));
     if (lane == 0) {
         red[0][threadIdx.x / kWave] = cw;
         red[1][threadIdx.x / kWave] = dw;
@@ -169,6 +190,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         for (int w = 0; w < BS / kWave; ++w) sm += red[threadIdx.x][w];
         ctr[2 * (int64_t)blockIdx.x + threadIdx.x] = sm;
     }
+    (void)QPB;
 }
 
 // --------------------------------------------------------------------------
@@ -348,21 +370,28 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 
 }  // namespace
 
-void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, bool sorted, const float* px,
-                      const float* py, const float* pz, const float4* ps4, const PairState* st, const uint32_t* off,
-                      const uint32_t* vm, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
-                      uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s)
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
+                      const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
+                      const uint32_t* off, const uint32_t* vm, const float4* qs4, int32_t* nn_idx, float* nn_d2,
+                      int32_t* fb_count, uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr,
+                      hipStream_t s)
 {
     if (njobs <= 0) return;
-#define VICP_NNS(BS, SORTED)                                                                                         \
-    hipLaunchKernelGGL((k_nns_local<BS, SORTED>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4, st, off,  \
-                       vm, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
+#define VICP_NNS(BS, L, SORTED)                                                                                      \
+    hipLaunchKernelGGL((k_nns_local<BS, L, SORTED>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4, st,    \
+                       off, vm, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
+#define VICP_NNS_L(BS, SORTED)                       \
+    switch (lpq) {                                   \
+    case 2: VICP_NNS(BS, 2, SORTED); break;          \
+    case 4: VICP_NNS(BS, 4, SORTED); break;          \
+    case 8: VICP_NNS(BS, 8, SORTED); break;          \
+    default: VICP_NNS(BS, 1, SORTED); break;         \
+    }
 #define VICP_NNS_BS(SORTED)                          \
     switch (block) {                                 \
-    case 64: VICP_NNS(64, SORTED); break;            \
-    case 128: VICP_NNS(128, SORTED); break;          \
-    case 512: VICP_NNS(512, SORTED); break;          \
-    default: VICP_NNS(256, SORTED); break;           \
+    case 128: VICP_NNS_L(128, SORTED); break;        \
+    case 512: VICP_NNS_L(512, SORTED); break;        \
+    default: VICP_NNS_L(256, SORTED); break;         \
     }
     if (sorted) {
         VICP_NNS_BS(true)
@@ -370,6 +399,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
         VICP_NNS_BS(false)
     }
 #undef VICP_NNS_BS
+#undef VICP_NNS_L
 #undef VICP_NNS
 }
 

@@ -125,27 +125,19 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Moments of the correspondences in float64 (sum p, sum q, sum p q^T,
 // sum d, count): each lane adds kMomItems correspondences in a fixed order,
-// the block reduces in a fixed order and writes one partial.  The last block
-// of a pair to arrive (an atomic ticket) reduces that pair's partials in
-// block order and solves Eq. 1, so the result does not depend on which block
-// arrives last.
-__global__ __launch_bounds__(kThreads) void k_moments_solve(
-    const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs, const int32_t* __restrict__ job_begin,
+// the block reduces in a fixed order and writes one partial.
+__global__ __launch_bounds__(kThreads) void k_moments(
+    const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
     const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
-    PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
-    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags, uint32_t* __restrict__ arrive,
-    int32_t* __restrict__ fb_count, const unsigned long long* __restrict__ ctr,
-    const int32_t* __restrict__ nns_begin, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
-    int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
+    const PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
+    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags)
 {
     __shared__ double red[kMoments][kThreads / kWave];
-    __shared__ double tot[kMoments];
-    __shared__ int s_last;
     const BlockJob job = jobs[blockIdx.x];
     const int pair = job.pair;
     const PairDev& P = pd[pair];
-    PairState& S = st[pair];
+    const PairState& S = st[pair];
     if (S.done) return;   // uniform over the block
     double a[kMoments];
 #pragma unroll
@@ -216,14 +208,25 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
         for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
         part[(int64_t)blockIdx.x * kMoments + threadIdx.x] = sm;
     }
-    __threadfence();
-    __syncthreads();
+}
+
+// One block per pair: the pair's moment partials and search counters in block
+// order (fixed, so the result does not depend on scheduling), then the solve
+// of Eq. 1 and the iteration bookkeeping on one lane.
+__global__ __launch_bounds__(kThreads) void k_solve(
+    const int32_t* __restrict__ job_begin, const double* __restrict__ part, PairState* __restrict__ st,
+    int32_t* __restrict__ fb_count, const unsigned long long* __restrict__ ctr,
+    const int32_t* __restrict__ nns_begin, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
+    int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
+{
+    __shared__ double red[kMoments][kThreads / kWave];
+    __shared__ double tot[kMoments];
+    __shared__ unsigned long long cred[2][kThreads / kWave];
+    const int pair = blockIdx.x;
+    PairState& S = st[pair];
+    if (S.done) return;   // uniform over the block
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int32_t b0 = job_begin[pair], b1 = job_begin[pair + 1];
-    if (threadIdx.x == 0) s_last = (atomicAdd(&arrive[pair], 1u) == (uint32_t)(b1 - b0 - 1));
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // the pair's partials in block order: lane t sums blocks b0+t, b0+t+256, ...
     double acc[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
@@ -236,15 +239,6 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
         const double sm = wave_sum(acc[j]);
         if (lane == 0) red[j][w] = sm;
     }
-    __syncthreads();
-    if (threadIdx.x < kMoments) {
-        double sm = red[threadIdx.x][0];
-#pragma unroll
-        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
-        tot[threadIdx.x] = sm;
-    }
-    // the search's per-block counters of this pair
-    __shared__ unsigned long long cred[2][kThreads / kWave];
     unsigned long long c0 = 0, c1 = 0;
     for (int32_t b = nns_begin[pair] + threadIdx.x; b < nns_begin[pair + 1]; b += kThreads) {
         c0 += ctr[2 * (int64_t)b];
@@ -259,12 +253,18 @@ __global__ __launch_bounds__(kThreads) void k_moments_solve(
         cred[1][w] = c1;
     }
     __syncthreads();
+    if (threadIdx.x < kMoments) {
+        double sm = red[threadIdx.x][0];
+#pragma unroll
+        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
+        tot[threadIdx.x] = sm;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     for (int q = 1; q < kThreads / kWave; ++q) {
         cred[0][0] += cred[0][q];
         cred[1][0] += cred[1][q];
     }
-    arrive[pair] = 0u;
     const double m = tot[16];
     const double rmse = m > 0.0 ? sqrt(tot[15] / m) : 0.0;
     double Rt[12];
@@ -311,18 +311,24 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 
 }  // namespace
 
-void launch_moments_solve(const PairDev* pd, const BlockJob* jobs, int njobs, const int32_t* job_begin,
-                          const float* px, const float* py, const float* pz, const float* qx, const float* qy,
-                          const float* qz, PairState* st, const unsigned long long* fb_key, int32_t* nn_idx,
-                          float* nn_d2, double* part, int32_t* flags, uint32_t* arrive, int32_t* fb_count,
-                          const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist,
-                          int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K,
-                          int early_stop, double eps, hipStream_t s)
+void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                    const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
+                    const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
+                    hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_moments_solve, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, job_begin, px, py, pz, qx, qy, qz,
-                       st, fb_key, nn_idx, nn_d2, part, flags, arrive, fb_count, ctr, nns_begin, rmse_hist, fb_hist,
-                       deg_hist, ctr_hist, k, K, early_stop, eps);
+    hipLaunchKernelGGL(k_moments, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, px, py, pz, qx, qy, qz, st, fb_key,
+                       nn_idx, nn_d2, part, flags);
+}
+
+void launch_solve(int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
+                  const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
+                  int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
+                  hipStream_t s)
+{
+    if (npairs <= 0) return;
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, job_begin, part, st, fb_count, ctr, nns_begin,
+                       rmse_hist, fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
 }
 
 int moments_items_per_block() { return kThreads * kMomItems; }

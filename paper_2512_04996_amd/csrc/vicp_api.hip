@@ -245,13 +245,16 @@ void make_jobs(const std::vector<int64_t>& counts, int items, std::vector<BlockJ
     }
 }
 
-constexpr int kBlockSizes[4] = {64, 128, 256, 512};
+// Work tables of source points: queries per block.
+constexpr int kNumTables = 6;
+constexpr int kQpb[kNumTables] = {16, 32, 64, 128, 256, 512};
+constexpr int kT256 = 4;   // the 256-per-block table (one lane per point kernels)
 
-int block_slot(int bs)
+int table_of(int qpb)
 {
-    for (int i = 0; i < 4; ++i)
-        if (kBlockSizes[i] == bs) return i;
-    return 2;
+    for (int i = 0; i < kNumTables; ++i)
+        if (kQpb[i] == qpb) return i;
+    return kT256;
 }
 
 }  // namespace
@@ -288,7 +291,8 @@ struct vicp_grid {
 
     // schedule choices (never change a result)
     int nns_block = 256;
-    int fb_grid = 256;
+    int nns_lpq = 4;
+    int fb_grid = 128;
     bool sort_src = true;
 
     // source workspace
@@ -304,14 +308,13 @@ struct vicp_grid {
     int32_t* nn_idx = nullptr;
     float* nn_d2 = nullptr;
     double* part = nullptr;
-    int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table (inside job_begin4)
-    int32_t* job_begin4 = nullptr;      // per pair, blocks of each of the four search tables
+    int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table (inside job_begin6)
+    int32_t* job_begin6 = nullptr;      // per pair, blocks of each source table
     int32_t* job_begin_mom = nullptr;   // per pair, blocks of the moments table
-    BlockJob* jobs_p[4] = {nullptr, nullptr, nullptr, nullptr};
-    int njobs_p[4] = {0, 0, 0, 0};
+    BlockJob* jobs_p[kNumTables] = {};
+    int njobs_p[kNumTables] = {};
     BlockJob* jobs_mom = nullptr;
     int njobs_mom = 0;
-    uint32_t* arrive = nullptr;
     int32_t* flags = nullptr;
     double* jl6 = nullptr;
     double* rmse_hist = nullptr;
@@ -421,12 +424,12 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     int64_t mt = 0;
     for (auto v : m) mt += v;
     const int Kc = std::max(K, 1);
-    std::vector<BlockJob> jobs[4], jm;
+    std::vector<BlockJob> jobs[kNumTables], jm;
     std::vector<int32_t> begin, begin_m;
-    std::vector<int32_t> begin4;
-    for (int k = 0; k < 4; ++k) {
-        make_jobs(m, kBlockSizes[k], jobs[k], &begin);
-        begin4.insert(begin4.end(), begin.begin(), begin.end());
+    std::vector<int32_t> begin6;
+    for (int k = 0; k < kNumTables; ++k) {
+        make_jobs(m, kQpb[k], jobs[k], &begin);
+        begin6.insert(begin6.end(), begin.begin(), begin.end());
     }
     make_jobs(m, moments_items_per_block(), jm, &begin_m);
     const int64_t nb = g->V_total + B;   // source buckets: V per pair plus one for "outside"
@@ -438,19 +441,19 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->staging = g->take(sizeof(double) * 12 * B, s, L, ok);
     g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
     g->flags = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
-    g->arrive = (uint32_t*)g->take(sizeof(uint32_t) * B, s, L, ok);
     g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
     g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L, ok);
     g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L, ok);
     g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L, ok);
-    g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[2].size(), 1), s, L, ok);
-    g->job_begin4 = (int32_t*)g->take(sizeof(int32_t) * 4 * (B + 1), s, L, ok);
+    g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[kT256].size(), 1), s, L, ok);
+    g->job_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * (B + 1), s, L, ok);
     g->job_begin_mom = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
     g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L, ok);
     g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L, ok);
     g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
     g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
-    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(jobs[0].size(), 1), s, L, ok);
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(jobs[0].size(), 1), s, L,
+                                          ok);
     g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L, ok);
     g->sh = (uint32_t*)g->take(sizeof(uint32_t) * nb, s, L, ok);
     g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
@@ -459,7 +462,7 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->ps4 = (float4*)g->take(sizeof(float4) * mt1, s, L, ok);
     g->s_status = (unsigned long long*)g->take(sizeof(unsigned long long) * std::max(stiles, 1), s, L, ok);
     g->s_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, L, ok);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kNumTables; ++k) {
         g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L, ok);
         g->njobs_p[k] = (int)jobs[k].size();
     }
@@ -473,16 +476,16 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
     VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kNumTables; ++k)
         if (!jobs[k].empty())
             VICP_HIP(hipMemcpyAsync(g->jobs_p[k], jobs[k].data(), sizeof(BlockJob) * jobs[k].size(),
                                     hipMemcpyHostToDevice, s));
     if (!jm.empty())
         VICP_HIP(hipMemcpyAsync(g->jobs_mom, jm.data(), sizeof(BlockJob) * jm.size(), hipMemcpyHostToDevice, s));
-    VICP_HIP(hipMemcpyAsync(g->job_begin4, begin4.data(), sizeof(int32_t) * 4 * (B + 1), hipMemcpyHostToDevice, s));
-    g->job_begin = g->job_begin4 + 2 * (B + 1);
+    VICP_HIP(hipMemcpyAsync(g->job_begin6, begin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
+                            hipMemcpyHostToDevice, s));
+    g->job_begin = g->job_begin6 + kT256 * (B + 1);
     VICP_HIP(hipMemcpyAsync(g->job_begin_mom, begin_m.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
-    launch_fill_u32(g->arrive, 0u, B, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
     VICP_HIP(hipStreamSynchronize(s));
     g->m_total = mt;
@@ -507,20 +510,21 @@ void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz,
     launch_fill_u32(g->sh, 0u, nb, s);
     launch_fill_u64(g->s_status, 0ull, scan_tiles(nb), s);
     launch_fill_u32(g->s_ticket, 0u, 4, s);
-    launch_src_bucket(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->st, g->sh, g->skey, g->srank, s);
+    launch_src_bucket(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->st, g->sh, g->skey, g->srank, s);
     launch_scan(g->sh, nb, g->soff, nullptr, g->s_status, g->s_ticket, s);
-    launch_src_place(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->skey, g->srank, g->soff, g->ps4, s);
+    launch_src_place(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->skey, g->srank, g->soff, g->ps4, s);
 }
 
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
 void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
                   hipStream_t s, bool cap)
 {
-    const int slot = block_slot(g->nns_block);
+    const int tab = table_of(g->nns_block / g->nns_lpq);
     {
         ProfScope ps("nns_local", s, cap);
-        launch_nns_local(g->d_pd, g->jobs_p[slot], g->njobs_p[slot], g->nns_block, g->sort_src, px, py, pz, g->ps4,
-                         g->st, g->off, g->vm, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr, s);
+        launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, px, py, pz,
+                         g->ps4, g->st, g->off, g->vm, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key,
+                         g->ctr, s);
     }
     {
         ProfScope ps("fallback", s, cap);
@@ -533,11 +537,15 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
                      double eps, hipStream_t s, bool cap)
 {
     queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
-    ProfScope ps("moments_solve", s, cap);
-    launch_moments_solve(g->d_pd, g->jobs_mom, g->njobs_mom, g->job_begin_mom, px, py, pz, g->qx, g->qy, g->qz, g->st,
-                         g->fb_key, g->nn_idx, g->nn_d2, g->part, g->flags, g->arrive, g->fb_count, g->ctr,
-                         g->job_begin4 + block_slot(g->nns_block) * (g->B + 1), g->rmse_hist, g->fb_hist,
-                         g->deg_hist, g->ctr_hist, k, K, early, eps, s);
+    {
+        ProfScope ps("moments", s, cap);
+        launch_moments(g->d_pd, g->jobs_mom, g->njobs_mom, px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+                       g->nn_idx, g->nn_d2, g->part, g->flags, s);
+    }
+    ProfScope ps("solve", s, cap);
+    const int tab = table_of(g->nns_block / g->nns_lpq);
+    launch_solve(g->B, g->job_begin_mom, g->part, g->st, g->fb_count, g->ctr, g->job_begin6 + tab * (g->B + 1),
+                 g->rmse_hist, g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
 }
 
 // float32 grid specification of one pair from its bounding box (host code,
@@ -834,12 +842,12 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
-    launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
+    launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap);
     {
         ProfScope ps("fb_finalize", s, cap);
-        launch_fb_finalize(g->d_pd, g->jobs_p[2], g->njobs_p[2], g->fb_key, nn_idx, nn_d2, g->flags, s);
+        launch_fb_finalize(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->fb_key, nn_idx, nn_d2, g->flags, s);
     }
     if (n_fallback) launch_copy_fb(g->fb_count, n_fallback, g->B, s);
     hipError_t e = hipGetLastError();
@@ -887,11 +895,12 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, B, s);
-    launch_check_finite(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->flags, s);
+    launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
-                                      (uintptr_t)g->nns_block, (uintptr_t)g->fb_grid, (uintptr_t)g->sort_src,
+                                      (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
+                                      (uintptr_t)g->sort_src,
                                       (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
         uint64_t eb;
         memcpy(&eb, &eps, 8);
@@ -1008,7 +1017,7 @@ int vicp_p2p_loss_fwd(const vicp_grid* gc, const float* px, const float* py, con
     const bool cap = capturing(s);
     {
         ProfScope ps("loss_terms", s, cap);
-        launch_loss_terms(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+        launch_loss_terms(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
                           g->nn_idx, nullptr, nullptr, nullptr, nullptr, g->part, g->flags, s);
     }
     launch_loss_finish(g->d_pd, g->B, g->job_begin, g->part, g->jl6, nullptr, loss, nullptr, s);
@@ -1030,7 +1039,7 @@ int vicp_p2p_loss_bwd(const vicp_grid* gc, const float* px, const float* py, con
     const bool cap = capturing(s);
     {
         ProfScope ps("loss_terms", s, cap);
-        launch_loss_terms(g->d_pd, g->jobs_p[2], g->njobs_p[2], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
+        launch_loss_terms(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
                           g->nn_idx, gloss, dpx, dpy, dpz, g->part, g->flags, s);
     }
     launch_loss_finish(g->d_pd, g->B, g->job_begin, g->part, g->jl6, gloss, nullptr, dxi, s);
@@ -1112,16 +1121,20 @@ int vicp_grid_free(vicp_grid* g)
     return VICP_OK;
 }
 
-// The search schedule (lanes per block, source bucketing on or off, blocks of
-// the global search) never changes a result; this times the candidates on
-// the caller's data at the identity pose and keeps the fastest.
+// The search schedule (threads per block, lanes per query, source bucketing
+// on or off, blocks of the global search) never changes a result; this times
+// the candidates on the caller's data at the identity pose and keeps the
+// fastest.  The bucketing pass serves `searches_per_plan` searches (1 for a
+// single search, the iteration count for a registration), so its time is
+// charged at that rate.
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
-                  hipStream_t s)
+                  int32_t searches_per_plan, hipStream_t s)
 {
     (void)hipGetLastError();   // an error left by other code is not ours to report
     int rc = check_grid(g);
     if (rc) return rc;
     if (!m_per_pair) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    if (searches_per_plan < 1) return fail(VICP_ERR_INVALID_ARG, "searches_per_plan must be >= 1");
     rc = ensure_source(g, m_per_pair, 1, s);
     if (rc) return rc;
     if (g->m_total == 0) return VICP_OK;
@@ -1133,16 +1146,12 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     hipEvent_t a, b;
     VICP_HIP(hipEventCreate(&a));
     VICP_HIP(hipEventCreate(&b));
-    auto time_cfg = [&](int bs, bool sorted, int fg) -> float {
-        g->nns_block = bs;
-        g->sort_src = sorted;
-        g->fb_grid = fg;
+    auto timed = [&](auto&& work) -> float {
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-                    (void)hipEventRecord(a, s);
-            if (sorted) queue_plan(g, px, py, pz, s, true);
-            queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true);
+            (void)hipEventRecord(a, s);
+            work();
             (void)hipEventRecord(b, s);
             (void)hipEventSynchronize(b);
             float ms = 0.0f;
@@ -1151,27 +1160,37 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
         }
         return best;
     };
-    int best_bs = 256, best_fg = 256;
+    const float plan_ms = timed([&] { queue_plan(g, px, py, pz, s, true); });
+    int best_bs = 256, best_lpq = 4, best_fg = g->fb_grid;
     bool best_sorted = true;
     float best = 1e30f;
     for (int sorted = 0; sorted < 2; ++sorted)
-        for (int bs : kBlockSizes) {
-            const float t = time_cfg(bs, sorted != 0, best_fg);
-            if (t < best) {
-                best = t;
-                best_bs = bs;
-                best_sorted = sorted != 0;
+        for (int bs : {128, 256, 512})
+            for (int lpq : {1, 2, 4, 8}) {
+                g->nns_block = bs;
+                g->nns_lpq = lpq;
+                g->sort_src = sorted != 0;
+                const float t = timed([&] { queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true); }) +
+                                (sorted ? plan_ms / (float)searches_per_plan : 0.0f);
+                if (t < best) {
+                    best = t;
+                    best_bs = bs;
+                    best_lpq = lpq;
+                    best_sorted = sorted != 0;
+                }
             }
-        }
+    g->nns_block = best_bs;
+    g->nns_lpq = best_lpq;
+    g->sort_src = best_sorted;
+    best = 1e30f;
     for (int fg : {64, 128, 256, 512, 1024}) {
-        const float t = time_cfg(best_bs, best_sorted, fg);
+        g->fb_grid = fg;
+        const float t = timed([&] { queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true); });
         if (t < best) {
             best = t;
             best_fg = fg;
         }
     }
-    g->nns_block = best_bs;
-    g->sort_src = best_sorted;
     g->fb_grid = best_fg;
     g->drop_graph();
     (void)hipEventDestroy(a);
@@ -1182,22 +1201,28 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     return VICP_OK;
 }
 
-int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* sort_source, int32_t* fallback_grid)
+int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per_query, int32_t* sort_source,
+                      int32_t* fallback_grid)
 {
     if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
     if (nns_block) *nns_block = g->nns_block;
+    if (lanes_per_query) *lanes_per_query = g->nns_lpq;
     if (sort_source) *sort_source = g->sort_src ? 1 : 0;
     if (fallback_grid) *fallback_grid = g->fb_grid;
     return VICP_OK;
 }
 
-int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t sort_source, int32_t fallback_grid)
+int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, int32_t sort_source,
+                      int32_t fallback_grid)
 {
     if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
-    if (nns_block != 64 && nns_block != 128 && nns_block != 256 && nns_block != 512)
-        return fail(VICP_ERR_INVALID_ARG, "nns_block must be 64, 128, 256 or 512");
+    if (nns_block != 128 && nns_block != 256 && nns_block != 512)
+        return fail(VICP_ERR_INVALID_ARG, "nns_block must be 128, 256 or 512");
+    if (lanes_per_query != 1 && lanes_per_query != 2 && lanes_per_query != 4 && lanes_per_query != 8)
+        return fail(VICP_ERR_INVALID_ARG, "lanes_per_query must be 1, 2, 4 or 8");
     if (fallback_grid < 1 || fallback_grid > 65536) return fail(VICP_ERR_INVALID_ARG, "fallback_grid out of range");
     g->nns_block = nns_block;
+    g->nns_lpq = lanes_per_query;
     g->sort_src = sort_source != 0;
     g->fb_grid = fallback_grid;
     g->drop_graph();

@@ -86,7 +86,7 @@ void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int 
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
 
 // search and moments
-void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, bool sorted,
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
                       const float* px, const float* py, const float* pz, const float4* ps4,
                       const PairState* st, const uint32_t* off, const uint32_t* vm, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
@@ -104,13 +104,14 @@ void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, c
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs,
                         const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2,
                         int32_t* flags, hipStream_t s);
-void launch_moments_solve(const PairDev* pd, const BlockJob* jobs, int njobs, const int32_t* job_begin,
-                          const float* px, const float* py, const float* pz, const float* qx, const float* qy,
-                          const float* qz, PairState* st, const unsigned long long* fb_key, int32_t* nn_idx,
-                          float* nn_d2, double* part, int32_t* flags, uint32_t* arrive, int32_t* fb_count,
-                          const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist,
-                          int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K,
-                          int early_stop, double eps, hipStream_t s);
+void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                    const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
+                    const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
+                    hipStream_t s);
+void launch_solve(int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
+                  const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
+                  int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
+                  hipStream_t s);
 int moments_items_per_block();
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,

@@ -282,20 +282,21 @@ def test_rebuild_equals_fresh_build():
 
 
 @pytest.mark.parametrize("sort_source", [False, True])
-@pytest.mark.parametrize("nns_block", [64, 512])
-def test_schedules_are_result_invariant(sort_source, nns_block):
+@pytest.mark.parametrize("nns_block,lpq", [(128, 1), (512, 1), (256, 2), (256, 8), (512, 4)])
+def test_schedules_are_result_invariant(sort_source, nns_block, lpq):
     P = synth.config("room_226k")
     g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
     p = dev(P.p)
     Rt = random_pose(5, 3.0, 0.08)
     ref_idx, ref_d2, ref_F, _ = oracle.nns(oracle.dilate(oracle.build_grid(P.q, P.voxel, P.rings), P.rings),
                                            P.q, P.p, Rt)
-    g.set_schedule(nns_block, sort_source, 128)
-    assert g.schedule == {"nns_block": nns_block, "sort_source": sort_source, "fallback_grid": 128}
+    g.set_schedule(nns_block, lpq, sort_source, 64)
+    assert g.schedule == {"nns_block": nns_block, "lanes_per_query": lpq, "sort_source": sort_source,
+                          "fallback_grid": 64}
     idx, d2, fb = g.nns(p, Rt)
     assert np.array_equal(idx.cpu().numpy(), ref_idx) and np.array_equal(d2.cpu().numpy(), ref_d2)
     assert int(fb.cpu()[0]) == ref_F
     r = g.register(p, 6)
-    g.set_schedule(256, True, 256)
+    g.set_schedule(256, 1, True, 256)
     r2 = g.register(p, 6)
     assert np.array_equal(r.Rt, r2.Rt) and np.array_equal(r.rmse[0], r2.rmse[0])
