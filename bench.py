@@ -221,6 +221,8 @@ def extra_figures(api, synth, torch, dev, np):
     iters = pairs[0].iters
 
     gb = api.build_grid_batched(qc, ns, vox, 3)
+    gb.dilate(3)
+    gb.autotune(pc, m_per_pair=ms_, searches_per_plan=iters)
     V_total = sum(gb.describe(b)["V"] for b in range(len(pairs)))
 
     def batched():
@@ -273,6 +275,7 @@ def extra_figures(api, synth, torch, dev, np):
     P3 = torch.from_numpy(np.stack([x.p.T for x in dpairs])).to(dev)       # (16, 40000, 3)
     g = api.build_grid_batched(qd, [x.n for x in dpairs], [x.voxel for x in dpairs], 2)
     g.dilate(2)
+    g.autotune(P3.permute(2, 0, 1).reshape(3, -1).contiguous(), m_per_pair=[x.m for x in dpairs])
     xit = torch.from_numpy(xi).to(dev)
 
     def fwd_bwd():

@@ -4,7 +4,8 @@
 // partials in a fixed order, then one lane forms the cross-covariance
 // H = sum (p - pbar)(q - qbar)^T = sum p q^T - m pbar qbar^T, takes its SVD
 // H = U S V^T by one-sided Jacobi, and sets R = V diag(1, 1, det(V U^T)) U^T,
-// t = qbar - R pbar.  When the second singular value is below 1e-12 times the
+// t = qbar - R pbar; when det H is clearly positive the same R is taken as
+// the orthogonal polar factor of H^T by a few Newton steps instead.  When the second singular value is below 1e-12 times the
 // first, the rotation is not determined and the previous pose is kept.
 #include <math.h>
 
@@ -16,7 +17,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ void svd3(double A[3][3], double U[3][3], double sig[3], double V[3][3])
+__host__ __device__ void svd3(double A[3][3], double U[3][3], double sig[3], double V[3][3])
 {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
@@ -83,14 +84,62 @@ __device__ void svd3(double A[3][3], double U[3][3], double sig[3], double V[3][
     }
 }
 
-__device__ double det3(const double M[3][3])
+__host__ __device__ double det3(const double M[3][3])
 {
     return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
            M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
 }
 
+// Orthogonal polar factor of a well-conditioned 3x3 matrix by the scaled
+// Newton iteration X <- (g X + X^{-T} / g) / 2 (Frobenius-norm scaling while
+// far from convergence).  Returns false when X becomes singular or the
+// iteration does not settle; the caller then uses the SVD.
+__host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
+{
+    double X[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X[i][j] = A[i][j];
+    bool scale = true;
+    for (int it = 0; it < 24; ++it) {
+        double C[3][3];   // cofactors: X^{-T} = C / det
+        C[0][0] = X[1][1] * X[2][2] - X[1][2] * X[2][1];
+        C[0][1] = X[1][2] * X[2][0] - X[1][0] * X[2][2];
+        C[0][2] = X[1][0] * X[2][1] - X[1][1] * X[2][0];
+        C[1][0] = X[0][2] * X[2][1] - X[0][1] * X[2][2];
+        C[1][1] = X[0][0] * X[2][2] - X[0][2] * X[2][0];
+        C[1][2] = X[0][1] * X[2][0] - X[0][0] * X[2][1];
+        C[2][0] = X[0][1] * X[1][2] - X[0][2] * X[1][1];
+        C[2][1] = X[0][2] * X[1][0] - X[0][0] * X[1][2];
+        C[2][2] = X[0][0] * X[1][1] - X[0][1] * X[1][0];
+        const double det = X[0][0] * C[0][0] + X[0][1] * C[0][1] + X[0][2] * C[0][2];
+        if (!(det > 0.0)) return false;
+        double nx = 0.0, nc = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                nx += X[i][j] * X[i][j];
+                nc += C[i][j] * C[i][j];
+            }
+        const double g = scale ? sqrt(sqrt(nc) / (det * sqrt(nx))) : 1.0;
+        const double a = 0.5 * g, b = 0.5 / (g * det);
+        double diff = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double v = a * X[i][j] + b * C[i][j];
+                diff += (v - X[i][j]) * (v - X[i][j]);
+                X[i][j] = v;
+            }
+        if (diff < 1e-4) scale = false;
+        if (diff < 1e-24) {   // quadratic convergence: the step just taken is accurate to rounding
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Q[i][j] = X[i][j];
+            return true;
+        }
+    }
+    return false;
+}
+
 // Returns false (pose untouched) when H has rank < 2.
-__device__ bool kabsch(const double* mom, double Rt[12])
+__host__ __device__ bool kabsch(const double* mom, double Rt[12])
 {
     const double m = mom[16];
     if (!(m > 0.0)) return false;
@@ -101,13 +150,25 @@ __device__ bool kabsch(const double* mom, double Rt[12])
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) H[a][b] = mom[6 + 3 * a + b] - m * pb[a] * qb[b];
-    double U[3][3], sig[3], V[3][3];
-    svd3(H, U, sig, V);
-    if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0]) return false;
-    const double d = (det3(U) * det3(V) < 0.0) ? -1.0 : 1.0;
     double R[3][3];
+    // R = V U^T is the orthogonal polar factor of H^T (H^T = V S U^T =
+    // (V U^T)(U S U^T)); when det H is clearly positive no reflection fix is
+    // needed and the Newton polar iteration gives it directly
+    double Ht[3][3], nh = 0.0;
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) R[i][j] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + d * V[i][2] * U[j][2];
+        for (int j = 0; j < 3; ++j) {
+            Ht[i][j] = H[j][i];
+            nh += H[i][j] * H[i][j];
+        }
+    const bool fast = det3(Ht) > 1e-6 * nh * sqrt(nh) && polar3(Ht, R);
+    if (!fast) {
+        double U[3][3], sig[3], V[3][3];
+        svd3(H, U, sig, V);
+        if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0]) return false;
+        const double d = (det3(U) * det3(V) < 0.0) ? -1.0 : 1.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) R[i][j] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + d * V[i][2] * U[j][2];
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Rt[3 * i + j] = R[i][j];
     for (int i = 0; i < 3; ++i) Rt[9 + i] = qb[i] - (R[i][0] * pb[0] + R[i][1] * pb[1] + R[i][2] * pb[2]);
@@ -117,11 +178,7 @@ __device__ bool kabsch(const double* mom, double Rt[12])
 constexpr int kWave = 64;
 constexpr int kMomItems = 4;   // correspondences per lane
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
 
 // Moments of the correspondences in float64 (sum p, sum q, sum p q^T,
 // sum d, count): each lane adds kMomItems correspondences in a fixed order,
@@ -142,49 +199,52 @@ __global__ __launch_bounds__(kThreads) void k_moments(
     double a[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) a[j] = 0.0;
-    // every load of the lane's correspondences is issued before any is used
+    // every load of the lane's correspondences is issued before any is used;
+    // lanes past the end read the pair's first point and add nothing
     int32_t jj[kMomItems];
     float dd[kMomItems];
     bool ok_[kMomItems];
+    int64_t gp[kMomItems];
 #pragma unroll
     for (int it = 0; it < kMomItems; ++it) {
         const int64_t i = (int64_t)job.start + threadIdx.x + it * kThreads;
         ok_[it] = i < P.m;
-        jj[it] = ok_[it] ? nn_idx[P.p_base + i] : 0;
-        dd[it] = ok_[it] ? nn_d2[P.p_base + i] : 0.0f;
+        gp[it] = P.p_base + (ok_[it] ? i : 0);
+        jj[it] = nn_idx[gp[it]];
+        dd[it] = nn_d2[gp[it]];
     }
 #pragma unroll
     for (int it = 0; it < kMomItems; ++it) {
         if (ok_[it] && jj[it] < 0) {
-            const int64_t gp = P.p_base + job.start + threadIdx.x + it * kThreads;
             const unsigned long long key = fb_key[P.p_base + (-1 - jj[it])];
             jj[it] = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
             dd[it] = __uint_as_float((uint32_t)(key >> 32));
-            nn_idx[gp] = jj[it];
-            nn_d2[gp] = dd[it];
+            nn_idx[gp[it]] = jj[it];
+            nn_d2[gp[it]] = dd[it];
         }
-        if (ok_[it] && (uint32_t)jj[it] >= (uint64_t)P.n) {   // unresolved global search (never expected)
-            atomicOr(&flags[pair], 2);
+        if ((uint32_t)jj[it] >= (uint64_t)P.n) {   // unresolved global search (never expected)
+            if (ok_[it]) atomicOr(&flags[pair], 2);
             jj[it] = 0;
         }
     }
     float pv[kMomItems][3], qv[kMomItems][3];
 #pragma unroll
     for (int it = 0; it < kMomItems; ++it) {
-        const int64_t gp = P.p_base + job.start + threadIdx.x + it * kThreads;
-        const int64_t gq = P.q_base + (ok_[it] ? jj[it] : 0);
-        pv[it][0] = ok_[it] ? px[gp] : 0.0f;
-        pv[it][1] = ok_[it] ? py[gp] : 0.0f;
-        pv[it][2] = ok_[it] ? pz[gp] : 0.0f;
-        qv[it][0] = ok_[it] ? qx[gq] : 0.0f;
-        qv[it][1] = ok_[it] ? qy[gq] : 0.0f;
-        qv[it][2] = ok_[it] ? qz[gq] : 0.0f;
+        const int64_t gq = P.q_base + jj[it];
+        pv[it][0] = px[gp[it]];
+        pv[it][1] = py[gp[it]];
+        pv[it][2] = pz[gp[it]];
+        qv[it][0] = qx[gq];
+        qv[it][1] = qy[gq];
+        qv[it][2] = qz[gq];
     }
 #pragma unroll
     for (int it = 0; it < kMomItems; ++it) {
-        if (!ok_[it]) continue;
-        const double p[3] = {pv[it][0], pv[it][1], pv[it][2]};
-        const double q[3] = {qv[it][0], qv[it][1], qv[it][2]};
+        // a select, not a product: a lane past the end adds exact zeros even
+        // if what it read is not finite
+        const bool o = ok_[it];
+        const double p[3] = {o ? (double)pv[it][0] : 0.0, o ? (double)pv[it][1] : 0.0, o ? (double)pv[it][2] : 0.0};
+        const double q[3] = {o ? (double)qv[it][0] : 0.0, o ? (double)qv[it][1] : 0.0, o ? (double)qv[it][2] : 0.0};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             a[r] += p[r];
@@ -192,8 +252,8 @@ __global__ __launch_bounds__(kThreads) void k_moments(
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] += p[r] * q[cc];
         }
-        a[15] += (double)dd[it];
-        a[16] += 1.0;
+        a[15] += o ? (double)dd[it] : 0.0;
+        a[16] += o ? 1.0 : 0.0;
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll

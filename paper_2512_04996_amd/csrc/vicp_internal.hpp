@@ -58,6 +58,34 @@ struct PairState {
 };
 
 // --------------------------------------------------------------------------
+// wave64 reductions on DPP (no LDS round trips)
+// --------------------------------------------------------------------------
+
+// x + (x moved by the DPP control CTRL within the rows of ROW_MASK; lanes
+// whose source is outside the row read 0).  Both 32-bit halves move.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, true);
+    return x + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order (an inclusive scan inside each row
+// of 16, then rows 0+1 and 2+3, then the two halves), returned to every lane.
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    x = dpp_add<0x111, 0xF>(x);   // row_shr:1
+    x = dpp_add<0x112, 0xF>(x);   // row_shr:2
+    x = dpp_add<0x114, 0xF>(x);   // row_shr:4
+    x = dpp_add<0x118, 0xF>(x);   // row_shr:8
+    x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                            __builtin_amdgcn_readlane(__double2loint(x), 63));
+}
+
+// --------------------------------------------------------------------------
 // kernel launchers (one translation unit each; all asynchronous)
 // --------------------------------------------------------------------------
 
