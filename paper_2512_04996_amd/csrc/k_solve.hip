@@ -138,10 +138,14 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
     return false;
 }
 
-// Returns false (pose untouched) when H has rank < 2.
-__host__ __device__ bool kabsch(const double* mom, double Rt[12])
+// Moments about the centre c (see k_moments); returns false (pose untouched)
+// when H has rank < 2: its second singular value is below 1e-12 of the first
+// or below the rounding floor of the one-pass sums, 1e-13 sqrt(sum|p|^2 sum|q|^2)
+// (taken about c), so that a cross-covariance made of rounding noise (e.g.
+// every correspondence on one target point) never yields a rotation.
+__host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12])
 {
-    const double m = mom[16];
+    const double m = mom[18];
     if (!(m > 0.0)) return false;
     double pb[3], qb[3], H[3][3];
     for (int a = 0; a < 3; ++a) {
@@ -150,28 +154,35 @@ __host__ __device__ bool kabsch(const double* mom, double Rt[12])
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) H[a][b] = mom[6 + 3 * a + b] - m * pb[a] * qb[b];
+    const double floor_ = 1e-13 * sqrt(mom[15] * mom[16]);
     double R[3][3];
     // R = V U^T is the orthogonal polar factor of H^T (H^T = V S U^T =
-    // (V U^T)(U S U^T)); when det H is clearly positive no reflection fix is
-    // needed and the Newton polar iteration gives it directly
+    // (V U^T)(U S U^T)); when H is far above the rounding floor and det H is
+    // clearly positive, no reflection fix is needed and the Newton polar
+    // iteration gives it directly
     double Ht[3][3], nh = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             Ht[i][j] = H[j][i];
             nh += H[i][j] * H[i][j];
         }
-    const bool fast = det3(Ht) > 1e-6 * nh * sqrt(nh) && polar3(Ht, R);
+    const double fro = sqrt(nh);
+    const bool fast = fro > 1e6 * floor_ && det3(Ht) > 1e-6 * nh * fro && polar3(Ht, R);
     if (!fast) {
         double U[3][3], sig[3], V[3][3];
         svd3(H, U, sig, V);
-        if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0]) return false;
+        if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0] || sig[1] <= floor_) return false;
         const double d = (det3(U) * det3(V) < 0.0) ? -1.0 : 1.0;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) R[i][j] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + d * V[i][2] * U[j][2];
     }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Rt[3 * i + j] = R[i][j];
-    for (int i = 0; i < 3; ++i) Rt[9 + i] = qb[i] - (R[i][0] * pb[0] + R[i][1] * pb[1] + R[i][2] * pb[2]);
+    // t = qbar - R pbar with the means taken back from c
+    for (int i = 0; i < 3; ++i) {
+        const double rp = R[i][0] * (pb[0] + c[0]) + R[i][1] * (pb[1] + c[1]) + R[i][2] * (pb[2] + c[2]);
+        Rt[9 + i] = (qb[i] + c[i]) - rp;
+    }
     return true;
 }
 
@@ -243,8 +254,11 @@ __global__ __launch_bounds__(kThreads) void k_moments(
         // a select, not a product: a lane past the end adds exact zeros even
         // if what it read is not finite
         const bool o = ok_[it];
-        const double p[3] = {o ? (double)pv[it][0] : 0.0, o ? (double)pv[it][1] : 0.0, o ? (double)pv[it][2] : 0.0};
-        const double q[3] = {o ? (double)qv[it][0] : 0.0, o ? (double)qv[it][1] : 0.0, o ? (double)qv[it][2] : 0.0};
+        const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
+        const double p[3] = {o ? (double)pv[it][0] - c0 : 0.0, o ? (double)pv[it][1] - c1 : 0.0,
+                             o ? (double)pv[it][2] - c2 : 0.0};
+        const double q[3] = {o ? (double)qv[it][0] - c0 : 0.0, o ? (double)qv[it][1] - c1 : 0.0,
+                             o ? (double)qv[it][2] - c2 : 0.0};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             a[r] += p[r];
@@ -252,8 +266,10 @@ __global__ __launch_bounds__(kThreads) void k_moments(
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] += p[r] * q[cc];
         }
-        a[15] += o ? (double)dd[it] : 0.0;
-        a[16] += o ? 1.0 : 0.0;
+        a[15] += p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        a[16] += q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        a[17] += o ? (double)dd[it] : 0.0;
+        a[18] += o ? 1.0 : 0.0;
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -274,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(
 // order (fixed, so the result does not depend on scheduling), then the solve
 // of Eq. 1 and the iteration bookkeeping on one lane.
 __global__ __launch_bounds__(kThreads) void k_solve(
-    const int32_t* __restrict__ job_begin, const double* __restrict__ part, PairState* __restrict__ st,
+    const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin, const double* __restrict__ part, PairState* __restrict__ st,
     int32_t* __restrict__ fb_count, const unsigned long long* __restrict__ ctr,
     const int32_t* __restrict__ nns_begin, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
     int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
@@ -325,11 +341,12 @@ __global__ __launch_bounds__(kThreads) void k_solve(
         cred[0][0] += cred[0][q];
         cred[1][0] += cred[1][q];
     }
-    const double m = tot[16];
-    const double rmse = m > 0.0 ? sqrt(tot[15] / m) : 0.0;
+    const double m = tot[18];
+    const double rmse = m > 0.0 ? sqrt(tot[17] / m) : 0.0;
     double Rt[12];
     for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
-    const bool ok = kabsch(tot, Rt);
+    const double cen[3] = {pd[pair].cx, pd[pair].cy, pd[pair].cz};
+    const bool ok = kabsch(tot, cen, Rt);
     if (ok) {
         for (int j = 0; j < 12; ++j) {
             S.Rt[j] = Rt[j];
@@ -381,13 +398,13 @@ void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const fl
                        nn_idx, nn_d2, part, flags);
 }
 
-void launch_solve(int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
                   const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
                   int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
                   hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, job_begin, part, st, fb_count, ctr, nns_begin,
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, ctr, nns_begin,
                        rmse_hist, fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
 }
 

@@ -396,6 +396,9 @@ void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
         d.fDx = (float)h.dims[0];
         d.fDy = (float)h.dims[1];
         d.fDz = (float)h.dims[2];
+        d.cx = h.origin[0] + 0.5f * (float)h.dims[0] * h.voxel;
+        d.cy = h.origin[1] + 0.5f * (float)h.dims[1] * h.voxel;
+        d.cz = h.origin[2] + 0.5f * (float)h.dims[2] * h.voxel;
         d.pad = g->pad;
         if ((int)g->m.size() == g->B) {
             d.p_base = pb;
@@ -544,7 +547,7 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
     }
     ProfScope ps("solve", s, cap);
     const int tab = table_of(g->nns_block / g->nns_lpq);
-    launch_solve(g->B, g->job_begin_mom, g->part, g->st, g->fb_count, g->ctr, g->job_begin6 + tab * (g->B + 1),
+    launch_solve(g->d_pd, g->B, g->job_begin_mom, g->part, g->st, g->fb_count, g->ctr, g->job_begin6 + tab * (g->B + 1),
                  g->rmse_hist, g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
 }
 

@@ -23,7 +23,8 @@ namespace vicp {
 
 constexpr uint32_t kMask = 0x80000000u;   // Mask(root) of Alg. 3
 constexpr uint32_t kNone = 0xFFFFFFFFu;   // no root (dilation state)
-constexpr int kMoments = 17;              // sum p (3), sum q (3), sum p q^T (9), sum d (1), count (1)
+constexpr int kMoments = 19;              // about the pair's centre c: sum p (3), sum q (3), sum p q^T (9),
+                                          // sum |p|^2, sum |q|^2, sum d, count
 constexpr int kGradTerms = 8;             // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
 
 // One pair: where its data lives and its grid (Sec. II.A Step 1).
@@ -36,6 +37,7 @@ struct PairDev {
     int64_t m;        // source points
     float ox, oy, oz, inv;  // origin and 1/voxel
     float fDx, fDy, fDz;    // dims as float32, for the inside test
+    float cx, cy, cz;       // centre of the grid: reference point of the moment sums
     int32_t Dx, Dy, Dz;     // dims
     int32_t pad;
 };
@@ -136,7 +138,7 @@ void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const fl
                     const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
                     const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
                     hipStream_t s);
-void launch_solve(int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
                   const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
                   int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
                   hipStream_t s);
