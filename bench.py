@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
+    ap.add_argument("--calib-copy-mib", type=float, default=0.0,
+                    help="after the run, one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -191,6 +193,15 @@ def main():
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P)
+
+    if a.calib_copy_mib > 0:
+        nel = int(a.calib_copy_mib * 2 ** 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_mib"] = a.calib_copy_mib
 
     print(json.dumps(out), flush=True)
 

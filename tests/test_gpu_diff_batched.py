@@ -1,0 +1,149 @@
+"""GPU parity of the differentiable loss and of the batched workload.
+
+Differentiable: per-pair loss, dL/dP and dL/dxi of the HIP path against the
+float64 CPU oracle on the same correspondences, and against float64 central
+finite differences (h = 1e-6, 8 random directions in the joint (P, xi) space,
+correspondences frozen).  Batched: pairs of the 64-pair workload (uneven
+sizes, both surfaces) registered in one launch sequence, each against the
+oracle run on that pair alone.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_04996_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2512_04996_amd.api import build_grid, build_grid_batched  # noqa: E402
+from paper_2512_04996_amd.autograd import p2p_loss  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rot_angle(R1, R2):
+    R1 = np.asarray(R1).reshape(3, 3)
+    R2 = np.asarray(R2).reshape(3, 3)
+    return float(np.arccos(np.clip((np.trace(R1.T @ R2) - 1) / 2, -1.0, 1.0)))
+
+
+def _diff_case(npairs=4, n=6000, seed=7):
+    rng = np.random.default_rng(seed)
+    pairs = [synth.bumpy_pair(seed=int(s), n=n, m=n, voxel=0.05, rings=2, iters=1)
+             for s in rng.integers(0, 2 ** 31 - 1, npairs)]
+    phi = rng.standard_normal((npairs, 3))
+    phi *= (rng.uniform(0, 0.1, (npairs, 1)) / np.linalg.norm(phi, axis=1, keepdims=True))
+    rho = rng.standard_normal((npairs, 3)) * 0.01
+    xi = np.concatenate([rho, phi], 1)
+    xi[0] = 0.0                                     # the identity pose is one of the cases
+    return pairs, xi
+
+
+def _gpu_loss_grad(pairs, xi, lanes=None):
+    qd = dev(np.concatenate([P.q for P in pairs], 1))
+    g = build_grid_batched(qd, [P.n for P in pairs], [P.voxel for P in pairs], 2).dilate(2)
+    if lanes is not None:
+        g.set_schedule(256, lanes, True, 128)
+    P3 = dev(np.stack([P.p.T for P in pairs])).requires_grad_(True)
+    xt = dev(xi).requires_grad_(True)
+    loss = p2p_loss(g, P3, xt)
+    loss.sum().backward()
+    return (loss.detach().cpu().numpy(), P3.grad.cpu().numpy().transpose(0, 2, 1), xt.grad.cpu().numpy())
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_p2p_matches_oracle(lanes):
+    pairs, xi = _diff_case()
+    L, dP, dxi = _gpu_loss_grad(pairs, xi, lanes)
+    for b, P in enumerate(pairs):
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
+        loss, dPo, dxio, idx = oracle.p2p(og, P.q, P.p, xi[b])
+        assert abs(L[b] - loss) <= 1e-12 * loss, b
+        # dL/dP is returned in float32
+        assert np.linalg.norm(dP[b] - dPo) <= 1e-7 * np.linalg.norm(dPo), b
+        assert np.abs(dxi[b] - dxio).max() <= 1e-10 * max(np.abs(dxio).max(), 1e-30), b
+
+
+def test_p2p_gradient_by_finite_differences():
+    pairs, xi = _diff_case(npairs=2, n=4000, seed=8)
+    L, dP, dxi = _gpu_loss_grad(pairs, xi)
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    for b, P in enumerate(pairs):
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
+        _, _, _, idx = oracle.p2p(og, P.q, P.p, xi[b])        # correspondences, frozen
+        p64 = P.p.astype(np.float64)
+        for _ in range(8):
+            u = rng.standard_normal(p64.shape)
+            w = rng.standard_normal(6)
+            nrm = math.sqrt((u * u).sum() + (w * w).sum())
+            u, w = u / nrm, w / nrm
+            fp = oracle.p2p_loss_fixed(P.q, p64 + h * u, idx, xi[b] + h * w)
+            fm = oracle.p2p_loss_fixed(P.q, p64 - h * u, idx, xi[b] - h * w)
+            fd = (fp - fm) / (2 * h)
+            an = float((dP[b].astype(np.float64) * u).sum() + (dxi[b] * w).sum())
+            scale = math.sqrt((dP[b].astype(np.float64) ** 2).sum() + (dxi[b] ** 2).sum())
+            assert abs(fd - an) <= 1e-6 * scale, (b, fd, an)
+
+
+def test_p2p_zero_at_alignment_and_backward_scale():
+    q = synth.tiny_cloud(3, 3000)
+    g = build_grid(dev(q), 0.1, 1).dilate(1)
+    P = dev(q.T.copy()[None]).requires_grad_(True)            # (1, m, 3) equal to the target
+    xi = torch.zeros((1, 6), dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = p2p_loss(g, P, xi)
+    assert float(loss) == 0.0
+    (3.0 * loss.sum()).backward()
+    assert float(P.grad.abs().max()) == 0.0 and float(xi.grad.abs().max()) == 0.0
+    # the incoming gradient scales the result
+    pairs, xv = _diff_case(npairs=1, n=3000, seed=10)
+    qd = dev(pairs[0].q)
+    g1 = build_grid(qd, pairs[0].voxel, 2).dilate(2)
+    P1 = dev(pairs[0].p.T.copy()[None]).requires_grad_(True)
+    x1 = dev(xv).requires_grad_(True)
+    l1 = p2p_loss(g1, P1, x1)
+    (2.5 * l1.sum()).backward()
+    gP, gx = P1.grad.clone(), x1.grad.clone()
+    P1.grad = None
+    x1.grad = None
+    p2p_loss(g1, P1, x1).sum().backward()
+    assert torch.allclose(gP, 2.5 * P1.grad, rtol=1e-6, atol=0)
+    assert torch.allclose(gx, 2.5 * x1.grad, rtol=1e-12, atol=0)
+
+
+def test_diff_workload_full_size_sampled():
+    dpairs, xi = synth.config("diff_16x40k")
+    L, dP, dxi = _gpu_loss_grad(dpairs, xi)
+    for b in (0, 7, 15):
+        P = dpairs[b]
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
+        loss, dPo, dxio, _ = oracle.p2p(og, P.q, P.p, xi[b])
+        assert abs(L[b] - loss) <= 1e-12 * loss
+        assert np.linalg.norm(dP[b] - dPo) <= 1e-7 * np.linalg.norm(dPo)
+        assert np.abs(dxi[b] - dxio).max() <= 1e-10 * np.abs(dxio).max()
+
+
+def test_batched_workload_sampled_pairs():
+    pairs = synth.config("batched_64")
+    sel = list(range(0, 64, 9))
+    qc = dev(np.concatenate([x.q for x in pairs], 1))
+    pc = dev(np.concatenate([x.p for x in pairs], 1))
+    gb = build_grid_batched(qc, [x.n for x in pairs], [x.voxel for x in pairs], 3).dilate(3)
+    res = gb.register(pc, 30, m_per_pair=[x.m for x in pairs], use_graph=True)
+    for b in sel:
+        P = pairs[b]
+        hist, off, vm = gb.export(b)
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 3), 3)
+        assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm), b
+        ref = oracle.register(P.q, P.p, P.voxel, 3, 30)
+        assert list(res.fallbacks[b]) == list(ref.fallbacks), b
+        assert rot_angle(res.Rt[b][:9], ref.Rt[:9]) <= 1e-5, b
+        assert np.linalg.norm(res.Rt[b][9:] - ref.Rt[9:]) <= 1e-6 * P.extent, b
