@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="room_226k")
     ap.add_argument("--graph", type=int, default=1, help="replay the ICP iterations from a hipGraph")
-    ap.add_argument("--autotune", type=int, default=1, help="pick the search schedule on this workload first")
+    ap.add_argument("--schedule", default="auto",
+                    help="search schedule: 'auto' (tuned on this workload first) or "
+                         "'BLOCK,LANES,SORT,FALLBACK_GRID', e.g. 128,2,0,64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
@@ -87,10 +89,15 @@ def main():
     # one grid object serves every step: each step refills it from the target
     # (bounding box, counts, offsets, segments), dilates it and registers
     g = api.build_grid(q, P.voxel, P.rings)
-    if a.autotune:
+    if a.schedule == "auto":
         g.dilate(P.rings)
         g.autotune(p, searches_per_plan=P.iters)
+    else:
+        bs, lpq, srt, fg = (int(x) for x in a.schedule.split(","))
+        g.set_schedule(bs, lpq, bool(srt), fg)
     schedule = g.schedule
+    nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
+                   f"{'true' if schedule['sort_source'] else 'false'}>")
 
     def step():
         g.rebuild(q)
@@ -158,9 +165,10 @@ def main():
         if os.path.exists(PROFILE_PMC):
             pmc = json.load(open(PROFILE_PMC))
             src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-            if pmc.get("kernel_source_sha256") == src_hash:
+            # counters of this very kernel variant, taken from the current source
+            if pmc.get("kernel_source_sha256") == src_hash and pmc.get("kernel") == nns_variant:
                 traffic = pmc.get("hbm_bytes_per_launch")
-        roofline = {"kernel": "k_nns_local", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        roofline = {"kernel": nns_variant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
                     "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3)}
@@ -180,6 +188,7 @@ def main():
         "config": {"workload": P.name, "n_target": P.n, "n_source": P.m, "voxel": P.voxel, "rings": P.rings,
                    "iters": P.iters, "step": "grid build + dilation + 30 ICP iterations",
                    "icp_mode": "graph" if a.graph else "eager", "schedule": schedule,
+                   "schedule_source": "autotuned" if a.schedule == "auto" else "given",
                    "kernel_timing": timing_pass},
         "icp_iters_per_s": round(K / (ms * 1e-3), 2),
         "roofline": roofline,

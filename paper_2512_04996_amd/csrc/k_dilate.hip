@@ -5,6 +5,8 @@
 // no atomics, no locks).  After the last ring every empty voxel that has a
 // root gets Mask(root) in the count word of its segment, found through the
 // offsets.  The ring state lives in a compact V-word array (root or none).
+// The same pass points the voxel's search-directory entry at its root's
+// points (start and count, with the mask bit set in the count).
 #include "vicp_internal.hpp"
 
 namespace vicp {
@@ -14,8 +16,9 @@ namespace {
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dilate_ring(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
-                                                    uint32_t* __restrict__ vm, const uint32_t* __restrict__ src,
-                                                    uint32_t* __restrict__ dst, int first, int last)
+                                                    uint32_t* __restrict__ vm, uint2* __restrict__ dir,
+                                                    const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                    int first, int last)
 {
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
@@ -45,28 +48,30 @@ __global__ __launch_bounds__(BS) void k_dilate_ring(const PairDev* __restrict__ 
         dst[g] = cur;
     } else if (cur != kNone && hist[g] == 0) {
         vm[(int64_t)off[g] + 1] = cur | kMask;
+        const int64_t gr = vb + cur;
+        dir[g] = make_uint2(off[gr] - 2u * (uint32_t)gr, hist[gr] | kMask);
     }
 }
 
 }  // namespace
 
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block, const uint32_t* hist,
-                        const uint32_t* off, uint32_t* vm, const uint32_t* src, uint32_t* dst, int first, int last,
-                        hipStream_t s)
+                        const uint32_t* off, uint32_t* vm, uint2* dir, const uint32_t* src, uint32_t* dst, int first,
+                        int last, hipStream_t s)
 {
     if (njobs <= 0) return;
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(k_dilate_ring<64>, dim3(njobs), dim3(64), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        hipLaunchKernelGGL(k_dilate_ring<64>, dim3(njobs), dim3(64), 0, s, pd, jobs, hist, off, vm, dir, src, dst, first, last);
         break;
     case 128:
-        hipLaunchKernelGGL(k_dilate_ring<128>, dim3(njobs), dim3(128), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        hipLaunchKernelGGL(k_dilate_ring<128>, dim3(njobs), dim3(128), 0, s, pd, jobs, hist, off, vm, dir, src, dst, first, last);
         break;
     case 512:
-        hipLaunchKernelGGL(k_dilate_ring<512>, dim3(njobs), dim3(512), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        hipLaunchKernelGGL(k_dilate_ring<512>, dim3(njobs), dim3(512), 0, s, pd, jobs, hist, off, vm, dir, src, dst, first, last);
         break;
     default:
-        hipLaunchKernelGGL(k_dilate_ring<256>, dim3(njobs), dim3(256), 0, s, pd, jobs, hist, off, vm, src, dst, first, last);
+        hipLaunchKernelGGL(k_dilate_ring<256>, dim3(njobs), dim3(256), 0, s, pd, jobs, hist, off, vm, dir, src, dst, first, last);
         break;
     }
 }

@@ -164,6 +164,11 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
 // plain exclusive scan of hist (!kSeg, for bucketing source points).  Single
 // pass, decoupled look-back (tile ids from a ticket so predecessors are
 // resident when a tile waits on them).
+//
+// kSeg also writes the search directory dir[g] = (off[g] - 2g, hist[g]): the
+// start of voxel g's points in the segment-ordered float4 copy of the target
+// and its count, so that a search reaches its candidates with one load (the
+// last dilation ring points empty voxels at their root's entry).
 // --------------------------------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
@@ -183,7 +188,8 @@ __device__ __forceinline__ void st_status(unsigned long long* p, unsigned long l
 template <bool kSeg>
 __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ hist, int64_t total,
                                                    uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
-                                                   unsigned long long* status, uint32_t* ticket)
+                                                   uint2* __restrict__ dir, unsigned long long* status,
+                                                   uint32_t* ticket)
 {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kThreads / kWave];
@@ -259,6 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
             if (kSeg) {
                 vm[run] = 0u;
                 vm[run + 1] = h[k];
+                dir[g] = make_uint2(run - 2u * (uint32_t)g, h[k]);
             }
             run += h[k] + (kSeg ? 2u : 0u);
             if (g == total - 1) off[total] = run;
@@ -348,15 +355,17 @@ void launch_count(const float* qx, const float* qy, const float* qz, const PairD
 
 int scan_tiles(int64_t total) { return (int)((total + kScanTile - 1) / kScanTile); }
 
-void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, unsigned long long* status,
-                 uint32_t* ticket, hipStream_t s)
+void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, uint2* dir,
+                 unsigned long long* status, uint32_t* ticket, hipStream_t s)
 {
     const int tiles = scan_tiles(total);
     if (tiles <= 0) return;
     if (vm)
-        hipLaunchKernelGGL(k_scan<true>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
+        hipLaunchKernelGGL(k_scan<true>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, dir, status,
+                           ticket);
     else
-        hipLaunchKernelGGL(k_scan<false>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, status, ticket);
+        hipLaunchKernelGGL(k_scan<false>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, dir, status,
+                           ticket);
 }
 
 void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* rank,

@@ -1,12 +1,17 @@
 // k_nns.hip -- correspondence search (Alg. 4).
 //
 // Local search: one lane per source point.  The transformed point's voxel is
-// found by the same float32 quantisation as the targets; its count word is
-// read through the offsets; a Mask(root) word redirects to the root voxel's
-// segment (indirect addressing, no replicated points).  Candidates are read
-// as float4 (x, y, z, index) from the segment-ordered copy of the target, one
-// 16-byte load each, four in flight; segments are in ascending index order,
-// so a strict "<" keeps the lowest index among equal distances.
+// found by the same float32 quantisation as the targets.  Its entry in the
+// search directory (derived from the offsets and count words, and for a
+// Mask(root) voxel from the root's, so still no replicated points) gives the
+// start and count of its candidates in one 8-byte load, where reading
+// offset -> count word -> root offset -> root count word would chain four
+// dependent loads.  Candidates are read as float4 (x, y, z, index) from the
+// segment-ordered copy of the target, a fixed number of 16-byte loads in
+// flight per lane (indices past the end are clamped to the last candidate:
+// a repeated candidate never changes a strict minimum); segments are in
+// ascending index order, so a strict "<" keeps the lowest index among equal
+// distances.
 //
 // Query order: lanes of a wave that look up different voxels diverge (the
 // wave runs the longest segment) and gather from unrelated cache lines.  The
@@ -74,8 +79,8 @@ template <int BS, int LPQ, bool kSorted>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
-                                                  const PairState* __restrict__ st, const uint32_t* __restrict__ off,
-                                                  const uint32_t* __restrict__ vm, const float4* __restrict__ qs4,
+                                                  const PairState* __restrict__ st, const uint2* __restrict__ dir,
+                                                  const float4* __restrict__ qs4,
                                                   int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
                                                   int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
@@ -112,20 +117,10 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         transform(S.Rtf, x, y, z, sx, sy, sz);
         uint32_t v;
         if (voxel_of(P, sx, sy, sz, v)) {
-            const int64_t g = P.v_base + v;
-            const uint32_t og = off[g];
-            const uint32_t h = vm[(int64_t)og + 1];
-            if (h & kMask) {
-                // dilated: follow Mask(root) to the root voxel's segment
-                const int64_t gr = P.v_base + (h & ~kMask);
-                const uint32_t ogr = off[gr];
-                c = vm[(int64_t)ogr + 1];
-                cs = (int64_t)ogr - 2 * gr;
-                dil = true;
-            } else {
-                c = h;
-                cs = (int64_t)og - 2 * g;
-            }
+            const uint2 e = dir[P.v_base + v];
+            c = e.y & ~kMask;
+            cs = e.x;
+            dil = (e.y & kMask) != 0u;
         }
     }
     const int64_t gp = P.p_base + i;
@@ -148,16 +143,18 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     float bd = INFINITY;
     uint32_t bj = 0xFFFFFFFFu;
     if (active && c > 0) {
+        // U candidates per lane per round, all loads issued before the first
+        // compare; no serial remainder
+        constexpr int U = LPQ <= 2 ? 8 : 4;
         const float4* seg = qs4 + cs;
-        uint32_t k = sub;
-        for (; k + 3 * LPQ < c; k += 4 * LPQ) {
-            const float4 a = seg[k], b = seg[k + LPQ], e = seg[k + 2 * LPQ], f = seg[k + 3 * LPQ];
-            consider(a, sx, sy, sz, bd, bj);
-            consider(b, sx, sy, sz, bd, bj);
-            consider(e, sx, sy, sz, bd, bj);
-            consider(f, sx, sy, sz, bd, bj);
+        const uint32_t last = c - 1u;
+        for (uint32_t k = sub; k < c; k += U * LPQ) {
+            float4 a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = seg[min(k + (uint32_t)(u * LPQ), last)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) consider(a[u], sx, sy, sz, bd, bj);
         }
-        for (; k < c; k += LPQ) consider(seg[k], sx, sy, sz, bd, bj);
     }
     if (LPQ > 1) {
 #pragma unroll
@@ -372,14 +369,14 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
-                      const uint32_t* off, const uint32_t* vm, const float4* qs4, int32_t* nn_idx, float* nn_d2,
+                      const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2,
                       int32_t* fb_count, uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr,
                       hipStream_t s)
 {
     if (njobs <= 0) return;
 #define VICP_NNS(BS, L, SORTED)                                                                                      \
     hipLaunchKernelGGL((k_nns_local<BS, L, SORTED>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4, st,    \
-                       off, vm, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
+                       dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
 #define VICP_NNS_L(BS, SORTED)                       \
     switch (lpq) {                                   \
     case 2: VICP_NNS(BS, 2, SORTED); break;          \

@@ -199,14 +199,28 @@ __global__ __launch_bounds__(kThreads) void k_moments(
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
     const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
     const PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
-    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags)
+    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags,
+    const int32_t* __restrict__ mom_begin, const int32_t* __restrict__ nns_begin,
+    const unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_part)
 {
     __shared__ double red[kMoments][kThreads / kWave];
+    __shared__ unsigned long long cred[2][kThreads / kWave];
     const BlockJob job = jobs[blockIdx.x];
     const int pair = job.pair;
     const PairDev& P = pd[pair];
     const PairState& S = st[pair];
     if (S.done) return;   // uniform over the block
+    // this block's share of the pair's search-block counters: the blocks of
+    // the search split evenly over the pair's moment blocks
+    const int32_t mb0 = mom_begin[pair], nmb = mom_begin[pair + 1] - mb0;
+    const int32_t nb0 = nns_begin[pair], nbn = nns_begin[pair + 1] - nb0;
+    const int32_t chunk = (nbn + nmb - 1) / nmb, r = (int32_t)blockIdx.x - mb0;
+    const int32_t c0 = nb0 + min(nbn, r * chunk), c1 = nb0 + min(nbn, (r + 1) * chunk);
+    unsigned long long k0 = 0, k1 = 0;
+    for (int32_t b = c0 + (int32_t)threadIdx.x; b < c1; b += kThreads) {
+        k0 += ctr[2 * (int64_t)b];
+        k1 += ctr[2 * (int64_t)b + 1];
+    }
     double a[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) a[j] = 0.0;
@@ -277,48 +291,68 @@ __global__ __launch_bounds__(kThreads) void k_moments(
         const double sm = wave_sum(a[j]);
         if (lane == 0) red[j][w] = sm;
     }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        k0 += __shfl_xor(k0, d, kWave);
+        k1 += __shfl_xor(k1, d, kWave);
+    }
+    if (lane == 0) {
+        cred[0][w] = k0;
+        cred[1][w] = k1;
+    }
     __syncthreads();
     if (threadIdx.x < kMoments) {
         double sm = red[threadIdx.x][0];
 #pragma unroll
         for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
         part[(int64_t)blockIdx.x * kMoments + threadIdx.x] = sm;
+    } else if (threadIdx.x < kMoments + 2) {
+        const int c = threadIdx.x - kMoments;
+        unsigned long long sm = cred[c][0];
+#pragma unroll
+        for (int q = 1; q < kThreads / kWave; ++q) sm += cred[c][q];
+        ctr_part[2 * (int64_t)blockIdx.x + c] = sm;
     }
 }
 
-// One block per pair: the pair's moment partials and search counters in block
-// order (fixed, so the result does not depend on scheduling), then the solve
-// of Eq. 1 and the iteration bookkeeping on one lane.
+// One block per pair: the pair's moment and counter partials in block order
+// (fixed, so the result does not depend on scheduling), then the solve of
+// Eq. 1 and the iteration bookkeeping on one lane.  Everything the block
+// reads is requested before the first use, so the loads overlap.
 __global__ __launch_bounds__(kThreads) void k_solve(
-    const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin, const double* __restrict__ part, PairState* __restrict__ st,
-    int32_t* __restrict__ fb_count, const unsigned long long* __restrict__ ctr,
-    const int32_t* __restrict__ nns_begin, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
-    int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
+    const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin, const double* __restrict__ part,
+    const unsigned long long* __restrict__ ctr_part, PairState* __restrict__ st, int32_t* __restrict__ fb_count,
+    double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist,
+    unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
 {
     __shared__ double red[kMoments][kThreads / kWave];
     __shared__ double tot[kMoments];
     __shared__ unsigned long long cred[2][kThreads / kWave];
     const int pair = blockIdx.x;
     PairState& S = st[pair];
-    if (S.done) return;   // uniform over the block
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int done = S.done;
     const int32_t b0 = job_begin[pair], b1 = job_begin[pair + 1];
+    double Rt[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
+    const double cen[3] = {pd[pair].cx, pd[pair].cy, pd[pair].cz};
+    const int32_t nfb = fb_count[pair];
+    const double prev = S.prev_rmse;
+    if (done) return;   // uniform over the block
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double acc[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
+    unsigned long long c0 = 0, c1 = 0;
     for (int32_t b = b0 + threadIdx.x; b < b1; b += kThreads) {
 #pragma unroll
         for (int j = 0; j < kMoments; ++j) acc[j] += part[(int64_t)b * kMoments + j];
+        c0 += ctr_part[2 * (int64_t)b];
+        c1 += ctr_part[2 * (int64_t)b + 1];
     }
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) {
         const double sm = wave_sum(acc[j]);
         if (lane == 0) red[j][w] = sm;
-    }
-    unsigned long long c0 = 0, c1 = 0;
-    for (int32_t b = nns_begin[pair] + threadIdx.x; b < nns_begin[pair + 1]; b += kThreads) {
-        c0 += ctr[2 * (int64_t)b];
-        c1 += ctr[2 * (int64_t)b + 1];
     }
     for (int d = kWave / 2; d > 0; d >>= 1) {
         c0 += __shfl_xor(c0, d, kWave);
@@ -343,9 +377,6 @@ __global__ __launch_bounds__(kThreads) void k_solve(
     }
     const double m = tot[18];
     const double rmse = m > 0.0 ? sqrt(tot[17] / m) : 0.0;
-    double Rt[12];
-    for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
-    const double cen[3] = {pd[pair].cx, pd[pair].cy, pd[pair].cz};
     const bool ok = kabsch(tot, cen, Rt);
     if (ok) {
         for (int j = 0; j < 12; ++j) {
@@ -357,13 +388,13 @@ __global__ __launch_bounds__(kThreads) void k_solve(
     }
     const int64_t h = (int64_t)pair * K + k;
     rmse_hist[h] = rmse;
-    fb_hist[h] = fb_count[pair];
+    fb_hist[h] = nfb;
     deg_hist[h] = ok ? 0 : 1;
     ctr_hist[2 * h] = cred[0][0];
     ctr_hist[2 * h + 1] = cred[1][0];
     fb_count[pair] = 0;
     S.iters = k + 1;
-    if (early_stop && k >= 1 && fabs(rmse - S.prev_rmse) < eps) S.done = 1;
+    if (early_stop && k >= 1 && fabs(rmse - prev) < eps) S.done = 1;
     S.prev_rmse = rmse;
 }
 
@@ -391,20 +422,21 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                     const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
                     const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
-                    hipStream_t s)
+                    const int32_t* mom_begin, const int32_t* nns_begin, const unsigned long long* ctr,
+                    unsigned long long* ctr_part, hipStream_t s)
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_moments, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, px, py, pz, qx, qy, qz, st, fb_key,
-                       nn_idx, nn_d2, part, flags);
+                       nn_idx, nn_d2, part, flags, mom_begin, nns_begin, ctr, ctr_part);
 }
 
-void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
-                  const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
-                  int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
-                  hipStream_t s)
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
+                  const unsigned long long* ctr_part, PairState* st, int32_t* fb_count, double* rmse_hist,
+                  int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
+                  double eps, hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, st, fb_count, ctr, nns_begin,
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, ctr_part, st, fb_count,
                        rmse_hist, fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
 }
 

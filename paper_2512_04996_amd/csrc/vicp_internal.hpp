@@ -99,7 +99,7 @@ void launch_count(const float* qx, const float* qy, const float* qz, const PairD
                   const BlockJob* jobs, int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank,
                   uint32_t* err, hipStream_t s);
 int scan_tiles(int64_t total);
-void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm,
+void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, uint2* dir,
                  unsigned long long* status, uint32_t* ticket, hipStream_t s);
 void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox,
                   const uint32_t* rank, const uint32_t* off, uint32_t* tmp, hipStream_t s);
@@ -112,13 +112,13 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
 
 // dilation
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
-                        const uint32_t* hist, const uint32_t* off, uint32_t* vm,
+                        const uint32_t* hist, const uint32_t* off, uint32_t* vm, uint2* dir,
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
 
 // search and moments
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
                       const float* px, const float* py, const float* pz, const float4* ps4,
-                      const PairState* st, const uint32_t* off, const uint32_t* vm, const float4* qs4,
+                      const PairState* st, const uint2* dir, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
                       unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
@@ -137,11 +137,12 @@ void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs,
 void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                     const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
                     const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
-                    hipStream_t s);
-void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part, PairState* st, int32_t* fb_count,
-                  const unsigned long long* ctr, const int32_t* nns_begin, double* rmse_hist, int32_t* fb_hist,
-                  int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop, double eps,
-                  hipStream_t s);
+                    const int32_t* mom_begin, const int32_t* nns_begin, const unsigned long long* ctr,
+                    unsigned long long* ctr_part, hipStream_t s);
+void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
+                  const unsigned long long* ctr_part, PairState* st, int32_t* fb_count, double* rmse_hist,
+                  int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
+                  double eps, hipStream_t s);
 int moments_items_per_block();
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
