@@ -253,6 +253,8 @@ def extra_figures(api, synth, torch, dev, np):
     qs = [torch.from_numpy(x.q).to(dev) for x in pairs]
     ps = [torch.from_numpy(x.p).to(dev) for x in pairs]
     singles = [api.build_grid(qs[b], x.voxel, 3) for b, x in enumerate(pairs)]
+    for x in singles:
+        x.set_schedule(**gb.schedule)      # the same kernels, so results can match bit for bit
 
     def looped():
         out = []

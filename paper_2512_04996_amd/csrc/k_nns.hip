@@ -18,8 +18,9 @@
 // search can therefore run over a copy of the source bucketed by target
 // voxel at the current pose (a counting sort: LDS-hashed bucket counts, a
 // plain scan, a placement pass), so neighbouring lanes share segments.
-// Results are written back by original index, so the order never changes a
-// result.
+// Within a bucket the points are then put in ascending index order (each
+// counts the smaller indices of its bucket), so the bucketed copy, and every
+// per-block sum taken over it, is the same from run to run.
 //
 // Global search (empty undilated voxel or outside the grid): the query is
 // appended to a per-pair list and an exact brute force over all targets
@@ -70,12 +71,35 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
     }
 }
 
+// The same, also keeping the best candidate's coordinates.
+__device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj,
+                                         float& bx, float& by, float& bz)
+{
+    const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
+    if (d < bd) {
+        bd = d;
+        bj = __float_as_uint(q.w);
+        bx = q.x;
+        by = q.y;
+        bz = q.z;
+    }
+}
+
 // LPQ lanes cooperate on one query: each scans every LPQ-th candidate of the
 // segment in ascending order (so it keeps the lowest index among its equal
 // distances), then the lanes combine by the lexicographic minimum of
 // (distance, index) -- the same result as one lane scanning everything, with
 // LPQ times more waves in flight to hide the load latency.
-template <int BS, int LPQ, bool kSorted>
+//
+// kMom (registration): instead of writing each correspondence, the block
+// adds the float64 moments of Eq. 1 over its locally resolved queries (sum p,
+// sum q, sum p q^T, sum |p|^2, sum |q|^2 about the grid centre, sum d, count)
+// in a fixed lane and wave order and writes one partial per block, with its
+// counters (candidates scanned, dilated lookups, queries sent to the global
+// search).  Partials and counters are stored moment-major: entry j of block
+// b at [j * gridDim.x + b].  Queries sent to the global search add their
+// moments later, once resolved.
+template <int BS, int LPQ, bool kSorted, bool kMom>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -84,10 +108,10 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
                                                   int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
-                                                  unsigned long long* __restrict__ ctr)
+                                                  unsigned long long* __restrict__ ctr, double* __restrict__ part)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
-    constexpr int QPB = BS / LPQ;   // queries per block
+    constexpr int kWaves = BS / kWave;
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
@@ -95,13 +119,13 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     const int sub = threadIdx.x % LPQ;
     const int64_t t = (int64_t)job.start + threadIdx.x / LPQ;
     const bool active = t < P.m;
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t c = 0, i = 0;
     int64_t cs = 0;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     bool dil = false;
     if (active) {
-        float x, y, z;
         if (kSorted) {
             const float4 pp = ps4[P.p_base + t];
             x = pp.x;
@@ -137,11 +161,12 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             const int32_t pos = base + (int32_t)__popcll(mmask & ((1ull << lane) - 1ull));
             fb_list[P.p_base + pos] = i;
             fb_key[P.p_base + pos] = ~0ull;
-            nn_idx[gp] = -1 - pos;
+            if (!kMom) nn_idx[gp] = -1 - pos;
         }
     }
     float bd = INFINITY;
     uint32_t bj = 0xFFFFFFFFu;
+    float bx = 0.0f, by = 0.0f, bz = 0.0f;
     if (active && c > 0) {
         // U candidates per lane per round, all loads issued before the first
         // compare; no serial remainder
@@ -153,7 +178,10 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
 #pragma unroll
             for (int u = 0; u < U; ++u) a[u] = seg[min(k + (uint32_t)(u * LPQ), last)];
 #pragma unroll
-            for (int u = 0; u < U; ++u) consider(a[u], sx, sy, sz, bd, bj);
+            for (int u = 0; u < U; ++u) {
+                if (kMom) consider(a[u], sx, sy, sz, bd, bj, bx, by, bz);
+                else consider(a[u], sx, sy, sz, bd, bj);
+            }
         }
     }
     if (LPQ > 1) {
@@ -161,33 +189,80 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         for (int d = 1; d < LPQ; d <<= 1) {
             const float od = __shfl_xor(bd, d, kWave);
             const uint32_t oj = (uint32_t)__shfl_xor((int)bj, d, kWave);
+            float ox = 0.0f, oy = 0.0f, oz = 0.0f;
+            if (kMom) {
+                ox = __shfl_xor(bx, d, kWave);
+                oy = __shfl_xor(by, d, kWave);
+                oz = __shfl_xor(bz, d, kWave);
+            }
             if (od < bd || (od == bd && oj < bj)) {
                 bd = od;
                 bj = oj;
+                if (kMom) {
+                    bx = ox;
+                    by = oy;
+                    bz = oz;
+                }
             }
         }
     }
-    if (active && c > 0 && sub == 0) {
+    const bool found = active && c > 0 && sub == 0;
+    if (!kMom && found) {
         nn_idx[gp] = (int32_t)bj;
         nn_d2[gp] = bd;
     }
-    // telemetry without atomics: one partial per block (candidates scanned,
-    // dilated lookups), summed per pair by the solve
-    __shared__ unsigned long long red[2][BS / kWave];
+    // counters without atomics: one partial per block
+    __shared__ unsigned long long red[3][kWaves];
     unsigned long long cw = (sub == 0) ? c : 0u;
     for (int d = kWave / 2; d > 0; d >>= 1) cw += __shfl_xor(cw, d, kWave);
     const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil && sub == 0));
     if (lane == 0) {
-        red[0][threadIdx.x / kWave] = cw;
-        red[1][threadIdx.x / kWave] = dw;
+        red[0][w] = cw;
+        red[1][w] = dw;
+        red[2][w] = (unsigned long long)__popcll(mmask);
     }
-    __syncthreads();
-    if (threadIdx.x < 2) {
+    if (kMom) {
+        // moments of this lane's query about the grid centre; zero for lanes
+        // that hold no resolved query (selects, so nothing else is read)
+        __shared__ double mred[kMoments][kWaves];
+        const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
+        const double p[3] = {found ? (double)x - c0 : 0.0, found ? (double)y - c1 : 0.0,
+                             found ? (double)z - c2 : 0.0};
+        const double q[3] = {found ? (double)bx - c0 : 0.0, found ? (double)by - c1 : 0.0,
+                             found ? (double)bz - c2 : 0.0};
+        double a[kMoments];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            a[r] = p[r];
+            a[3 + r] = q[r];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] = p[r] * q[cc];
+        }
+        a[15] = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        a[16] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        a[17] = found ? (double)bd : 0.0;
+        a[18] = found ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < kMoments; ++j) {
+            const double sm = wave_sum_f64(a[j]);
+            if (lane == 0) mred[j][w] = sm;
+        }
+        __syncthreads();
+        if (threadIdx.x < kMoments) {
+            double sm = mred[threadIdx.x][0];
+#pragma unroll
+            for (int q2 = 1; q2 < kWaves; ++q2) sm += mred[threadIdx.x][q2];
+            part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sm;
+        }
+    } else {
+        __syncthreads();
+    }
+    if (threadIdx.x >= 32 && threadIdx.x < 35) {
+        const int k = threadIdx.x - 32;
         unsigned long long sm = 0;
-        for (int w = 0; w < BS / kWave; ++w) sm += red[threadIdx.x][w];
-        ctr[2 * (int64_t)blockIdx.x + threadIdx.x] = sm;
+        for (int q2 = 0; q2 < kWaves; ++q2) sm += red[k][q2];
+        ctr[(int64_t)k * gridDim.x + blockIdx.x] = sm;
     }
-    (void)QPB;
 }
 
 // --------------------------------------------------------------------------
@@ -201,7 +276,8 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
                                                           const float* __restrict__ px, const float* __restrict__ py,
                                                           const float* __restrict__ pz,
                                                           const PairState* __restrict__ st, uint32_t* __restrict__ sh,
-                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank)
+                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank,
+                                                          int32_t* __restrict__ sbig)
 {
     __shared__ uint32_t key_[kBSlots];
     __shared__ uint32_t cnt_[kBSlots];
@@ -221,8 +297,8 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
         float sx, sy, sz;
         transform(st[job.pair].Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
         uint32_t v;
-        if (!voxel_of(P, sx, sy, sz, v)) v = (uint32_t)P.V;
-        key = (uint32_t)(P.v_base + job.pair) + v;   // pair p owns buckets [v_base + p, v_base + p + V]
+        if (!voxel_of(P, sx, sy, sz, v)) v = (uint32_t)(P.V + (i >> kOutShift));
+        key = (uint32_t)(P.s_base + v);
         slot = (key * 2654435761u) >> 23;
         while (true) {
             const uint32_t prev = atomicCAS(&key_[slot], kNone, key);
@@ -234,7 +310,10 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
     __syncthreads();
     for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
         const uint32_t k = key_[s];
-        if (k != kNone) base_[s] = atomicAdd(&sh[k], cnt_[s]);
+        if (k != kNone) {
+            base_[s] = atomicAdd(&sh[k], cnt_[s]);
+            if (base_[s] + cnt_[s] > kRankCap) atomicOr(&sbig[job.pair], 1);
+        }
     }
     __syncthreads();
     if (valid) {
@@ -243,20 +322,50 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
     }
 }
 
-// Places each source point at its bucket position (a global position inside
-// the pair's range, because buckets are concatenated in pair order).
+// Puts each source point's index at its bucket position (a global position
+// inside the pair's range, because buckets are concatenated in pair order);
+// the order inside a bucket is whatever the counting atomics gave.
 __global__ __launch_bounds__(256) void k_src_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
-                                                   const float* __restrict__ px, const float* __restrict__ py,
-                                                   const float* __restrict__ pz, const uint32_t* __restrict__ skey,
+                                                   const uint32_t* __restrict__ skey,
                                                    const uint32_t* __restrict__ srank,
-                                                   const uint32_t* __restrict__ soff, float4* __restrict__ ps4)
+                                                   const uint32_t* __restrict__ soff, uint32_t* __restrict__ sidx)
 {
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const int64_t i = (int64_t)job.start + threadIdx.x;
     if (i >= P.m) return;
     const int64_t gp = P.p_base + i;
-    const int64_t pos = (int64_t)soff[skey[gp]] + srank[gp];
+    sidx[(int64_t)soff[skey[gp]] + srank[gp]] = (uint32_t)i;
+}
+
+// Final position = bucket start + the number of smaller indices in the
+// bucket (ascending order within a bucket); a pair with a bucket above
+// kRankCap keeps its points in index order instead.
+__global__ __launch_bounds__(256) void k_src_rank(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                  const float* __restrict__ px, const float* __restrict__ py,
+                                                  const float* __restrict__ pz, const uint32_t* __restrict__ skey,
+                                                  const uint32_t* __restrict__ soff, const uint32_t* __restrict__ sidx,
+                                                  const int32_t* __restrict__ sbig, float4* __restrict__ ps4)
+{
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.m) return;
+    const int64_t gp = P.p_base + i;
+    int64_t pos = gp;
+    if (sbig[job.pair] == 0) {
+        const uint32_t key = skey[gp];
+        const uint32_t lo = soff[key], hi = soff[key + 1];
+        uint32_t r = 0;
+        for (uint32_t k = lo; k < hi; k += 8) {   // eight loads in flight per round
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = sidx[min(k + (uint32_t)u, hi - 1u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r += (k + (uint32_t)u < hi && v[u] < (uint32_t)i) ? 1u : 0u;
+        }
+        pos = (int64_t)lo + r;
+    }
     ps4[pos] = make_float4(px[gp], py[gp], pz[gp], __uint_as_float((uint32_t)i));
 }
 
@@ -275,10 +384,45 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
                                                          const PairState* __restrict__ st,
                                                          const int32_t* __restrict__ fb_count,
                                                          const uint32_t* __restrict__ fb_list,
-                                                         unsigned long long* __restrict__ fb_key)
+                                                         unsigned long long* __restrict__ fb_key,
+                                                         const FoldJob* __restrict__ fjobs, int nunits, int stride,
+                                                         const double* __restrict__ part,
+                                                         const unsigned long long* __restrict__ ctr,
+                                                         double* __restrict__ fpart,
+                                                         unsigned long long* __restrict__ fctr)
 {
     __shared__ int32_t s_pref[kMaxPairs + 1];
     __shared__ float tx[kFbT], ty[kFbT], tz[kFbT];
+    // registration: first fold the search blocks' moment partials, kFoldChunk
+    // blocks per unit, each summed in block order (the launch runs anyway,
+    // and the fold does not depend on the global search)
+    if (fjobs) {
+        __shared__ double fv[kMoments][kFoldChunk];
+        __shared__ unsigned long long fc[2][kFoldChunk];
+        for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+            const FoldJob fj = fjobs[u];
+            if (st[fj.pair].done) continue;   // uniform over the block
+            const int cnt = fj.b1 - fj.b0;
+            for (int e = threadIdx.x; e < (kMoments + 2) * cnt; e += kFbThreads) {
+                const int j = e / cnt, bb = e - j * cnt;
+                const int64_t b = (int64_t)fj.b0 + bb;
+                if (j < kMoments) fv[j][bb] = part[(int64_t)j * stride + b];
+                else fc[j - kMoments][bb] = ctr[(int64_t)(j - kMoments) * stride + b];
+            }
+            __syncthreads();
+            if (threadIdx.x < kMoments) {
+                double sm = 0.0;
+                for (int bb = 0; bb < cnt; ++bb) sm += fv[threadIdx.x][bb];
+                fpart[(int64_t)threadIdx.x * nunits + u] = sm;
+            } else if (threadIdx.x < kMoments + 2) {
+                const int j = threadIdx.x - kMoments;
+                unsigned long long sm = 0;
+                for (int bb = 0; bb < cnt; ++bb) sm += fc[j][bb];
+                fctr[(int64_t)j * nunits + u] = sm;
+            }
+            __syncthreads();
+        }
+    }
     // items per pair, loaded in parallel, then an in-LDS running sum
     for (int p = threadIdx.x; p < npairs; p += kFbThreads) {
         const int64_t F = fb_count[p];
@@ -367,33 +511,41 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 
 }  // namespace
 
-void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
-                      const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2,
-                      int32_t* fb_count, uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr,
+                      const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
+                      uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
                       hipStream_t s)
 {
     if (njobs <= 0) return;
-#define VICP_NNS(BS, L, SORTED)                                                                                      \
-    hipLaunchKernelGGL((k_nns_local<BS, L, SORTED>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4, st,    \
-                       dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr)
-#define VICP_NNS_L(BS, SORTED)                       \
+#define VICP_NNS(BS, L, SORTED, MOM)                                                                                 \
+    hipLaunchKernelGGL((k_nns_local<BS, L, SORTED, MOM>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4,  \
+                       st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part)
+#define VICP_NNS_L(BS, SORTED, MOM)                  \
     switch (lpq) {                                   \
-    case 2: VICP_NNS(BS, 2, SORTED); break;          \
-    case 4: VICP_NNS(BS, 4, SORTED); break;          \
-    case 8: VICP_NNS(BS, 8, SORTED); break;          \
-    default: VICP_NNS(BS, 1, SORTED); break;         \
+    case 2: VICP_NNS(BS, 2, SORTED, MOM); break;     \
+    case 4: VICP_NNS(BS, 4, SORTED, MOM); break;     \
+    case 8: VICP_NNS(BS, 8, SORTED, MOM); break;     \
+    default: VICP_NNS(BS, 1, SORTED, MOM); break;    \
     }
-#define VICP_NNS_BS(SORTED)                          \
+#define VICP_NNS_BS(SORTED, MOM)                     \
     switch (block) {                                 \
-    case 128: VICP_NNS_L(128, SORTED); break;        \
-    case 512: VICP_NNS_L(512, SORTED); break;        \
-    default: VICP_NNS_L(256, SORTED); break;         \
+    case 128: VICP_NNS_L(128, SORTED, MOM); break;   \
+    case 512: VICP_NNS_L(512, SORTED, MOM); break;   \
+    default: VICP_NNS_L(256, SORTED, MOM); break;    \
     }
-    if (sorted) {
-        VICP_NNS_BS(true)
+    if (mom) {
+        if (sorted) {
+            VICP_NNS_BS(true, true)
+        } else {
+            VICP_NNS_BS(false, true)
+        }
     } else {
-        VICP_NNS_BS(false)
+        if (sorted) {
+            VICP_NNS_BS(true, false)
+        } else {
+            VICP_NNS_BS(false, false)
+        }
     }
 #undef VICP_NNS_BS
 #undef VICP_NNS_L
@@ -402,27 +554,37 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
-                       hipStream_t s)
+                       int32_t* sbig, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank);
+    hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank,
+                       sbig);
 }
 
-void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                      const float* pz, const uint32_t* skey, const uint32_t* srank, const uint32_t* soff,
-                      float4* ps4, hipStream_t s)
+void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,
+                      const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_src_place, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, srank, soff, ps4);
+    hipLaunchKernelGGL(k_src_place, dim3(njobs), dim3(256), 0, s, pd, jobs, skey, srank, soff, sidx);
+}
+
+void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                     const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
+                     const int32_t* sbig, float4* ps4, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_rank, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, soff, sidx, sbig, ps4);
 }
 
 void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
-                     const uint32_t* fb_list, unsigned long long* fb_key, hipStream_t s)
+                     const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
+                     int stride, const double* part, const unsigned long long* ctr, double* fpart,
+                     unsigned long long* fctr, hipStream_t s)
 {
     if (npairs <= 0 || npairs > kMaxPairs) return;
     hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(kFbThreads), 0, s, pd, npairs, qx, qy, qz, px, py, pz, st,
-                       fb_count, fb_list, fb_key);
+                       fb_count, fb_list, fb_key, fjobs, nunits, stride, part, ctr, fpart, fctr);
 }
 
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs, const unsigned long long* fb_key,

@@ -1,7 +1,8 @@
 // k_solve.hip -- the closed-form rigid transform of Eq. 1 per pair, in
 // float64, and the ICP iteration bookkeeping (Sec. II.A; stop rule of
-// Sec. IV.A).  One block per pair reduces that pair's per-block moment
-// partials in a fixed order, then one lane forms the cross-covariance
+// Sec. IV.A).  One block per pair reduces the moment partials that the
+// search blocks wrote, adds the queries resolved by the global search in
+// index order (both in a fixed order), then one lane forms the cross-covariance
 // H = sum (p - pbar)(q - qbar)^T = sum p q^T - m pbar qbar^T, takes its SVD
 // H = U S V^T by one-sided Jacobi, and sets R = V diag(1, 1, det(V U^T)) U^T,
 // t = qbar - R pbar; when det H is clearly positive the same R is taken as
@@ -187,154 +188,63 @@ __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[
 }
 
 constexpr int kWave = 64;
-constexpr int kMomItems = 4;   // correspondences per lane
+constexpr int kSolveThreads = 1024;
+constexpr int kSolveWaves = kSolveThreads / kWave;
+constexpr int kFbWindow = 8 * kSolveThreads;   // queries per pass over the global-search list
 
-__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
-
-// Moments of the correspondences in float64 (sum p, sum q, sum p q^T,
-// sum d, count): each lane adds kMomItems correspondences in a fixed order,
-// the block reduces in a fixed order and writes one partial.
-__global__ __launch_bounds__(kThreads) void k_moments(
-    const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
-    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
-    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
-    const PairState* __restrict__ st, const unsigned long long* __restrict__ fb_key, int32_t* __restrict__ nn_idx,
-    float* __restrict__ nn_d2, double* __restrict__ part, int32_t* __restrict__ flags,
-    const int32_t* __restrict__ mom_begin, const int32_t* __restrict__ nns_begin,
-    const unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_part)
+// Adds the moments of one correspondence (p, q about the centre c, squared
+// distance d) to a[].
+__device__ __forceinline__ void add_moments(double* a, float px, float py, float pz, float qx, float qy, float qz,
+                                            float d, double c0, double c1, double c2)
 {
-    __shared__ double red[kMoments][kThreads / kWave];
-    __shared__ unsigned long long cred[2][kThreads / kWave];
-    const BlockJob job = jobs[blockIdx.x];
-    const int pair = job.pair;
-    const PairDev& P = pd[pair];
-    const PairState& S = st[pair];
-    if (S.done) return;   // uniform over the block
-    // this block's share of the pair's search-block counters: the blocks of
-    // the search split evenly over the pair's moment blocks
-    const int32_t mb0 = mom_begin[pair], nmb = mom_begin[pair + 1] - mb0;
-    const int32_t nb0 = nns_begin[pair], nbn = nns_begin[pair + 1] - nb0;
-    const int32_t chunk = (nbn + nmb - 1) / nmb, r = (int32_t)blockIdx.x - mb0;
-    const int32_t c0 = nb0 + min(nbn, r * chunk), c1 = nb0 + min(nbn, (r + 1) * chunk);
-    unsigned long long k0 = 0, k1 = 0;
-    for (int32_t b = c0 + (int32_t)threadIdx.x; b < c1; b += kThreads) {
-        k0 += ctr[2 * (int64_t)b];
-        k1 += ctr[2 * (int64_t)b + 1];
+    const double p[3] = {(double)px - c0, (double)py - c1, (double)pz - c2};
+    const double q[3] = {(double)qx - c0, (double)qy - c1, (double)qz - c2};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        a[r] += p[r];
+        a[3 + r] += q[r];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] += p[r] * q[cc];
     }
-    double a[kMoments];
-#pragma unroll
-    for (int j = 0; j < kMoments; ++j) a[j] = 0.0;
-    // every load of the lane's correspondences is issued before any is used;
-    // lanes past the end read the pair's first point and add nothing
-    int32_t jj[kMomItems];
-    float dd[kMomItems];
-    bool ok_[kMomItems];
-    int64_t gp[kMomItems];
-#pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        const int64_t i = (int64_t)job.start + threadIdx.x + it * kThreads;
-        ok_[it] = i < P.m;
-        gp[it] = P.p_base + (ok_[it] ? i : 0);
-        jj[it] = nn_idx[gp[it]];
-        dd[it] = nn_d2[gp[it]];
-    }
-#pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        if (ok_[it] && jj[it] < 0) {
-            const unsigned long long key = fb_key[P.p_base + (-1 - jj[it])];
-            jj[it] = (int32_t)(uint32_t)(key & 0xFFFFFFFFull);
-            dd[it] = __uint_as_float((uint32_t)(key >> 32));
-            nn_idx[gp[it]] = jj[it];
-            nn_d2[gp[it]] = dd[it];
-        }
-        if ((uint32_t)jj[it] >= (uint64_t)P.n) {   // unresolved global search (never expected)
-            if (ok_[it]) atomicOr(&flags[pair], 2);
-            jj[it] = 0;
-        }
-    }
-    float pv[kMomItems][3], qv[kMomItems][3];
-#pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        const int64_t gq = P.q_base + jj[it];
-        pv[it][0] = px[gp[it]];
-        pv[it][1] = py[gp[it]];
-        pv[it][2] = pz[gp[it]];
-        qv[it][0] = qx[gq];
-        qv[it][1] = qy[gq];
-        qv[it][2] = qz[gq];
-    }
-#pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        // a select, not a product: a lane past the end adds exact zeros even
-        // if what it read is not finite
-        const bool o = ok_[it];
-        const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
-        const double p[3] = {o ? (double)pv[it][0] - c0 : 0.0, o ? (double)pv[it][1] - c1 : 0.0,
-                             o ? (double)pv[it][2] - c2 : 0.0};
-        const double q[3] = {o ? (double)qv[it][0] - c0 : 0.0, o ? (double)qv[it][1] - c1 : 0.0,
-                             o ? (double)qv[it][2] - c2 : 0.0};
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            a[r] += p[r];
-            a[3 + r] += q[r];
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] += p[r] * q[cc];
-        }
-        a[15] += p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-        a[16] += q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-        a[17] += o ? (double)dd[it] : 0.0;
-        a[18] += o ? 1.0 : 0.0;
-    }
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-    for (int j = 0; j < kMoments; ++j) {
-        const double sm = wave_sum(a[j]);
-        if (lane == 0) red[j][w] = sm;
-    }
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        k0 += __shfl_xor(k0, d, kWave);
-        k1 += __shfl_xor(k1, d, kWave);
-    }
-    if (lane == 0) {
-        cred[0][w] = k0;
-        cred[1][w] = k1;
-    }
-    __syncthreads();
-    if (threadIdx.x < kMoments) {
-        double sm = red[threadIdx.x][0];
-#pragma unroll
-        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
-        part[(int64_t)blockIdx.x * kMoments + threadIdx.x] = sm;
-    } else if (threadIdx.x < kMoments + 2) {
-        const int c = threadIdx.x - kMoments;
-        unsigned long long sm = cred[c][0];
-#pragma unroll
-        for (int q = 1; q < kThreads / kWave; ++q) sm += cred[c][q];
-        ctr_part[2 * (int64_t)blockIdx.x + c] = sm;
-    }
+    a[15] += p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    a[16] += q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+    a[17] += (double)d;
+    a[18] += 1.0;
 }
 
-// One block per pair: the pair's moment and counter partials in block order
-// (fixed, so the result does not depend on scheduling), then the solve of
-// Eq. 1 and the iteration bookkeeping on one lane.  Everything the block
-// reads is requested before the first use, so the loads overlap.
-__global__ __launch_bounds__(kThreads) void k_solve(
-    const PairDev* __restrict__ pd, const int32_t* __restrict__ job_begin, const double* __restrict__ part,
-    const unsigned long long* __restrict__ ctr_part, PairState* __restrict__ st, int32_t* __restrict__ fb_count,
-    double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist, int32_t* __restrict__ deg_hist,
-    unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop, double eps)
+// One block per pair.  (1) The pair's folded partials of its search blocks
+// (moment-major, stride = number of fold units), each thread a fixed subset
+// in unit order.  (2) Queries resolved by the global search: their
+// list is in arbitrary order, so it is replayed in windows of kFbWindow
+// source indices through an LDS bitmap, and each thread adds the
+// correspondences of its own 8 indices per window in index order.  (3) A
+// fixed-order block reduction, then the solve of Eq. 1 and the iteration
+// bookkeeping on one lane.  Everything the block reads early is requested
+// before its first use, so the loads overlap.
+__global__ __launch_bounds__(kSolveThreads) void k_solve(
+    const PairDev* __restrict__ pd, const int32_t* __restrict__ fold_begin, int32_t nunits,
+    const double* __restrict__ fpart, const unsigned long long* __restrict__ fctr, PairState* __restrict__ st,
+    int32_t* __restrict__ fb_count, const uint32_t* __restrict__ fb_list, const unsigned long long* __restrict__ fb_key,
+    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+    int32_t* __restrict__ flags, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
+    int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop,
+    double eps)
 {
-    __shared__ double red[kMoments][kThreads / kWave];
+    __shared__ double red[kMoments][kSolveWaves];
     __shared__ double tot[kMoments];
-    __shared__ unsigned long long cred[2][kThreads / kWave];
+    __shared__ unsigned long long cred[2][kSolveWaves];
+    __shared__ uint32_t wbits[kFbWindow / 32];
+    __shared__ uint32_t wslot[kFbWindow];
     const int pair = blockIdx.x;
     PairState& S = st[pair];
+    const PairDev& P = pd[pair];
     const int done = S.done;
-    const int32_t b0 = job_begin[pair], b1 = job_begin[pair + 1];
+    const int32_t u0 = fold_begin[pair], u1 = fold_begin[pair + 1];
     double Rt[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
-    const double cen[3] = {pd[pair].cx, pd[pair].cy, pd[pair].cz};
+    const double cen[3] = {P.cx, P.cy, P.cz};
     const int32_t nfb = fb_count[pair];
     const double prev = S.prev_rmse;
     if (done) return;   // uniform over the block
@@ -343,15 +253,45 @@ __global__ __launch_bounds__(kThreads) void k_solve(
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
     unsigned long long c0 = 0, c1 = 0;
-    for (int32_t b = b0 + threadIdx.x; b < b1; b += kThreads) {
+    for (int32_t u = u0 + threadIdx.x; u < u1; u += kSolveThreads) {
 #pragma unroll
-        for (int j = 0; j < kMoments; ++j) acc[j] += part[(int64_t)b * kMoments + j];
-        c0 += ctr_part[2 * (int64_t)b];
-        c1 += ctr_part[2 * (int64_t)b + 1];
+        for (int j = 0; j < kMoments; ++j) acc[j] += fpart[(int64_t)j * nunits + u];
+        c0 += fctr[u];
+        c1 += fctr[(int64_t)nunits + u];
+    }
+    if (nfb > 0) {
+        for (int64_t w0 = 0; w0 < P.m; w0 += kFbWindow) {
+            for (int e = threadIdx.x; e < kFbWindow / 32; e += kSolveThreads) wbits[e] = 0u;
+            __syncthreads();
+            for (int32_t e = threadIdx.x; e < nfb; e += kSolveThreads) {
+                const int64_t r = (int64_t)fb_list[P.p_base + e] - w0;
+                if (r >= 0 && r < kFbWindow) {
+                    atomicOr(&wbits[r >> 5], 1u << (r & 31));
+                    wslot[r] = (uint32_t)e;
+                }
+            }
+            __syncthreads();
+            uint32_t bits = (wbits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 8)) & 0xFFu;
+            while (bits) {
+                const int u = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                const int r = 8 * (int)threadIdx.x + u;
+                const unsigned long long key = fb_key[P.p_base + wslot[r]];
+                const uint32_t j = (uint32_t)(key & 0xFFFFFFFFull);
+                if (j >= (uint64_t)P.n) {   // unresolved global search (never expected)
+                    atomicOr(&flags[pair], 2);
+                    continue;
+                }
+                const int64_t gp = P.p_base + w0 + r, gq = P.q_base + j;
+                add_moments(acc, px[gp], py[gp], pz[gp], qx[gq], qy[gq], qz[gq],
+                            __uint_as_float((uint32_t)(key >> 32)), cen[0], cen[1], cen[2]);
+            }
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) {
-        const double sm = wave_sum(acc[j]);
+        const double sm = wave_sum_f64(acc[j]);
         if (lane == 0) red[j][w] = sm;
     }
     for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -366,12 +306,12 @@ __global__ __launch_bounds__(kThreads) void k_solve(
     if (threadIdx.x < kMoments) {
         double sm = red[threadIdx.x][0];
 #pragma unroll
-        for (int q = 1; q < kThreads / kWave; ++q) sm += red[threadIdx.x][q];
+        for (int q = 1; q < kSolveWaves; ++q) sm += red[threadIdx.x][q];
         tot[threadIdx.x] = sm;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int q = 1; q < kThreads / kWave; ++q) {
+    for (int q = 1; q < kSolveWaves; ++q) {
         cred[0][0] += cred[0][q];
         cred[1][0] += cred[1][q];
     }
@@ -419,28 +359,18 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 
 }  // namespace
 
-void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                    const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
-                    const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
-                    const int32_t* mom_begin, const int32_t* nns_begin, const unsigned long long* ctr,
-                    unsigned long long* ctr_part, hipStream_t s)
-{
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_moments, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, px, py, pz, qx, qy, qz, st, fb_key,
-                       nn_idx, nn_d2, part, flags, mom_begin, nns_begin, ctr, ctr_part);
-}
-
-void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
-                  const unsigned long long* ctr_part, PairState* st, int32_t* fb_count, double* rmse_hist,
+void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int32_t nunits, const double* fpart,
+                  const unsigned long long* fctr, PairState* st, int32_t* fb_count, const uint32_t* fb_list,
+                  const unsigned long long* fb_key, const float* px, const float* py, const float* pz,
+                  const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
                   double eps, hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kThreads), 0, s, pd, job_begin, part, ctr_part, st, fb_count,
-                       rmse_hist, fb_hist, deg_hist, ctr_hist, k, K, early_stop, eps);
+    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kSolveThreads), 0, s, pd, fold_begin, nunits, fpart, fctr, st,
+                       fb_count, fb_list, fb_key, px, py, pz, qx, qy, qz, flags, rmse_hist, fb_hist, deg_hist,
+                       ctr_hist, k, K, early_stop, eps);
 }
-
-int moments_items_per_block() { return kThreads * kMomItems; }
 
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)
 {

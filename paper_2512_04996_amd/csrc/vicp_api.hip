@@ -302,6 +302,14 @@ struct vicp_grid {
     int64_t ws_V = -1;
     int K_cap = 0;
     PairState* st = nullptr;
+    // every per-registration output (state, histories, counters, flags) lives
+    // in one device block, read back with one copy into pinned host memory
+    char* res = nullptr;
+    size_t res_bytes = 0;
+    size_t o_rmse = 0, o_ctr = 0, o_fb = 0, o_deg = 0, o_flags = 0;
+    void* h_res = nullptr;
+    size_t h_res_cap = 0;
+    uint32_t* h_box = nullptr;   // pinned: the bounding boxes read back by each build
     void* staging = nullptr;
     int32_t* fb_count = nullptr;
     uint32_t* fb_list = nullptr;
@@ -311,20 +319,23 @@ struct vicp_grid {
     double* part = nullptr;
     int32_t* job_begin = nullptr;       // per pair, blocks of the 256-point table (inside job_begin6)
     int32_t* job_begin6 = nullptr;      // per pair, blocks of each source table
-    int32_t* job_begin_mom = nullptr;   // per pair, blocks of the moments table
     BlockJob* jobs_p[kNumTables] = {};
     int njobs_p[kNumTables] = {};
-    BlockJob* jobs_mom = nullptr;
-    int njobs_mom = 0;
+    FoldJob* fjobs[kNumTables] = {};    // fold units of each search table
+    int nfjobs[kNumTables] = {};
+    int32_t* fold_begin6 = nullptr;     // per table and pair, first fold unit
+    double* fpart = nullptr;            // per fold unit: folded moment partials
+    unsigned long long* fctr = nullptr; // per fold unit: folded counters
     int32_t* flags = nullptr;
     double* jl6 = nullptr;
     double* rmse_hist = nullptr;
     int32_t* fb_hist = nullptr;
     int32_t* deg_hist = nullptr;
-    unsigned long long* ctr = nullptr;        // per search block: candidates scanned, dilated lookups
-    unsigned long long* ctr_hist = nullptr;   // the same per iteration
-    unsigned long long* ctr_part = nullptr;   // the same summed per moments block
-    uint32_t *sh = nullptr, *soff = nullptr, *skey = nullptr, *srank = nullptr;
+    unsigned long long* ctr = nullptr;        // per search block: candidates, dilated lookups, global searches
+    unsigned long long* ctr_hist = nullptr;   // candidates and dilated lookups per pair and iteration
+    double* npart = nullptr;                  // per search block: the moment partials (registration)
+    uint32_t *sh = nullptr, *soff = nullptr, *skey = nullptr, *srank = nullptr, *sidx = nullptr;
+    int32_t* sbig = nullptr;   // per pair: a bucket exceeded kRankCap (index order)
     float4* ps4 = nullptr;
     unsigned long long* s_status = nullptr;
     uint32_t* s_ticket = nullptr;
@@ -380,7 +391,7 @@ bool capturing(hipStream_t s)
 void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
 {
     pd.assign(g->B, PairDev{});
-    int64_t pb = 0;
+    int64_t pb = 0, sb = 0;
     for (int p = 0; p < g->B; ++p) {
         const PairHost& h = g->pairs[p];
         PairDev& d = pd[p];
@@ -405,9 +416,20 @@ void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
         if ((int)g->m.size() == g->B) {
             d.p_base = pb;
             d.m = g->m[p];
+            d.s_base = sb;
             pb += g->m[p];
+            sb += h.V + (g->m[p] + kOutChunk - 1) / kOutChunk;
         }
     }
+}
+
+// Source buckets of a layout: per pair, V voxel buckets and the "outside"
+// chunks.
+int64_t source_buckets(const vicp_grid* g, const std::vector<int64_t>& m)
+{
+    int64_t nb = 0;
+    for (int p = 0; p < g->B; ++p) nb += g->pairs[p].V + (m[p] + kOutChunk - 1) / kOutChunk;
+    return nb;
 }
 
 // (Re)build the source-side device state for a per-pair source layout.
@@ -429,52 +451,85 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     int64_t mt = 0;
     for (auto v : m) mt += v;
     const int Kc = std::max(K, 1);
-    std::vector<BlockJob> jobs[kNumTables], jm;
-    std::vector<int32_t> begin, begin_m;
+    std::vector<BlockJob> jobs[kNumTables];
+    std::vector<int32_t> begin;
     std::vector<int32_t> begin6;
+    std::vector<FoldJob> folds[kNumTables];
+    std::vector<int32_t> fbegin6;
     for (int k = 0; k < kNumTables; ++k) {
         make_jobs(m, kQpb[k], jobs[k], &begin);
         begin6.insert(begin6.end(), begin.begin(), begin.end());
+        fbegin6.push_back(0);
+        for (int p = 0; p < B; ++p) {
+            for (int32_t b = begin[p]; b < begin[p + 1]; b += kFoldChunk)
+                folds[k].push_back({p, b, std::min(b + kFoldChunk, begin[p + 1]), 0});
+            fbegin6.push_back((int32_t)folds[k].size());
+        }
     }
-    make_jobs(m, moments_items_per_block(), jm, &begin_m);
-    const int64_t nb = g->V_total + B;   // source buckets: V per pair plus one for "outside"
+    const int64_t nb = source_buckets(g, m);
     const int stiles = scan_tiles(nb);
     auto& L = g->ws_bufs;
     bool ok = true;
     const size_t mt1 = (size_t)std::max<int64_t>(mt, 1);
-    g->st = (PairState*)g->take(sizeof(PairState) * B, s, L, ok);
+    {
+        auto a8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
+        const size_t bk = (size_t)B * Kc;
+        g->o_rmse = a8(sizeof(PairState) * B);
+        g->o_ctr = g->o_rmse + sizeof(double) * bk;
+        g->o_fb = g->o_ctr + sizeof(unsigned long long) * 2 * bk;
+        g->o_deg = g->o_fb + sizeof(int32_t) * bk;
+        g->o_flags = g->o_deg + sizeof(int32_t) * bk;
+        g->res_bytes = a8(g->o_flags + sizeof(int32_t) * B);
+        g->res = (char*)g->take(g->res_bytes, s, L, ok);
+        if (g->res) {
+            g->st = (PairState*)g->res;
+            g->rmse_hist = (double*)(g->res + g->o_rmse);
+            g->ctr_hist = (unsigned long long*)(g->res + g->o_ctr);
+            g->fb_hist = (int32_t*)(g->res + g->o_fb);
+            g->deg_hist = (int32_t*)(g->res + g->o_deg);
+            g->flags = (int32_t*)(g->res + g->o_flags);
+        }
+        if (g->h_res_cap < g->res_bytes) {
+            if (g->h_res) (void)hipHostFree(g->h_res);
+            g->h_res = nullptr;
+            g->h_res_cap = 0;
+            if (hipHostMalloc(&g->h_res, g->res_bytes, hipHostMallocDefault) == hipSuccess)
+                g->h_res_cap = g->res_bytes;
+            else
+                ok = false;
+        }
+    }
     g->staging = g->take(sizeof(double) * 12 * B, s, L, ok);
     g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
-    g->flags = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
     g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
     g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L, ok);
     g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L, ok);
     g->nn_d2 = (float*)g->take(sizeof(float) * mt1, s, L, ok);
     g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[kT256].size(), 1), s, L, ok);
     g->job_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * (B + 1), s, L, ok);
-    g->job_begin_mom = (int32_t*)g->take(sizeof(int32_t) * (B + 1), s, L, ok);
     g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L, ok);
-    g->rmse_hist = (double*)g->take(sizeof(double) * (size_t)B * Kc, s, L, ok);
-    g->fb_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
-    g->deg_hist = (int32_t*)g->take(sizeof(int32_t) * (size_t)B * Kc, s, L, ok);
-    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(jobs[0].size(), 1), s, L,
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 3 * std::max<size_t>(jobs[0].size(), 1), s, L,
                                           ok);
-    g->ctr_hist = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * (size_t)B * Kc, s, L, ok);
-    g->ctr_part = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(jm.size(), 1), s, L,
-                                               ok);
+    g->npart = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[0].size(), 1), s, L, ok);
+    g->fpart = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(folds[0].size(), 1), s, L, ok);
+    g->fctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(folds[0].size(), 1), s,
+                                           L, ok);
+    g->fold_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * (B + 1), s, L, ok);
     g->sh = (uint32_t*)g->take(sizeof(uint32_t) * nb, s, L, ok);
     g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
     g->skey = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
     g->srank = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->sidx = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->sbig = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
     g->ps4 = (float4*)g->take(sizeof(float4) * mt1, s, L, ok);
     g->s_status = (unsigned long long*)g->take(sizeof(unsigned long long) * std::max(stiles, 1), s, L, ok);
     g->s_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, L, ok);
     for (int k = 0; k < kNumTables; ++k) {
         g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L, ok);
         g->njobs_p[k] = (int)jobs[k].size();
+        g->fjobs[k] = (FoldJob*)g->take(sizeof(FoldJob) * std::max<size_t>(folds[k].size(), 1), s, L, ok);
+        g->nfjobs[k] = (int)folds[k].size();
     }
-    g->jobs_mom = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jm.size(), 1), s, L, ok);
-    g->njobs_mom = (int)jm.size();
     if (!ok) {
         g->release(g->ws_bufs, s);
         return fail(VICP_ERR_OOM, "workspace allocation failed");
@@ -483,16 +538,19 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
     VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
-    for (int k = 0; k < kNumTables; ++k)
+    for (int k = 0; k < kNumTables; ++k) {
         if (!jobs[k].empty())
             VICP_HIP(hipMemcpyAsync(g->jobs_p[k], jobs[k].data(), sizeof(BlockJob) * jobs[k].size(),
                                     hipMemcpyHostToDevice, s));
-    if (!jm.empty())
-        VICP_HIP(hipMemcpyAsync(g->jobs_mom, jm.data(), sizeof(BlockJob) * jm.size(), hipMemcpyHostToDevice, s));
+        if (!folds[k].empty())
+            VICP_HIP(hipMemcpyAsync(g->fjobs[k], folds[k].data(), sizeof(FoldJob) * folds[k].size(),
+                                    hipMemcpyHostToDevice, s));
+    }
+    VICP_HIP(hipMemcpyAsync(g->fold_begin6, fbegin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
+                            hipMemcpyHostToDevice, s));
     VICP_HIP(hipMemcpyAsync(g->job_begin6, begin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
                             hipMemcpyHostToDevice, s));
     g->job_begin = g->job_begin6 + kT256 * (B + 1);
-    VICP_HIP(hipMemcpyAsync(g->job_begin_mom, begin_m.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
     launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
     VICP_HIP(hipStreamSynchronize(s));
     g->m_total = mt;
@@ -513,46 +571,48 @@ int check_grid(const vicp_grid* g)
 void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz, hipStream_t s, bool cap)
 {
     ProfScope ps("src_plan", s, cap);
-    const int64_t nb = g->V_total + g->B;
+    const int64_t nb = source_buckets(g, g->m);
     launch_fill_u32(g->sh, 0u, nb, s);
     launch_fill_u64(g->s_status, 0ull, scan_tiles(nb), s);
     launch_fill_u32(g->s_ticket, 0u, 4, s);
-    launch_src_bucket(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->st, g->sh, g->skey, g->srank, s);
+    launch_fill_u32((uint32_t*)g->sbig, 0u, g->B, s);
+    launch_src_bucket(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->st, g->sh, g->skey, g->srank,
+                      g->sbig, s);
     launch_scan(g->sh, nb, g->soff, nullptr, nullptr, g->s_status, g->s_ticket, s);
-    launch_src_place(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->skey, g->srank, g->soff, g->ps4, s);
+    launch_src_place(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->skey, g->srank, g->soff, g->sidx, s);
+    launch_src_rank(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->skey, g->soff, g->sidx, g->sbig,
+                    g->ps4, s);
 }
 
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
+// mom: registration form (per-block moment partials instead of per-query
+// results).
 void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
-                  hipStream_t s, bool cap)
+                  hipStream_t s, bool cap, bool mom)
 {
     const int tab = table_of(g->nns_block / g->nns_lpq);
     {
         ProfScope ps("nns_local", s, cap);
-        launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, px, py, pz,
-                         g->ps4, g->st, g->dir, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key,
-                         g->ctr, s);
+        launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
+                         pz, g->ps4, g->st, g->dir, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr,
+                         g->npart, s);
     }
     {
         ProfScope ps("fallback", s, cap);
         launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count, g->fb_list,
-                        g->fb_key, s);
+                        g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->njobs_p[tab], g->npart, g->ctr,
+                        g->fpart, g->fctr, s);
     }
 }
 
 void queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
                      double eps, hipStream_t s, bool cap)
 {
-    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
-    const int tab = table_of(g->nns_block / g->nns_lpq);
-    {
-        ProfScope ps("moments", s, cap);
-        launch_moments(g->d_pd, g->jobs_mom, g->njobs_mom, px, py, pz, g->qx, g->qy, g->qz, g->st, g->fb_key,
-                       g->nn_idx, g->nn_d2, g->part, g->flags, g->job_begin_mom, g->job_begin6 + tab * (g->B + 1),
-                       g->ctr, g->ctr_part, s);
-    }
+    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true);
     ProfScope ps("solve", s, cap);
-    launch_solve(g->d_pd, g->B, g->job_begin_mom, g->part, g->ctr_part, g->st, g->fb_count, g->rmse_hist,
+    const int tab = table_of(g->nns_block / g->nns_lpq);
+    launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
+                 g->fb_count, g->fb_list, g->fb_key, px, py, pz, g->qx, g->qy, g->qz, g->flags, g->rmse_hist,
                  g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
 }
 
@@ -599,9 +659,13 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         ProfScope ps("aabb", s, false);
         launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
     }
-    std::vector<uint32_t> hbox(8 * B);
-    VICP_HIP(hipMemcpyAsync(hbox.data(), g->box, sizeof(uint32_t) * 8 * B, hipMemcpyDeviceToHost, s));
+    if (!g->h_box && hipHostMalloc((void**)&g->h_box, sizeof(uint32_t) * 8 * B, hipHostMallocDefault) != hipSuccess) {
+        g->h_box = nullptr;
+        return fail(VICP_ERR_OOM, "pinned host allocation failed");
+    }
+    VICP_HIP(hipMemcpyAsync(g->h_box, g->box, sizeof(uint32_t) * 8 * B, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
+    const uint32_t* hbox = g->h_box;
     std::vector<PairHost> pairs = g->pairs;
     int64_t Vt = 0, words = 0;
     for (int p = 0; p < B; ++p) {
@@ -853,7 +917,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-    queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap);
+    queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, false);
     {
         ProfScope ps("fb_finalize", s, cap);
         launch_fb_finalize(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->fb_key, nn_idx, nn_d2, g->flags, s);
@@ -951,17 +1015,14 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
         if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
         for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap);
     }
-    std::vector<PairState> hst(B);
-    std::vector<double> hr((size_t)B * K);
-    std::vector<int32_t> hf((size_t)B * K), hd((size_t)B * K), hflags(B);
-    std::vector<unsigned long long> hc(2 * (size_t)B * K);
-    VICP_HIP(hipMemcpyAsync(hst.data(), g->st, sizeof(PairState) * B, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipMemcpyAsync(hr.data(), g->rmse_hist, sizeof(double) * B * K, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipMemcpyAsync(hf.data(), g->fb_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipMemcpyAsync(hd.data(), g->deg_hist, sizeof(int32_t) * B * K, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipMemcpyAsync(hflags.data(), g->flags, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipMemcpyAsync(hc.data(), g->ctr_hist, sizeof(unsigned long long) * 2 * B * K, hipMemcpyDeviceToHost, s));
+    VICP_HIP(hipMemcpyAsync(g->h_res, g->res, g->res_bytes, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
+    const char* hb = (const char*)g->h_res;
+    const PairState* hst = (const PairState*)hb;
+    const double* hr = (const double*)(hb + g->o_rmse);
+    const unsigned long long* hc = (const unsigned long long*)(hb + g->o_ctr);
+    const int32_t* hf = (const int32_t*)(hb + g->o_fb);
+    const int32_t* hflags = (const int32_t*)(hb + g->o_flags);
     if (o->use_graph && g_prof.on) prof_add_graph(g->gevents);
     bool nonfinite = false, degenerate = false, internal = false;
     for (int p = 0; p < B; ++p) {
@@ -1011,7 +1072,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap);
+    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap, false);
     return VICP_OK;
 }
 
@@ -1126,6 +1187,8 @@ int vicp_grid_free(vicp_grid* g)
     g->release(g->vbufs, nullptr);
     g->release(g->owned, nullptr);
     (void)hipDeviceSynchronize();
+    if (g->h_res) (void)hipHostFree(g->h_res);
+    if (g->h_box) (void)hipHostFree(g->h_box);
     delete g;
     return VICP_OK;
 }
@@ -1187,7 +1250,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
                 g->nns_block = bs;
                 g->nns_lpq = lpq;
                 g->sort_src = sorted != 0;
-                const float t = timed([&] { queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true); }) +
+                const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
                                 (sorted ? plan_ms / (float)searches_per_plan : 0.0f);
                 if (t < kMargin * best) {
                     best = t;
@@ -1202,7 +1265,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     best = 1e30f;
     for (int fg : {64, 128, 256, 512, 1024}) {
         g->fb_grid = fg;
-        const float t = timed([&] { queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, true); });
+        const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); });
         if (t < kMargin * best) {
             best = t;
             best_fg = fg;

@@ -25,7 +25,14 @@ constexpr uint32_t kMask = 0x80000000u;   // Mask(root) of Alg. 3
 constexpr uint32_t kNone = 0xFFFFFFFFu;   // no root (dilation state)
 constexpr int kMoments = 19;              // about the pair's centre c: sum p (3), sum q (3), sum p q^T (9),
                                           // sum |p|^2, sum |q|^2, sum d, count
-constexpr int kGradTerms = 8;             // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
+constexpr int kGradTerms = 8;
+// Source bucketing: points outside the grid go to buckets of kOutChunk
+// consecutive indices, and a bucket larger than kRankCap turns the pair's
+// bucketing off (identity order), so that ranking a point within its bucket
+// costs at most kRankCap reads.
+constexpr int kOutShift = 6;
+constexpr int64_t kOutChunk = (int64_t)1 << kOutShift;
+constexpr uint32_t kRankCap = 1024;             // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
 
 // One pair: where its data lives and its grid (Sec. II.A Step 1).
 struct PairDev {
@@ -40,12 +47,22 @@ struct PairDev {
     float cx, cy, cz;       // centre of the grid: reference point of the moment sums
     int32_t Dx, Dy, Dz;     // dims
     int32_t pad;
+    int64_t s_base;   // first source bucket: V voxel buckets, then ceil(m / kOutChunk) "outside" buckets
 };
 
 // A block's work: the pair it serves and its first item within the pair.
 struct BlockJob {
     int32_t pair;
     int32_t start;
+};
+
+// First-level fold of the search blocks' moment partials: up to kFoldChunk
+// consecutive search blocks [b0, b1) of one pair.
+constexpr int kFoldChunk = 64;
+struct FoldJob {
+    int32_t pair;
+    int32_t b0, b1;
+    int32_t pad;
 };
 
 // Per-pair ICP state on the device.
@@ -116,34 +133,33 @@ void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int 
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
 
 // search and moments
-void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted,
+void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
                       const float* px, const float* py, const float* pz, const float4* ps4,
                       const PairState* st, const uint2* dir, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
-                      unsigned long long* fb_key, unsigned long long* ctr, hipStream_t s);
+                      unsigned long long* fb_key, unsigned long long* ctr, double* part, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
-                       hipStream_t s);
-void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                      const float* pz, const uint32_t* skey, const uint32_t* srank, const uint32_t* soff,
-                      float4* ps4, hipStream_t s);
-void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy,
-                     const float* qz, const float* px, const float* py, const float* pz,
-                     const PairState* st, const int32_t* fb_count, const uint32_t* fb_list,
-                     unsigned long long* fb_key, hipStream_t s);
+                       int32_t* sbig, hipStream_t s);
+void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,
+                      const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s);
+void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                     const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
+                     const int32_t* sbig, float4* ps4, hipStream_t s);
+void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
+                     const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
+                     const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
+                     int stride, const double* part, const unsigned long long* ctr, double* fpart,
+                     unsigned long long* fctr, hipStream_t s);
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs,
                         const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2,
                         int32_t* flags, hipStream_t s);
-void launch_moments(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                    const float* pz, const float* qx, const float* qy, const float* qz, const PairState* st,
-                    const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2, double* part, int32_t* flags,
-                    const int32_t* mom_begin, const int32_t* nns_begin, const unsigned long long* ctr,
-                    unsigned long long* ctr_part, hipStream_t s);
-void launch_solve(const PairDev* pd, int npairs, const int32_t* job_begin, const double* part,
-                  const unsigned long long* ctr_part, PairState* st, int32_t* fb_count, double* rmse_hist,
+void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int32_t nunits, const double* fpart,
+                  const unsigned long long* fctr, PairState* st, int32_t* fb_count, const uint32_t* fb_list,
+                  const unsigned long long* fb_key, const float* px, const float* py, const float* pz,
+                  const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
                   double eps, hipStream_t s);
-int moments_items_per_block();
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                          const float* pz, int32_t* flags, hipStream_t s);
