@@ -62,13 +62,14 @@ __device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, f
     return in;
 }
 
+// Selects, not branches: a branch lets the compiler sink the index load into
+// the taken path and then wait for every load in flight.
 __device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj)
 {
     const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-    if (d < bd) {
-        bd = d;
-        bj = __float_as_uint(q.w);
-    }
+    const bool better = d < bd;
+    bd = better ? d : bd;
+    bj = better ? __float_as_uint(q.w) : bj;
 }
 
 // The same, also keeping the best candidate's coordinates.
@@ -76,13 +77,12 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
                                          float& bx, float& by, float& bz)
 {
     const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-    if (d < bd) {
-        bd = d;
-        bj = __float_as_uint(q.w);
-        bx = q.x;
-        by = q.y;
-        bz = q.z;
-    }
+    const bool better = d < bd;
+    bd = better ? d : bd;
+    bj = better ? __float_as_uint(q.w) : bj;
+    bx = better ? q.x : bx;
+    by = better ? q.y : by;
+    bz = better ? q.z : bz;
 }
 
 // LPQ lanes cooperate on one query: each scans every LPQ-th candidate of the
