@@ -223,14 +223,20 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     }
     if (kMom) {
         // moments of this lane's query about the grid centre; zero for lanes
-        // that hold no resolved query (selects, so nothing else is read)
-        __shared__ double mred[kMoments][kWaves];
+        // that hold no resolved query (selects, so nothing else is read).
+        // Reduction: float64 sums inside each row of 16 lanes (DPP), then
+        // the block's rows in order from LDS.  The two squared norms only
+        // set the solve's rounding floor and are summed in float32; the
+        // count is a popcount.
+        constexpr int kRows = 4 * kWaves;
+        __shared__ double mred[kMoments - 1][kRows];
+        __shared__ uint32_t mcnt[kWaves];
         const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
         const double p[3] = {found ? (double)x - c0 : 0.0, found ? (double)y - c1 : 0.0,
                              found ? (double)z - c2 : 0.0};
         const double q[3] = {found ? (double)bx - c0 : 0.0, found ? (double)by - c1 : 0.0,
                              found ? (double)bz - c2 : 0.0};
-        double a[kMoments];
+        double a[16];   // sum p, sum q, sum p q^T, sum d
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             a[r] = p[r];
@@ -238,21 +244,33 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] = p[r] * q[cc];
         }
-        a[15] = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-        a[16] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-        a[17] = found ? (double)bd : 0.0;
-        a[18] = found ? 1.0 : 0.0;
+        a[15] = found ? (double)bd : 0.0;
+        const float np = (float)(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        const float nq = (float)(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        const int row = w * 4 + (lane >> 4);
+        const bool row_end = (lane & 15) == 15;
 #pragma unroll
-        for (int j = 0; j < kMoments; ++j) {
-            const double sm = wave_sum_f64(a[j]);
-            if (lane == 0) mred[j][w] = sm;
+        for (int j = 0; j < 16; ++j) {
+            const double sm = row_sum_f64(a[j]);
+            if (row_end) mred[j == 15 ? 17 : j][row] = sm;
         }
+        const float snp = row_sum_f32(np), snq = row_sum_f32(nq);
+        if (row_end) {
+            mred[15][row] = (double)snp;
+            mred[16][row] = (double)snq;
+        }
+        const uint32_t nfound = (uint32_t)__popcll(__ballot(found));
+        if (lane == 0) mcnt[w] = nfound;
         __syncthreads();
-        if (threadIdx.x < kMoments) {
+        if (threadIdx.x < kMoments - 1) {
             double sm = mred[threadIdx.x][0];
 #pragma unroll
-            for (int q2 = 1; q2 < kWaves; ++q2) sm += mred[threadIdx.x][q2];
+            for (int r = 1; r < kRows; ++r) sm += mred[threadIdx.x][r];
             part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sm;
+        } else if (threadIdx.x == kMoments - 1) {
+            uint32_t cn = 0;
+            for (int q2 = 0; q2 < kWaves; ++q2) cn += mcnt[q2];
+            part[(int64_t)(kMoments - 1) * gridDim.x + blockIdx.x] = (double)cn;
         }
     } else {
         __syncthreads();

@@ -289,18 +289,25 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
             __syncthreads();
         }
     }
+    // waves that hold nothing (no fold unit, no global-search query) skip the
+    // reduction: their sums are exact zeros
+    const bool has = (int64_t)u0 + (int64_t)w * kWave < (int64_t)u1 || nfb > 0;
+    if (has) {
 #pragma unroll
-    for (int j = 0; j < kMoments; ++j) {
-        const double sm = wave_sum_f64(acc[j]);
-        if (lane == 0) red[j][w] = sm;
-    }
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        c0 += __shfl_xor(c0, d, kWave);
-        c1 += __shfl_xor(c1, d, kWave);
+        for (int j = 0; j < kMoments; ++j) {
+            const double sm = wave_sum_f64(acc[j]);
+            if (lane == 0) red[j][w] = sm;
+        }
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            c0 += __shfl_xor(c0, d, kWave);
+            c1 += __shfl_xor(c1, d, kWave);
+        }
+    } else if (lane == 0) {
+        for (int j = 0; j < kMoments; ++j) red[j][w] = 0.0;
     }
     if (lane == 0) {
-        cred[0][w] = c0;
-        cred[1][w] = c1;
+        cred[0][w] = has ? c0 : 0ull;
+        cred[1][w] = has ? c1 : 0ull;
     }
     __syncthreads();
     if (threadIdx.x < kMoments) {

@@ -90,6 +90,32 @@ __device__ __forceinline__ double dpp_add(double x)
     return x + __hiloint2double(hi, lo);
 }
 
+// Sum inside each row of 16 lanes in a fixed order (an inclusive scan): the
+// row's total ends in its last lane (15, 31, 47, 63).
+__device__ __forceinline__ double row_sum_f64(double x)
+{
+    x = dpp_add<0x111, 0xF>(x);   // row_shr:1
+    x = dpp_add<0x112, 0xF>(x);   // row_shr:2
+    x = dpp_add<0x114, 0xF>(x);   // row_shr:4
+    x = dpp_add<0x118, 0xF>(x);   // row_shr:8
+    return x;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add_f32(float x)
+{
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+
+__device__ __forceinline__ float row_sum_f32(float x)
+{
+    x = dpp_add_f32<0x111, 0xF>(x);
+    x = dpp_add_f32<0x112, 0xF>(x);
+    x = dpp_add_f32<0x114, 0xF>(x);
+    x = dpp_add_f32<0x118, 0xF>(x);
+    return x;
+}
+
 // Sum over the 64 lanes in a fixed order (an inclusive scan inside each row
 // of 16, then rows 0+1 and 2+3, then the two halves), returned to every lane.
 __device__ __forceinline__ double wave_sum_f64(double x)
