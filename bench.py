@@ -56,13 +56,13 @@ def parse():
     return ap.parse_args()
 
 
-def nns_local_bytes(m, F, cand, dil):
-    """Algorithmic bytes of one local-search launch (each logical access once):
-    per query 12 (p) + 4 (off[v]) + 4 (count word); +8 (off[root] + count
-    word) when the voxel is dilated; 16 per candidate (float4 x, y, z, index);
-    8 out (index + distance) for a local search, or 16 (index marker, list
-    slot, 64-bit key) for a query sent to the global search."""
-    return m * 20 + (m - F) * 8 + F * 16 + 8 * dil + 16 * cand
+def nns_local_bytes(m, F, cand, nblocks):
+    """Algorithmic bytes of one registration-search launch (each logical
+    access once): per query 16 (the bucketed source point, float4) + 8 (its
+    voxel's search-directory entry); 16 per candidate (float4 x, y, z,
+    index); 12 per query sent to the global search (list slot + 64-bit key);
+    per block 19 float64 moment partials + 3 counters (176)."""
+    return m * 24 + 16 * cand + 12 * F + 176 * nblocks
 
 
 def main():
@@ -97,7 +97,8 @@ def main():
         g.set_schedule(bs, lpq, bool(srt), fg)
     schedule = g.schedule
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
-                   f"{'true' if schedule['sort_source'] else 'false'}>")
+                   f"{'true' if schedule['sort_source'] else 'false'}, true>")
+    nns_blocks = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block'])
 
     def step():
         g.rebuild(q)
@@ -105,57 +106,48 @@ def main():
         return g.register(p, P.iters, use_graph=bool(a.graph))
 
     log(f"[bench] workload {P.name}: n={P.n} m={P.m} voxel={P.voxel} rings={P.rings} iters={P.iters}")
-    prof = not a.no_prof
-    if prof:
-        api.prof_enable(True)        # before warm-up, so the captured graph already holds the events
+    # the timed region runs with no timing events at all (events recorded
+    # inside a graph perturb it); per-kernel durations come from an eager
+    # pass of the same steps afterwards
     for _ in range(max(a.warmup, 1)):
         res = step()
     log("[bench] warmup done")
-    timing_pass = "events in the timed region"
-    if prof and a.graph and api.prof_read("graph_untimed")[0] > 0:
-        # this runtime cannot time events recorded by a graph: time the graph
-        # without them and take kernel durations from an eager pass below
-        api.prof_enable(False)
-        prof = False
-        timing_pass = "events in an eager pass of the same steps"
-        step()
-    if prof:
-        api.prof_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         res = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if prof:
-        api.prof_enable(False)
     log("[bench] timed region done")
     ms = (t1 - t0) * 1e3 / a.steps
     K = int(res.iters[0])
     queries_per_s = K * P.m / (ms * 1e-3)
     kernels = {}
-    if not prof and not a.no_prof:
+    timing_pass = None
+    if not a.no_prof:
+        prof_steps = min(a.steps, 5)
         api.prof_reset()
         api.prof_enable(True)
-        for _ in range(a.steps):
+        for _ in range(prof_steps):
             g.rebuild(q)
             g.dilate(P.rings)
             g.register(p, P.iters, use_graph=False)
         torch.cuda.synchronize()
         api.prof_enable(False)
-        prof = True
-    if prof:
+        timing_pass = (f"eager pass of {prof_steps} steps after the timed region: search, global search and solve "
+                       "timed by start/stop HIP events recorded at the kernel (hipExtLaunchKernelGGL), other "
+                       "kernels by HIP events around the launch")
         for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "src_plan", "nns_local",
-                     "fallback", "moments", "solve", "icp_graph"):
+                     "fallback", "solve"):
             n_launch, tot = api.prof_read(name)
             if n_launch:
-                kernels[name] = {"launches_per_step": n_launch / a.steps, "avg_us": 1e3 * tot / n_launch,
-                                 "ms_per_step": tot / a.steps}
+                kernels[name] = {"launches_per_step": n_launch / prof_steps, "avg_us": 1e3 * tot / n_launch,
+                                 "ms_per_step": tot / prof_steps}
 
     F = np.asarray(res.fallbacks[0], np.int64)
     cand = np.asarray(res.candidates[0], np.int64)
     dil = np.asarray(res.dilated_lookups[0], np.int64)
-    per_launch = [nns_local_bytes(P.m, int(F[k]), int(cand[k]), int(dil[k])) for k in range(K)]
+    per_launch = [nns_local_bytes(P.m, int(F[k]), int(cand[k]), nns_blocks) for k in range(K)]
     bytes_per_launch = float(np.mean(per_launch))
     roofline = None
     if "nns_local" in kernels:
@@ -171,7 +163,8 @@ def main():
         roofline = {"kernel": nns_variant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                    "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3)}
+                    "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3),
+                    "dilated_lookup_fraction": round(float(dil.mean()) / P.m, 4)}
 
     desc = g.describe()
     g.free()

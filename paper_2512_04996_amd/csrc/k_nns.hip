@@ -96,9 +96,10 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // sum q, sum p q^T, sum |p|^2, sum |q|^2 about the grid centre, sum d, count)
 // in a fixed lane and wave order and writes one partial per block, with its
 // counters (candidates scanned, dilated lookups, queries sent to the global
-// search).  Partials and counters are stored moment-major: entry j of block
-// b at [j * gridDim.x + b].  Queries sent to the global search add their
-// moments later, once resolved.
+// search).  Partials and counters are stored block-major: entry j of block
+// b at [b * kMoments + j], counter k at [b * 3 + k], one contiguous record per
+// block.  Queries sent to the global search add their moments later, once
+// resolved.  Launch blocks are mapped to jobs XCD by XCD (xcd_job).
 template <int BS, int LPQ, bool kSorted, bool kMom>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
@@ -112,7 +113,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
     constexpr int kWaves = BS / kWave;
-    const BlockJob job = jobs[blockIdx.x];
+    const int jb = xcd_job((int)blockIdx.x, (int)gridDim.x);
+    const BlockJob job = jobs[jb];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
     if (S.done) return;   // uniform over the block
@@ -266,11 +268,11 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             double sm = mred[threadIdx.x][0];
 #pragma unroll
             for (int r = 1; r < kRows; ++r) sm += mred[threadIdx.x][r];
-            part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sm;
+            part[(int64_t)jb * kMoments + threadIdx.x] = sm;
         } else if (threadIdx.x == kMoments - 1) {
             uint32_t cn = 0;
             for (int q2 = 0; q2 < kWaves; ++q2) cn += mcnt[q2];
-            part[(int64_t)(kMoments - 1) * gridDim.x + blockIdx.x] = (double)cn;
+            part[(int64_t)jb * kMoments + kMoments - 1] = (double)cn;
         }
     } else {
         __syncthreads();
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         const int k = threadIdx.x - 32;
         unsigned long long sm = 0;
         for (int q2 = 0; q2 < kWaves; ++q2) sm += red[k][q2];
-        ctr[(int64_t)k * gridDim.x + blockIdx.x] = sm;
+        ctr[(int64_t)jb * 3 + k] = sm;
     }
 }
 
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
                                                          const int32_t* __restrict__ fb_count,
                                                          const uint32_t* __restrict__ fb_list,
                                                          unsigned long long* __restrict__ fb_key,
-                                                         const FoldJob* __restrict__ fjobs, int nunits, int stride,
+                                                         const FoldJob* __restrict__ fjobs, int nunits,
                                                          const double* __restrict__ part,
                                                          const unsigned long long* __restrict__ ctr,
                                                          double* __restrict__ fpart,
@@ -421,11 +423,13 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
             const FoldJob fj = fjobs[u];
             if (st[fj.pair].done) continue;   // uniform over the block
             const int cnt = fj.b1 - fj.b0;
-            for (int e = threadIdx.x; e < (kMoments + 2) * cnt; e += kFbThreads) {
-                const int j = e / cnt, bb = e - j * cnt;
-                const int64_t b = (int64_t)fj.b0 + bb;
-                if (j < kMoments) fv[j][bb] = part[(int64_t)j * stride + b];
-                else fc[j - kMoments][bb] = ctr[(int64_t)(j - kMoments) * stride + b];
+            for (int e = threadIdx.x; e < kMoments * cnt; e += kFbThreads) {
+                const int bb = e / kMoments, j = e - bb * kMoments;
+                fv[j][bb] = part[(int64_t)fj.b0 * kMoments + e];
+            }
+            for (int e = threadIdx.x; e < 3 * cnt; e += kFbThreads) {
+                const int bb = e / 3, j = e - bb * 3;
+                if (j < 2) fc[j][bb] = ctr[(int64_t)fj.b0 * 3 + e];
             }
             __syncthreads();
             if (threadIdx.x < kMoments) {
@@ -537,8 +541,8 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 {
     if (njobs <= 0) return;
 #define VICP_NNS(BS, L, SORTED, MOM)                                                                                 \
-    hipLaunchKernelGGL((k_nns_local<BS, L, SORTED, MOM>), dim3(njobs), dim3(BS), 0, s, pd, jobs, px, py, pz, ps4,  \
-                       st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part)
+    launch_timed(k_nns_local<BS, L, SORTED, MOM>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, ps4, st, dir,  \
+                 qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part)
 #define VICP_NNS_L(BS, SORTED, MOM)                  \
     switch (lpq) {                                   \
     case 2: VICP_NNS(BS, 2, SORTED, MOM); break;     \
@@ -597,12 +601,12 @@ void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const f
 void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
                      const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
-                     int stride, const double* part, const unsigned long long* ctr, double* fpart,
+                     const double* part, const unsigned long long* ctr, double* fpart,
                      unsigned long long* fctr, hipStream_t s)
 {
     if (npairs <= 0 || npairs > kMaxPairs) return;
-    hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(kFbThreads), 0, s, pd, npairs, qx, qy, qz, px, py, pz, st,
-                       fb_count, fb_list, fb_key, fjobs, nunits, stride, part, ctr, fpart, fctr);
+    launch_timed(k_fallback, dim3(grid), dim3(kFbThreads), s, pd, npairs, qx, qy, qz, px, py, pz, st, fb_count,
+                 fb_list, fb_key, fjobs, nunits, part, ctr, fpart, fctr);
 }
 
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs, const unsigned long long* fb_key,

@@ -374,9 +374,9 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                   double eps, hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_solve, dim3(npairs), dim3(kSolveThreads), 0, s, pd, fold_begin, nunits, fpart, fctr, st,
-                       fb_count, fb_list, fb_key, px, py, pz, qx, qy, qz, flags, rmse_hist, fb_hist, deg_hist,
-                       ctr_hist, k, K, early_stop, eps);
+    launch_timed(k_solve, dim3(npairs), dim3(kSolveThreads), s, pd, fold_begin, nunits, fpart, fctr, st, fb_count,
+                 fb_list, fb_key, px, py, pz, qx, qy, qz, flags, rmse_hist, fb_hist, deg_hist, ctr_hist, k, K,
+                 early_stop, eps);
 }
 
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)

@@ -140,18 +140,65 @@ thread_local std::vector<ProfRec>* t_capture_events = nullptr;
 // Brackets one launch with events when timing is on.  Outside capture the
 // pair is read at the next vicp_prof_read; inside capture it is kept with the
 // graph and read after each replay.
+// Records an event on a stream.  Under capture, the event goes in as an
+// explicit event-record node after the stream's current dependencies (an
+// event recorded through capture cannot be timed on this runtime; an
+// explicit node can).
+void record_event(hipEvent_t e, hipStream_t s, bool capturing)
+{
+    if (!capturing) {
+        (void)hipEventRecord(e, s);
+        return;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t graph = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t ndeps = 0;
+    if (hipStreamGetCaptureInfo_v2(s, &cs, &id, &graph, &deps, &ndeps) != hipSuccess ||
+        cs != hipStreamCaptureStatusActive) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraphNode_t node = nullptr;
+    if (hipGraphAddEventRecordNode(&node, graph, deps, ndeps, e) != hipSuccess ||
+        hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies) != hipSuccess)
+        (void)hipGetLastError();
+}
+
+// The events of the open timed scope, for a launch that records them at the
+// kernel's own start and end (launch_timed).
+struct ExtEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool used = false;
+};
+thread_local ExtEvents* t_ext = nullptr;
+
+// A timed scope: events around the work queued inside it.  With ext set and
+// no capture, a launch_timed launch inside the scope takes the events
+// instead, which excludes the launch overhead from the measured time.
 struct ProfScope {
     hipStream_t s;
     const char* name;
-    hipEvent_t b = nullptr;
-    ProfScope(const char* nm, hipStream_t st, bool capturing) : s(st), name(nm)
+    bool cap;
+    hipEvent_t a = nullptr, b = nullptr;
+    ExtEvents ext;
+    bool use_ext = false;
+    ProfScope(const char* nm, hipStream_t st, bool capturing, bool ext_launch = false) : s(st), name(nm), cap(capturing)
     {
         if (!g_prof.on) return;
         if (capturing && !t_capture_events) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
-        hipEvent_t a = prof_event();
+        a = prof_event();
         b = prof_event();
-        (void)hipEventRecord(a, s);
+        use_ext = ext_launch && !capturing;
+        if (use_ext) {
+            ext.a = a;
+            ext.b = b;
+            t_ext = &ext;
+        } else {
+            record_event(a, s, cap);
+        }
         if (capturing)
             t_capture_events->push_back({name, a, b});
         else
@@ -159,9 +206,31 @@ struct ProfScope {
     }
     ~ProfScope()
     {
-        if (b) (void)hipEventRecord(b, s);
+        if (!b) return;
+        if (use_ext) {
+            t_ext = nullptr;
+            if (!ext.used) {   // nothing was launched: an empty interval
+                (void)hipEventRecord(a, s);
+                (void)hipEventRecord(b, s);
+            }
+        } else {
+            record_event(b, s, cap);
+        }
     }
 };
+
+}  // namespace
+
+bool vicp::prof_take_ext_events(hipEvent_t* start, hipEvent_t* stop)
+{
+    if (!t_ext || t_ext->used) return false;
+    t_ext->used = true;
+    *start = t_ext->a;
+    *stop = t_ext->b;
+    return true;
+}
+
+namespace {
 
 // After a replay has finished: add the graph's kernel times.  Runtimes that
 // cannot time events recorded by a graph report an error here; it is cleared
@@ -592,15 +661,15 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
 {
     const int tab = table_of(g->nns_block / g->nns_lpq);
     {
-        ProfScope ps("nns_local", s, cap);
+        ProfScope ps("nns_local", s, cap, true);
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
                          pz, g->ps4, g->st, g->dir, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr,
                          g->npart, s);
     }
     {
-        ProfScope ps("fallback", s, cap);
+        ProfScope ps("fallback", s, cap, true);
         launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count, g->fb_list,
-                        g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->njobs_p[tab], g->npart, g->ctr,
+                        g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->npart, g->ctr,
                         g->fpart, g->fctr, s);
     }
 }
@@ -609,7 +678,7 @@ void queue_iteration(vicp_grid* g, const float* px, const float* py, const float
                      double eps, hipStream_t s, bool cap)
 {
     queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true);
-    ProfScope ps("solve", s, cap);
+    ProfScope ps("solve", s, cap, true);
     const int tab = table_of(g->nns_block / g->nns_lpq);
     launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
                  g->fb_count, g->fb_list, g->fb_key, px, py, pz, g->qx, g->qy, g->qz, g->flags, g->rmse_hist,

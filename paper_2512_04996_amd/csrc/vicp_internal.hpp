@@ -17,6 +17,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace vicp {
@@ -77,6 +78,31 @@ struct PairState {
 };
 
 // --------------------------------------------------------------------------
+// XCD-aware block order.  Workgroups are dealt to the 8 XCDs round-robin
+// (block b runs on XCD b mod 8), and each XCD has its own L2.  xcd_job maps
+// the launch index to a job index so that each XCD receives chunks of
+// kXcdChunk consecutive jobs (jobs touching the same data, such as
+// neighbouring queries of the bucketed source, then share one L2), while the
+// chunks still rotate over the XCDs (a dense region does not land on one
+// XCD).  A bijection on [0, n); the ragged tail keeps its order.
+// --------------------------------------------------------------------------
+constexpr int kXcds = 8;
+#ifndef VICP_XCD_CHUNK
+#define VICP_XCD_CHUNK 16
+#endif
+constexpr int kXcdChunk = VICP_XCD_CHUNK;
+
+__device__ __forceinline__ int xcd_job(int b, int n)
+{
+    if (kXcdChunk <= 0) return b;
+    constexpr int span = kXcds * kXcdChunk;
+    const int full = (n / span) * span;
+    if (b >= full) return b;
+    const int x = b % kXcds, i = b / kXcds;
+    return ((i / kXcdChunk) * kXcds + x) * kXcdChunk + (i % kXcdChunk);
+}
+
+// --------------------------------------------------------------------------
 // wave64 reductions on DPP (no LDS round trips)
 // --------------------------------------------------------------------------
 
@@ -131,6 +157,24 @@ __device__ __forceinline__ double wave_sum_f64(double x)
 }
 
 // --------------------------------------------------------------------------
+// Kernel timing.  While a timed scope of the runtime is open on this thread
+// (and its stream is not being captured), launch_timed hands the scope's two
+// events to the launch, and the runtime records them at the kernel's own
+// start and end; otherwise it is a plain launch.
+// --------------------------------------------------------------------------
+bool prof_take_ext_events(hipEvent_t* start, hipEvent_t* stop);
+
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof_take_ext_events(&a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
+// --------------------------------------------------------------------------
 // kernel launchers (one translation unit each; all asynchronous)
 // --------------------------------------------------------------------------
 
@@ -175,7 +219,7 @@ void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const f
 void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
                      const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
-                     int stride, const double* part, const unsigned long long* ctr, double* fpart,
+                     const double* part, const unsigned long long* ctr, double* fpart,
                      unsigned long long* fctr, hipStream_t s);
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs,
                         const unsigned long long* fb_key, int32_t* nn_idx, float* nn_d2,
