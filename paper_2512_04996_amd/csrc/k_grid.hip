@@ -1,6 +1,8 @@
 // k_grid.hip -- target grid build: bounding box, voxelise + count (Alg. 1,
 // GPU part), offsets by a single-pass scan (Alg. 1, CPU part, moved to the
 // GPU), scatter into segments and canonical in-segment order (Alg. 2).
+#include <algorithm>
+
 #include "vicp_internal.hpp"
 
 namespace vicp {
@@ -47,14 +49,6 @@ __device__ __forceinline__ bool voxel_id(const PairDev& P, float x, float y, flo
 // bounding box per pair: box[8 p + 0..2] = ordered min, [3..5] = ordered max,
 // [6] = non-finite flag
 // --------------------------------------------------------------------------
-__global__ void k_box_init(uint32_t* box, int npairs)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npairs * 8) return;
-    int f = i & 7;
-    box[i] = (f < 3) ? 0xFFFFFFFFu : 0u;
-}
-
 __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx, const float* __restrict__ qy,
                                                    const float* __restrict__ qz, const PairDev* __restrict__ pd,
                                                    const BlockJob* __restrict__ jobs, int items, uint32_t* box)
@@ -91,15 +85,14 @@ __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx,
         red[6][w] = bad;
     }
     __syncthreads();
+    // one partial per block (no atomics: same-address atomics from many
+    // blocks serialise across the XCDs); the host, which reads the box back
+    // anyway, combines the partials per pair
     if (threadIdx.x < 7) {
         uint32_t r = red[threadIdx.x][0];
         for (int k = 1; k < kThreads / kWave; ++k)
             r = (threadIdx.x < 3) ? min(r, red[threadIdx.x][k]) : max(r, red[threadIdx.x][k]);
-        uint32_t* dst = box + 8 * job.pair + threadIdx.x;
-        if (threadIdx.x < 3)
-            atomicMin(dst, r);
-        else
-            atomicMax(dst, r);
+        box[8 * (int64_t)blockIdx.x + threadIdx.x] = r;
     }
 }
 
@@ -313,10 +306,21 @@ __global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict_
     const uint32_t og = off[g];
     const int64_t cs = (int64_t)og - 2 * g;
     const uint32_t c = hist[g];
-    uint32_t r = 0;
-    for (uint32_t t = 0; t < c; ++t) r += (tmp[cs + t] < e) ? 1u : 0u;
+    const uint32_t r = rank_in(tmp, cs, c, e);
     vm[(int64_t)og + 2 + r] = e;
     qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+}
+
+// Zeroes up to four arrays (u32, u64, u32, u32) in one launch.
+__global__ void k_clear4(uint32_t* __restrict__ a, int64_t na, unsigned long long* __restrict__ b, int64_t nb,
+                         uint32_t* __restrict__ c, int64_t nc, uint32_t* __restrict__ d, int64_t nd, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < na) a[i] = 0u;
+        if (i < nb) b[i] = 0ull;
+        if (i < nc) c[i] = 0u;
+        if (i < nd) d[i] = 0u;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count)
@@ -332,12 +336,6 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 }
 
 }  // namespace
-
-void launch_box_init(uint32_t* box, int npairs, hipStream_t s)
-{
-    const int n = npairs * 8;
-    hipLaunchKernelGGL(k_box_init, dim3((n + 255) / 256), dim3(256), 0, s, box, npairs);
-}
 
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
                  int njobs, int items_per_block, uint32_t* box, hipStream_t s)
@@ -382,6 +380,15 @@ void launch_rank_sort(const float* qx, const float* qy, const float* qz, const P
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_rank_sort, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm,
                        qs4);
+}
+
+void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, uint32_t* c, int64_t nc, uint32_t* d,
+                   int64_t nd, hipStream_t s)
+{
+    const int64_t n = std::max(std::max(na, nb), std::max(nc, nd));
+    if (n <= 0) return;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_clear4, dim3(blocks), dim3(256), 0, s, a, na, b, nb, c, nc, d, nd, n);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s)

@@ -376,15 +376,7 @@ __global__ __launch_bounds__(256) void k_src_rank(const PairDev* __restrict__ pd
     if (sbig[job.pair] == 0) {
         const uint32_t key = skey[gp];
         const uint32_t lo = soff[key], hi = soff[key + 1];
-        uint32_t r = 0;
-        for (uint32_t k = lo; k < hi; k += 8) {   // eight loads in flight per round
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = sidx[min(k + (uint32_t)u, hi - 1u)];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) r += (k + (uint32_t)u < hi && v[u] < (uint32_t)i) ? 1u : 0u;
-        }
-        pos = (int64_t)lo + r;
+        pos = (int64_t)lo + rank_in(sidx, lo, hi - lo, (uint32_t)i);
     }
     ps4[pos] = make_float4(px[gp], py[gp], pz[gp], __uint_as_float((uint32_t)i));
 }

@@ -346,12 +346,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
 }
 
 // Initial state: pose rounded to float32 for the search; pairs with no
-// source points are done from the start.
+// source points are done from the start; the global-search counts and the
+// fault flags start at zero.
 __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restrict__ st, const double* __restrict__ rt64,
-                            int npairs)
+                            int npairs, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
+    fb_count[p] = 0;
+    flags[p] = 0;
     PairState& S = st[p];
     S.done = pd[p].m > 0 ? 0 : 1;
     for (int j = 0; j < 12; ++j) {
@@ -379,10 +382,11 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                  early_stop, eps);
 }
 
-void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s)
+void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, int32_t* fb_count,
+                      int32_t* flags, hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_set_state, dim3((npairs + 63) / 64), dim3(64), 0, s, pd, st, rt64, npairs);
+    hipLaunchKernelGGL(k_set_state, dim3((npairs + 63) / 64), dim3(64), 0, s, pd, st, rt64, npairs, fb_count, flags);
 }
 
 // Flags pairs whose source holds NaN or Inf (bit 0 of PairState::status).

@@ -378,7 +378,8 @@ struct vicp_grid {
     size_t o_rmse = 0, o_ctr = 0, o_fb = 0, o_deg = 0, o_flags = 0;
     void* h_res = nullptr;
     size_t h_res_cap = 0;
-    uint32_t* h_box = nullptr;   // pinned: the bounding boxes read back by each build
+    uint32_t* h_box = nullptr;   // pinned: per-block bounding-box partials read back by each build
+    std::vector<BlockJob> h_jobs_q8;
     void* staging = nullptr;
     int32_t* fb_count = nullptr;
     uint32_t* fb_list = nullptr;
@@ -588,7 +589,7 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
     g->skey = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
     g->srank = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
-    g->sidx = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
+    g->sidx = (uint32_t*)g->take(sizeof(uint32_t) * (mt1 + 4), s, L, ok);   // +4: rank_in reads 16-byte chunks
     g->sbig = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
     g->ps4 = (float4*)g->take(sizeof(float4) * mt1, s, L, ok);
     g->s_status = (unsigned long long*)g->take(sizeof(unsigned long long) * std::max(stiles, 1), s, L, ok);
@@ -641,10 +642,7 @@ void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz,
 {
     ProfScope ps("src_plan", s, cap);
     const int64_t nb = source_buckets(g, g->m);
-    launch_fill_u32(g->sh, 0u, nb, s);
-    launch_fill_u64(g->s_status, 0ull, scan_tiles(nb), s);
-    launch_fill_u32(g->s_ticket, 0u, 4, s);
-    launch_fill_u32((uint32_t*)g->sbig, 0u, g->B, s);
+    launch_clear4(g->sh, nb, g->s_status, scan_tiles(nb), g->s_ticket, 4, (uint32_t*)g->sbig, g->B, s);
     launch_src_bucket(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->st, g->sh, g->skey, g->srank,
                       g->sbig, s);
     launch_scan(g->sh, nb, g->soff, nullptr, nullptr, g->s_status, g->s_ticket, s);
@@ -722,19 +720,29 @@ float unordered(uint32_t k)
 int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
     const int B = g->B;
-    launch_box_init(g->box, B, s);
-    launch_fill_u32(g->err, 0u, 4, s);
     {
         ProfScope ps("aabb", s, false);
         launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
     }
-    if (!g->h_box && hipHostMalloc((void**)&g->h_box, sizeof(uint32_t) * 8 * B, hipHostMallocDefault) != hipSuccess) {
+    const size_t nbox = 8 * (size_t)g->njobs_q8;
+    if (!g->h_box && nbox &&
+        hipHostMalloc((void**)&g->h_box, sizeof(uint32_t) * nbox, hipHostMallocDefault) != hipSuccess) {
         g->h_box = nullptr;
         return fail(VICP_ERR_OOM, "pinned host allocation failed");
     }
-    VICP_HIP(hipMemcpyAsync(g->h_box, g->box, sizeof(uint32_t) * 8 * B, hipMemcpyDeviceToHost, s));
+    if (nbox) VICP_HIP(hipMemcpyAsync(g->h_box, g->box, sizeof(uint32_t) * nbox, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
-    const uint32_t* hbox = g->h_box;
+    // per pair: min of the block minima, max of the block maxima, any
+    // non-finite flag (a pair with no points keeps the empty box)
+    std::vector<uint32_t> hbox(8 * (size_t)B);
+    for (int p = 0; p < B; ++p)
+        for (int f = 0; f < 8; ++f) hbox[8 * p + f] = f < 3 ? 0xFFFFFFFFu : 0u;
+    for (int j = 0; j < g->njobs_q8; ++j) {
+        uint32_t* d = &hbox[8 * (size_t)g->h_jobs_q8[j].pair];
+        const uint32_t* b = &g->h_box[8 * (size_t)j];
+        for (int f = 0; f < 3; ++f) d[f] = std::min(d[f], b[f]);
+        for (int f = 3; f < 7; ++f) d[f] = std::max(d[f], b[f]);
+    }
     std::vector<PairHost> pairs = g->pairs;
     int64_t Vt = 0, words = 0;
     for (int p = 0; p < B; ++p) {
@@ -799,9 +807,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
     VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
-    launch_fill_u32(g->hist, 0u, Vt, s);
-    launch_fill_u64(g->scan_status, 0ull, scan_tiles(Vt), s);
-    launch_fill_u32(g->scan_ticket, 0u, 4, s);
+    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
     {
         ProfScope ps("count", s, false);
         launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, s);
@@ -895,17 +901,18 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, c
     make_jobs(ncount, 2048, jq8, nullptr);
     bool ok = true;
     g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned, ok);
-    g->box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * npairs, s, g->owned, ok);
+    g->box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * std::max<size_t>(jq8.size(), 1), s, g->owned, ok);
     g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned, ok);
     g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned, ok);
     g->jobs_q8 = (BlockJob*)g->take(sizeof(BlockJob) * jq8.size(), s, g->owned, ok);
     g->vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
     g->rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
-    g->slots = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
+    g->slots = (uint32_t*)g->take(sizeof(uint32_t) * (nt + 4), s, g->owned, ok);   // +4: rank_in reads 16-byte chunks
     g->qs4 = (float4*)g->take(sizeof(float4) * nt, s, g->owned, ok);
     if (!ok) return bail(fail(VICP_ERR_OOM, "allocation failed"));
     g->njobs_q = (int)jq.size();
     g->njobs_q8 = (int)jq8.size();
+    g->h_jobs_q8 = jq8;
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);   // target fields only; the grid fields follow the bounding box
     if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -981,9 +988,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     std::vector<double> rt64(12 * g->B);
     for (int i = 0; i < 12 * g->B; ++i) rt64[i] = (double)Rt[i];
     upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-    launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, g->fb_count, g->flags, s);
     launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, false);
@@ -1035,10 +1040,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     const int early = o->early_stop ? 1 : 0;
     const double eps = o->rmse_eps;
     upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, s);
-    launch_fill_u32((uint32_t*)g->flags, 0u, B, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, g->fb_count, g->flags, s);
     launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
@@ -1283,7 +1286,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     std::vector<double> rt(12 * g->B, 0.0);
     for (int p = 0; p < g->B; ++p) rt[12 * p] = rt[12 * p + 4] = rt[12 * p + 8] = 1.0;
     upload(rt.data(), sizeof(double) * 12 * g->B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, s);
+    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, g->fb_count, g->flags, s);
     hipEvent_t a, b;
     VICP_HIP(hipEventCreate(&a));
     VICP_HIP(hipEventCreate(&b));

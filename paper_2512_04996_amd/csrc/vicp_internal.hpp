@@ -157,6 +157,35 @@ __device__ __forceinline__ double wave_sum_f64(double x)
 }
 
 // --------------------------------------------------------------------------
+// Rank of e among the c values a[lo .. lo + c): how many are smaller.  Reads
+// 16-byte aligned chunks, eight in flight per round; a must be allocated with
+// at least 4 words of slack past its last element (a chunk may run over).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ a, int64_t lo, uint32_t c, uint32_t e)
+{
+    if (c == 0) return 0;
+    const uint4* v4 = reinterpret_cast<const uint4*>(a + (lo & ~(int64_t)3));
+    const int64_t first = lo & 3, end = first + c;   // positions relative to the aligned base
+    const int64_t last_chunk = (end - 1) >> 2;
+    uint32_t r = 0;
+    for (int64_t k = 0; k <= last_chunk; k += 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = v4[min(k + u, last_chunk)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t pos = 4 * (k + u);
+            const bool live = k + u <= last_chunk;
+            r += (live && pos >= first && pos < end && v[u].x < e) ? 1u : 0u;
+            r += (live && pos + 1 >= first && pos + 1 < end && v[u].y < e) ? 1u : 0u;
+            r += (live && pos + 2 >= first && pos + 2 < end && v[u].z < e) ? 1u : 0u;
+            r += (live && pos + 3 >= first && pos + 3 < end && v[u].w < e) ? 1u : 0u;
+        }
+    }
+    return r;
+}
+
+// --------------------------------------------------------------------------
 // Kernel timing.  While a timed scope of the runtime is open on this thread
 // (and its stream is not being captured), launch_timed hands the scope's two
 // events to the launch, and the runtime records them at the kernel's own
@@ -179,7 +208,6 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, Args...
 // --------------------------------------------------------------------------
 
 // grid build
-void launch_box_init(uint32_t* box, int npairs, hipStream_t s);
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd,
                  const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd,
@@ -194,6 +222,8 @@ void launch_rank_sort(const float* qx, const float* qy, const float* qz, const P
                       const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* hist,
                       const uint32_t* off, const uint32_t* tmp, uint32_t* vm, float4* qs4,
                       hipStream_t s);
+void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, uint32_t* c, int64_t nc, uint32_t* d,
+                   int64_t nd, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t s);
 
@@ -230,7 +260,8 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                   const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
                   double eps, hipStream_t s);
-void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, hipStream_t s);
+void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, int32_t* fb_count,
+                      int32_t* flags, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                          const float* pz, int32_t* flags, hipStream_t s);
 void launch_copy_fb(const int32_t* fb_count, int32_t* out, int npairs, hipStream_t s);
