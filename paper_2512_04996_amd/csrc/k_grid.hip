@@ -184,19 +184,35 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
                                                    uint2* __restrict__ dir, unsigned long long* status,
                                                    uint32_t* ticket)
 {
+    // Each thread scans kScanItems consecutive entries; the tile moves between
+    // global memory and that blocked layout through LDS (padded rows), so that
+    // every global load and store of hist, off and dir is contiguous across
+    // the lanes of a wave.
+    constexpr int kPad = kScanItems + 1;
+    __shared__ uint32_t s_h[kThreads * kPad];
+    __shared__ uint32_t s_o[kThreads * kPad];
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kThreads / kWave];
     __shared__ uint32_t s_prefix;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t tbase = tile * kScanTile;
+    auto lds = [](int idx) { return (idx / kScanItems) * kPad + idx % kScanItems; };
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int idx = j * kThreads + (int)threadIdx.x;
+        const int64_t g = tbase + idx;
+        s_h[lds(idx)] = (g < total) ? hist[g] : 0u;
+    }
+    __syncthreads();
+    const int64_t base = tbase + (int64_t)threadIdx.x * kScanItems;
     uint32_t h[kScanItems];
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t g = base + k;
-        h[k] = (g < total) ? hist[g] : 0u;
+        h[k] = s_h[threadIdx.x * kPad + k];
         sum += (g < total) ? h[k] + (kSeg ? 2u : 0u) : 0u;
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -253,15 +269,25 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t g = base + k;
+        s_o[threadIdx.x * kPad + k] = run;
         if (g < total) {
-            off[g] = run;
             if (kSeg) {
                 vm[run] = 0u;
                 vm[run + 1] = h[k];
-                dir[g] = make_uint2(run - 2u * (uint32_t)g, h[k]);
             }
             run += h[k] + (kSeg ? 2u : 0u);
             if (g == total - 1) off[total] = run;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int idx = j * kThreads + (int)threadIdx.x;
+        const int64_t g = tbase + idx;
+        if (g < total) {
+            const uint32_t o = s_o[lds(idx)];
+            off[g] = o;
+            if (kSeg) dir[g] = make_uint2(o - 2u * (uint32_t)g, s_h[lds(idx)]);
         }
     }
 }

@@ -93,13 +93,20 @@ __host__ __device__ double det3(const double M[3][3])
 
 // Orthogonal polar factor of a well-conditioned 3x3 matrix by the scaled
 // Newton iteration X <- (g X + X^{-T} / g) / 2 (Frobenius-norm scaling while
-// far from convergence).  Returns false when X becomes singular or the
-// iteration does not settle; the caller then uses the SVD.
+// far from convergence).  X starts as A / ||A||_F (the polar factor does not
+// change), so every quantity is of order one and the scale g, which only
+// speeds convergence, is computed in float32.  Returns false when X becomes
+// singular or the iteration does not settle; the caller then uses the SVD.
 __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
 {
     double X[3][3];
+    double na = 0.0;
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) X[i][j] = A[i][j];
+        for (int j = 0; j < 3; ++j) na += A[i][j] * A[i][j];
+    if (!(na > 0.0)) return false;
+    const double inv = 1.0 / sqrt(na);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X[i][j] = A[i][j] * inv;
     bool scale = true;
     for (int it = 0; it < 24; ++it) {
         double C[3][3];   // cofactors: X^{-T} = C / det
@@ -120,7 +127,7 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
                 nx += X[i][j] * X[i][j];
                 nc += C[i][j] * C[i][j];
             }
-        const double g = scale ? sqrt(sqrt(nc) / (det * sqrt(nx))) : 1.0;
+        const double g = scale ? (double)sqrtf(sqrtf((float)nc) / ((float)det * sqrtf((float)nx))) : 1.0;
         const double a = 0.5 * g, b = 0.5 / (g * det);
         double diff = 0.0;
         for (int i = 0; i < 3; ++i)
@@ -130,7 +137,9 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
                 X[i][j] = v;
             }
         if (diff < 1e-4) scale = false;
-        if (diff < 1e-24) {   // quadratic convergence: the step just taken is accurate to rounding
+        // quadratic convergence: after a step of size below 1e-8 the new
+        // iterate is within rounding of the polar factor
+        if (diff < 1e-16) {
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) Q[i][j] = X[i][j];
             return true;
@@ -139,7 +148,8 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
     return false;
 }
 
-// Moments about the centre c (see k_moments); returns false (pose untouched)
+// Moments about the centre c (sum p, sum q, sum p q^T, sum |p|^2, sum |q|^2,
+// sum d, count); returns false (pose untouched)
 // when H has rank < 2: its second singular value is below 1e-12 of the first
 // or below the rounding floor of the one-pass sums, 1e-13 sqrt(sum|p|^2 sum|q|^2)
 // (taken about c), so that a cross-covariance made of rounding noise (e.g.
@@ -188,9 +198,10 @@ __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[
 }
 
 constexpr int kWave = 64;
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 256;
 constexpr int kSolveWaves = kSolveThreads / kWave;
-constexpr int kFbWindow = 8 * kSolveThreads;   // queries per pass over the global-search list
+constexpr int kFbWindow = 32 * kSolveThreads;   // queries per pass over the global-search list
+constexpr int kFoldBatch = 32;                  // fold-unit loads in flight per thread
 
 // Adds the moments of one correspondence (p, q about the centre c, squared
 // distance d) to a[].
@@ -212,15 +223,14 @@ __device__ __forceinline__ void add_moments(double* a, float px, float py, float
     a[18] += 1.0;
 }
 
-// One block per pair.  (1) The pair's folded partials of its search blocks
-// (moment-major, stride = number of fold units), each thread a fixed subset
-// in unit order.  (2) Queries resolved by the global search: their
-// list is in arbitrary order, so it is replayed in windows of kFbWindow
-// source indices through an LDS bitmap, and each thread adds the
-// correspondences of its own 8 indices per window in index order.  (3) A
-// fixed-order block reduction, then the solve of Eq. 1 and the iteration
-// bookkeeping on one lane.  Everything the block reads early is requested
-// before its first use, so the loads overlap.
+// One block per pair.  (1) Thread j < 19 sums moment j of the pair's fold
+// units (moment-major, stride nunits) in unit order, kFoldBatch loads in
+// flight; two more threads sum the counters.  (2) Queries resolved by the
+// global search, when there are any: their list is in arbitrary order, so it
+// is replayed in windows of kFbWindow source indices through an LDS bitmap;
+// each thread adds the correspondences of its own 32 indices per window in
+// index order, and a fixed-order block reduction adds them to (1).  (3) The
+// solve of Eq. 1 and the iteration bookkeeping on one lane.
 __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const PairDev* __restrict__ pd, const int32_t* __restrict__ fold_begin, int32_t nunits,
     const double* __restrict__ fpart, const unsigned long long* __restrict__ fctr, PairState* __restrict__ st,
@@ -231,9 +241,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop,
     double eps)
 {
-    __shared__ double red[kMoments][kSolveWaves];
     __shared__ double tot[kMoments];
-    __shared__ unsigned long long cred[2][kSolveWaves];
+    __shared__ unsigned long long ctot[2];
+    __shared__ double red[kMoments][kSolveWaves];
     __shared__ uint32_t wbits[kFbWindow / 32];
     __shared__ uint32_t wslot[kFbWindow];
     const int pair = blockIdx.x;
@@ -241,27 +251,40 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const PairDev& P = pd[pair];
     const int done = S.done;
     const int32_t u0 = fold_begin[pair], u1 = fold_begin[pair + 1];
-    double Rt[12];
-#pragma unroll
-    for (int j = 0; j < 12; ++j) Rt[j] = S.Rt[j];
-    const double cen[3] = {P.cx, P.cy, P.cz};
     const int32_t nfb = fb_count[pair];
     const double prev = S.prev_rmse;
     if (done) return;   // uniform over the block
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    double acc[kMoments];
+    if (threadIdx.x < kMoments) {
+        const double* row = fpart + (int64_t)threadIdx.x * nunits;
+        double sm = 0.0;
+        for (int32_t u = u0; u < u1; u += kFoldBatch) {
+            double v[kFoldBatch];
 #pragma unroll
-    for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
-    unsigned long long c0 = 0, c1 = 0;
-    for (int32_t u = u0 + threadIdx.x; u < u1; u += kSolveThreads) {
+            for (int i = 0; i < kFoldBatch; ++i) v[i] = (u + i < u1) ? row[u + i] : 0.0;
 #pragma unroll
-        for (int j = 0; j < kMoments; ++j) acc[j] += fpart[(int64_t)j * nunits + u];
-        c0 += fctr[u];
-        c1 += fctr[(int64_t)nunits + u];
+            for (int i = 0; i < kFoldBatch; ++i) sm += v[i];
+        }
+        tot[threadIdx.x] = sm;
+    } else if (threadIdx.x < kMoments + 2) {
+        const unsigned long long* row = fctr + (int64_t)(threadIdx.x - kMoments) * nunits;
+        unsigned long long sm = 0;
+        for (int32_t u = u0; u < u1; u += kFoldBatch) {
+            unsigned long long v[kFoldBatch];
+#pragma unroll
+            for (int i = 0; i < kFoldBatch; ++i) v[i] = (u + i < u1) ? row[u + i] : 0ull;
+#pragma unroll
+            for (int i = 0; i < kFoldBatch; ++i) sm += v[i];
+        }
+        ctot[threadIdx.x - kMoments] = sm;
     }
-    if (nfb > 0) {
+    const double cen[3] = {P.cx, P.cy, P.cz};
+    if (nfb > 0) {   // uniform over the block
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        double acc[kMoments];
+#pragma unroll
+        for (int j = 0; j < kMoments; ++j) acc[j] = 0.0;
         for (int64_t w0 = 0; w0 < P.m; w0 += kFbWindow) {
-            for (int e = threadIdx.x; e < kFbWindow / 32; e += kSolveThreads) wbits[e] = 0u;
+            wbits[threadIdx.x] = 0u;
             __syncthreads();
             for (int32_t e = threadIdx.x; e < nfb; e += kSolveThreads) {
                 const int64_t r = (int64_t)fb_list[P.p_base + e] - w0;
@@ -271,11 +294,11 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
                 }
             }
             __syncthreads();
-            uint32_t bits = (wbits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 8)) & 0xFFu;
+            uint32_t bits = wbits[threadIdx.x];
             while (bits) {
                 const int u = __ffs(bits) - 1;
                 bits &= bits - 1u;
-                const int r = 8 * (int)threadIdx.x + u;
+                const int r = 32 * (int)threadIdx.x + u;
                 const unsigned long long key = fb_key[P.p_base + wslot[r]];
                 const uint32_t j = (uint32_t)(key & 0xFFFFFFFFull);
                 if (j >= (uint64_t)P.n) {   // unresolved global search (never expected)
@@ -288,40 +311,22 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
             }
             __syncthreads();
         }
-    }
-    // waves that hold nothing (no fold unit, no global-search query) skip the
-    // reduction: their sums are exact zeros
-    const bool has = (int64_t)u0 + (int64_t)w * kWave < (int64_t)u1 || nfb > 0;
-    if (has) {
 #pragma unroll
         for (int j = 0; j < kMoments; ++j) {
             const double sm = wave_sum_f64(acc[j]);
             if (lane == 0) red[j][w] = sm;
         }
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            c0 += __shfl_xor(c0, d, kWave);
-            c1 += __shfl_xor(c1, d, kWave);
-        }
-    } else if (lane == 0) {
-        for (int j = 0; j < kMoments; ++j) red[j][w] = 0.0;
-    }
-    if (lane == 0) {
-        cred[0][w] = has ? c0 : 0ull;
-        cred[1][w] = has ? c1 : 0ull;
-    }
-    __syncthreads();
-    if (threadIdx.x < kMoments) {
-        double sm = red[threadIdx.x][0];
+        __syncthreads();
+        if (threadIdx.x < kMoments) {
+            double sm = tot[threadIdx.x];
 #pragma unroll
-        for (int q = 1; q < kSolveWaves; ++q) sm += red[threadIdx.x][q];
-        tot[threadIdx.x] = sm;
+            for (int q = 0; q < kSolveWaves; ++q) sm += red[threadIdx.x][q];
+            tot[threadIdx.x] = sm;
+        }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int q = 1; q < kSolveWaves; ++q) {
-        cred[0][0] += cred[0][q];
-        cred[1][0] += cred[1][q];
-    }
+    double Rt[12];   // written by kabsch only when it succeeds
     const double m = tot[18];
     const double rmse = m > 0.0 ? sqrt(tot[17] / m) : 0.0;
     const bool ok = kabsch(tot, cen, Rt);
@@ -337,8 +342,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     rmse_hist[h] = rmse;
     fb_hist[h] = nfb;
     deg_hist[h] = ok ? 0 : 1;
-    ctr_hist[2 * h] = cred[0][0];
-    ctr_hist[2 * h + 1] = cred[1][0];
+    ctr_hist[2 * h] = ctot[0];
+    ctr_hist[2 * h + 1] = ctot[1];
     fb_count[pair] = 0;
     S.iters = k + 1;
     if (early_stop && k >= 1 && fabs(rmse - prev) < eps) S.done = 1;
