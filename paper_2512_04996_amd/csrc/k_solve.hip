@@ -148,20 +148,88 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
     return false;
 }
 
+// Orthogonal polar factor of A refined from a nearby rotation Q0 (the
+// previous pose's rotation): with M = R^T A, the rotation increment exp([w]x)
+// that makes M symmetric solves (tr(S) I - S) w = 2 axial(skew M) to first
+// order, S = sym(M); it is applied as the Cayley rotation of w (exactly
+// orthogonal), and the step repeats until |w| < 1e-8 (the error then is at
+// rounding: the convergence is quadratic).  Accepted only if the final S is
+// positive definite (so R is the polar factor, not another stationary point)
+// and Q0 was orthogonal; otherwise returns false.
+__host__ __device__ bool polar_refine(const double A[3][3], double fro, const double Q0[3][3], double Q[3][3])
+{
+    double R[3][3], An[3][3];
+    double orth = 0.0;
+    const double ifro = 1.0 / fro;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            R[i][j] = Q0[i][j];
+            An[i][j] = A[i][j] * ifro;
+            const double d = Q0[0][i] * Q0[0][j] + Q0[1][i] * Q0[1][j] + Q0[2][i] * Q0[2][j] - (i == j ? 1.0 : 0.0);
+            orth = fmax(orth, fabs(d));
+        }
+    if (!(orth < 1e-12)) return false;
+    for (int it = 0; it < 8; ++it) {
+        double M[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = R[0][i] * An[0][j] + R[1][i] * An[1][j] + R[2][i] * An[2][j];
+        double S[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) S[i][j] = 0.5 * (M[i][j] + M[j][i]);
+        const double k[3] = {M[2][1] - M[1][2], M[0][2] - M[2][0], M[1][0] - M[0][1]};   // 2 axial(skew M)
+        const double tr = S[0][0] + S[1][1] + S[2][2];
+        // T = tr(S) I - S is symmetric: w = adj(T) k / det T
+        const double t00 = tr - S[0][0], t11 = tr - S[1][1], t22 = tr - S[2][2];
+        const double t01 = -S[0][1], t02 = -S[0][2], t12 = -S[1][2];
+        const double a00 = t11 * t22 - t12 * t12, a01 = t02 * t12 - t01 * t22, a02 = t01 * t12 - t02 * t11;
+        const double a11 = t00 * t22 - t02 * t02, a12 = t01 * t02 - t00 * t12, a22 = t00 * t11 - t01 * t01;
+        const double dT = t00 * a00 + t01 * a01 + t02 * a02;
+        if (!(dT > 0.0)) return false;
+        const double idT = 1.0 / dT;
+        const double w[3] = {(a00 * k[0] + a01 * k[1] + a02 * k[2]) * idT, (a01 * k[0] + a11 * k[1] + a12 * k[2]) * idT,
+                             (a02 * k[0] + a12 * k[1] + a22 * k[2]) * idT};
+        const double w2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        // Cayley rotation of w: I + 2/(1 + |h|^2) (H + H^2), h = w / 2, H = [h]x
+        const double h[3] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2]};
+        const double f = 2.0 / (1.0 + 0.25 * w2);
+        const double Hm[3][3] = {{0.0, -h[2], h[1]}, {h[2], 0.0, -h[0]}, {-h[1], h[0], 0.0}};
+        double D[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double hh = Hm[i][0] * Hm[0][j] + Hm[i][1] * Hm[1][j] + Hm[i][2] * Hm[2][j];
+                D[i][j] = (i == j ? 1.0 : 0.0) + f * (Hm[i][j] + hh);
+            }
+        double Rn[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Rn[i][j] = R[i][0] * D[0][j] + R[i][1] * D[1][j] + R[i][2] * D[2][j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) R[i][j] = Rn[i][j];
+        if (w2 < 1e-16) {
+            const bool pd = S[0][0] > 0.0 && S[0][0] * S[1][1] - S[0][1] * S[0][1] > 0.0 && det3(S) > 0.0;
+            if (!pd) return false;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Q[i][j] = R[i][j];
+            return true;
+        }
+    }
+    return false;
+}
+
 // Moments about the centre c (sum p, sum q, sum p q^T, sum |p|^2, sum |q|^2,
 // sum d, count); returns false (pose untouched)
 // when H has rank < 2: its second singular value is below 1e-12 of the first
 // or below the rounding floor of the one-pass sums, 1e-13 sqrt(sum|p|^2 sum|q|^2)
 // (taken about c), so that a cross-covariance made of rounding noise (e.g.
 // every correspondence on one target point) never yields a rotation.
-__host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12])
+__host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12], const double* Rprev)
 {
     const double m = mom[18];
     if (!(m > 0.0)) return false;
     double pb[3], qb[3], H[3][3];
+    const double im = 1.0 / m;
     for (int a = 0; a < 3; ++a) {
-        pb[a] = mom[a] / m;
-        qb[a] = mom[3 + a] / m;
+        pb[a] = mom[a] * im;
+        qb[a] = mom[3 + a] * im;
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) H[a][b] = mom[6 + 3 * a + b] - m * pb[a] * qb[b];
@@ -169,8 +237,9 @@ __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[
     double R[3][3];
     // R = V U^T is the orthogonal polar factor of H^T (H^T = V S U^T =
     // (V U^T)(U S U^T)); when H is far above the rounding floor and det H is
-    // clearly positive, no reflection fix is needed and the Newton polar
-    // iteration gives it directly
+    // clearly positive, no reflection fix is needed: the polar factor is
+    // refined from the previous rotation (Rprev, row-major, may be null), or
+    // else taken by the Newton polar iteration
     double Ht[3][3], nh = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -178,7 +247,14 @@ __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[
             nh += H[i][j] * H[i][j];
         }
     const double fro = sqrt(nh);
-    const bool fast = fro > 1e6 * floor_ && det3(Ht) > 1e-6 * nh * fro && polar3(Ht, R);
+    const bool well = fro > 1e6 * floor_ && det3(Ht) > 1e-6 * nh * fro;
+    bool fast = false;
+    if (well && Rprev) {
+        const double Q0[3][3] = {{Rprev[0], Rprev[1], Rprev[2]}, {Rprev[3], Rprev[4], Rprev[5]},
+                                 {Rprev[6], Rprev[7], Rprev[8]}};
+        fast = polar_refine(Ht, fro, Q0, R);
+    }
+    if (well && !fast) fast = polar3(Ht, R);
     if (!fast) {
         double U[3][3], sig[3], V[3][3];
         svd3(H, U, sig, V);
@@ -253,6 +329,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const int32_t u0 = fold_begin[pair], u1 = fold_begin[pair + 1];
     const int32_t nfb = fb_count[pair];
     const double prev = S.prev_rmse;
+    double Rp[9];   // the current rotation: the start of the polar refinement
+#pragma unroll
+    for (int j = 0; j < 9; ++j) Rp[j] = threadIdx.x == 0 ? S.Rt[j] : 0.0;
     if (done) return;   // uniform over the block
     if (threadIdx.x < kMoments) {
         const double* row = fpart + (int64_t)threadIdx.x * nunits;
@@ -329,7 +408,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     double Rt[12];   // written by kabsch only when it succeeds
     const double m = tot[18];
     const double rmse = m > 0.0 ? sqrt(tot[17] / m) : 0.0;
-    const bool ok = kabsch(tot, cen, Rt);
+    const bool ok = kabsch(tot, cen, Rt, Rp);
     if (ok) {
         for (int j = 0; j < 12; ++j) {
             S.Rt[j] = Rt[j];

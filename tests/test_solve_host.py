@@ -1,7 +1,10 @@
 """The GPU path's float64 rigid-transform solve, compiled for the host with
 hipcc, against the textbook SVD solution (numpy) on random correspondences,
 reflections, planar and far-from-origin clouds, and against the rank test on
-degenerate inputs (one target point, exactly collinear targets)."""
+degenerate inputs (one target point, exactly collinear targets).  The polar
+factor refined from a starting rotation (the previous pose in the ICP loop)
+must give the same answer from near, far, identity and non-orthogonal
+starts (the last two fall back to the Newton or SVD path)."""
 import ctypes as C
 import os
 import shutil
@@ -29,6 +32,7 @@ def solve_lib(tmp_path_factory):
     subprocess.run(cmd, check=True, capture_output=True)
     L = C.CDLL(out)
     L.vicp_test_kabsch.argtypes = [C.POINTER(C.c_double)] * 3
+    L.vicp_test_kabsch_from.argtypes = [C.POINTER(C.c_double)] * 4
     return L
 
 
@@ -85,3 +89,38 @@ def test_solve_matches_svd_and_detects_rank(solve_lib):
         Rk, tk, _ = kabsch_svd(p, q)
         assert np.abs(out[:9].reshape(3, 3) - Rk).max() < 1e-11, (trial, kind)
         assert np.abs(out[9:] - tk).max() < 1e-11 * max(1.0, np.abs(tk).max()), (trial, kind)
+
+
+def test_refined_solve_matches_svd_from_any_start(solve_lib):
+    rng = np.random.default_rng(1)
+    for trial in range(1200):
+        kind = trial % 6
+        n = int(rng.integers(3, 300))
+        p = rng.standard_normal((3, n)) * rng.uniform(0.01, 10)
+        if kind == 1:
+            p[2] *= 1e-3
+        R = random_rotation(rng.standard_normal(3), rng.uniform(0, np.pi))
+        q = R @ p + rng.standard_normal((3, 1)) + rng.standard_normal((3, n)) * rng.uniform(0, 0.5)
+        if kind == 2:
+            q[0] *= -1                     # mirror image: needs the reflection fix
+        if kind == 3:
+            p, q = p + 100.0, q + 100.0
+        p = p.astype(np.float32).astype(np.float64)
+        q = q.astype(np.float32).astype(np.float64)
+        c = np.round(q.mean(1), 1)
+        Rk, tk, _ = kabsch_svd(p, q)
+        start = trial % 4
+        if start == 0:     # near: within 0.3 rad of the answer
+            R0 = random_rotation(rng.standard_normal(3), rng.uniform(0, 0.3)) @ Rk
+        elif start == 1:
+            R0 = np.eye(3)
+        elif start == 2:   # anywhere
+            R0 = random_rotation(rng.standard_normal(3), rng.uniform(0, np.pi))
+        else:              # not orthogonal: the refinement must refuse it
+            R0 = Rk + rng.standard_normal((3, 3)) * 1e-6
+        out = np.zeros(12)
+        ok = solve_lib.vicp_test_kabsch_from(_p(moments(p, q, c)), _p(c), _p(np.ascontiguousarray(R0).reshape(9)),
+                                             _p(out))
+        assert ok, (trial, kind, start)
+        assert np.abs(out[:9].reshape(3, 3) - Rk).max() < 1e-11, (trial, kind, start)
+        assert np.abs(out[9:] - tk).max() < 1e-11 * max(1.0, np.abs(tk).max()), (trial, kind, start)
