@@ -213,24 +213,28 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         nn_idx[gp] = (int32_t)bj;
         nn_d2[gp] = bd;
     }
-    // counters without atomics: one partial per block
-    __shared__ unsigned long long red[3][kWaves];
-    unsigned long long cw = (sub == 0) ? c : 0u;
-    for (int d = kWave / 2; d > 0; d >>= 1) cw += __shfl_xor(cw, d, kWave);
-    const unsigned long long dw = (unsigned long long)__popcll(__ballot(dil && sub == 0));
+    // Reductions over the block in a fixed order: values live in the lanes
+    // that hold a query (multiples of LPQ), so each row of 16 lanes is summed
+    // with DPP steps of LPQ, 2 LPQ, ... 8 and its total (in lane 16 - LPQ)
+    // goes to LDS; then one thread per entry adds the rows in order.
+    // Counters are exact integers (candidates scanned per row, dilated
+    // lookups and global-search queries per wave by popcount).
+    constexpr int kRows = 4 * kWaves;
+    const int row = w * 4 + (lane >> 4);
+    const bool row_end = (lane & 15) == 16 - LPQ;
+    __shared__ uint32_t cred[kRows];
+    __shared__ uint32_t wred[2][kWaves];
+    const uint32_t cw = row_sum_u32<LPQ>((sub == 0) ? c : 0u);
+    if (row_end) cred[row] = cw;
     if (lane == 0) {
-        red[0][w] = cw;
-        red[1][w] = dw;
-        red[2][w] = (unsigned long long)__popcll(mmask);
+        wred[0][w] = (uint32_t)__popcll(__ballot(dil && sub == 0));
+        wred[1][w] = (uint32_t)__popcll(mmask);
     }
     if (kMom) {
         // moments of this lane's query about the grid centre; zero for lanes
         // that hold no resolved query (selects, so nothing else is read).
-        // Reduction: float64 sums inside each row of 16 lanes (DPP), then
-        // the block's rows in order from LDS.  The two squared norms only
-        // set the solve's rounding floor and are summed in float32; the
-        // count is a popcount.
-        constexpr int kRows = 4 * kWaves;
+        // The two squared norms only set the solve's rounding floor and are
+        // summed in float32; the count is a popcount.
         __shared__ double mred[kMoments - 1][kRows];
         __shared__ uint32_t mcnt[kWaves];
         const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
@@ -249,14 +253,12 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         a[15] = found ? (double)bd : 0.0;
         const float np = (float)(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         const float nq = (float)(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-        const int row = w * 4 + (lane >> 4);
-        const bool row_end = (lane & 15) == 15;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            const double sm = row_sum_f64(a[j]);
+            const double sm = row_sum_f64<LPQ>(a[j]);
             if (row_end) mred[j == 15 ? 17 : j][row] = sm;
         }
-        const float snp = row_sum_f32(np), snq = row_sum_f32(nq);
+        const float snp = row_sum_f32<LPQ>(np), snq = row_sum_f32<LPQ>(nq);
         if (row_end) {
             mred[15][row] = (double)snp;
             mred[16][row] = (double)snq;
@@ -280,7 +282,10 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     if (threadIdx.x >= 32 && threadIdx.x < 35) {
         const int k = threadIdx.x - 32;
         unsigned long long sm = 0;
-        for (int q2 = 0; q2 < kWaves; ++q2) sm += red[k][q2];
+        if (k == 0)
+            for (int r = 0; r < kRows; ++r) sm += cred[r];
+        else
+            for (int q2 = 0; q2 < kWaves; ++q2) sm += wred[k - 1][q2];
         ctr[(int64_t)jb * 3 + k] = sm;
     }
 }
