@@ -62,6 +62,17 @@ __device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, f
     return in;
 }
 
+// The value of lane (this lane xor d): a DPP quad permutation for d = 1, 2
+// (a VALU move), an LDS permute otherwise.
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int d)
+{
+    if (d == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    if (d == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
+    return (uint32_t)__shfl_xor((int)x, d, kWave);
+}
+
+__device__ __forceinline__ float xor_lanes(float x, int d) { return __uint_as_float(xor_lanes(__float_as_uint(x), d)); }
+
 // Selects, not branches: a branch lets the compiler sink the index load into
 // the taken path and then wait for every load in flight.
 __device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj)
@@ -189,22 +200,21 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     if (LPQ > 1) {
 #pragma unroll
         for (int d = 1; d < LPQ; d <<= 1) {
-            const float od = __shfl_xor(bd, d, kWave);
-            const uint32_t oj = (uint32_t)__shfl_xor((int)bj, d, kWave);
+            const float od = xor_lanes(bd, d);
+            const uint32_t oj = xor_lanes(bj, d);
             float ox = 0.0f, oy = 0.0f, oz = 0.0f;
             if (kMom) {
-                ox = __shfl_xor(bx, d, kWave);
-                oy = __shfl_xor(by, d, kWave);
-                oz = __shfl_xor(bz, d, kWave);
+                ox = xor_lanes(bx, d);
+                oy = xor_lanes(by, d);
+                oz = xor_lanes(bz, d);
             }
-            if (od < bd || (od == bd && oj < bj)) {
-                bd = od;
-                bj = oj;
-                if (kMom) {
-                    bx = ox;
-                    by = oy;
-                    bz = oz;
-                }
+            const bool take = od < bd || (od == bd && oj < bj);
+            bd = take ? od : bd;
+            bj = take ? oj : bj;
+            if (kMom) {
+                bx = take ? ox : bx;
+                by = take ? oy : by;
+                bz = take ? oz : bz;
             }
         }
     }
