@@ -58,7 +58,7 @@ def lib():
         L.vicpo_build.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64, u32p, u32p, u32p]
         L.vicpo_dilate.argtypes = [i32p, i64, u32p, u32p, i32, u32p, u32p]
         L.vicpo_nns.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, u32p, u32p,
-                                f32p, f32p, f32p, i64, f32p, i32p, f32p, i64p, i64p]
+                                f32p, f32p, f32p, i64, f32p, i32p, f32p, i64p, i64p, i64p]
         L.vicpo_solve.argtypes = [f32p, f32p, f32p, f32p, f32p, f32p, i32p, i64, f64p, f64p, f64p, i32p]
         L.vicpo_register.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, C.c_float, i32, i32,
                                      C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
@@ -162,6 +162,20 @@ def nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
 
     Returns (idx int32[m], d2 float32[m], n_fallback, candidates_total).
     """
+    idx, d2, F, Ct, _ = _nns(g, q, p, Rt)
+    return idx, d2, F, Ct
+
+
+def nns_counts(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
+    """Counts of one Alg. 4 pass: (queries sent to the global search,
+    candidates scanned by the local searches, queries whose voxel is a
+    dilated one, i.e. whose count word holds Mask(root))."""
+    q, p = _soa(q), _soa(p)
+    _, _, F, Ct, Dl = _nns(g, q, p, Rt)
+    return F, Ct - F * q.shape[1], Dl
+
+
+def _nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
     q, p = _soa(q), _soa(p)
     Rt = np.ascontiguousarray(Rt, np.float32).reshape(12)
     m = p.shape[1]
@@ -169,13 +183,14 @@ def nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
     d2 = np.zeros(max(m, 1), np.float32)
     F = np.zeros(1, np.int64)
     Ct = np.zeros(1, np.int64)
+    Dl = np.zeros(1, np.int64)
     qs, ps = _rows(q), _rows(p)
     rc = lib().vicpo_nns(*(_p(a, C.c_float) for a in qs), q.shape[1], _p(g.origin, C.c_float), C.c_float(g.inv),
                          _p(g.dims, C.c_int32), _p(g.off, C.c_uint32), _p(g.vm, C.c_uint32),
                          *(_p(a, C.c_float) for a in ps), m, _p(Rt, C.c_float), _p(idx, C.c_int32),
-                         _p(d2, C.c_float), _p(F, C.c_int64), _p(Ct, C.c_int64))
+                         _p(d2, C.c_float), _p(F, C.c_int64), _p(Ct, C.c_int64), _p(Dl, C.c_int64))
     _check(rc, "nns")
-    return idx[:m], d2[:m], int(F[0]), int(Ct[0])
+    return idx[:m], d2[:m], int(F[0]), int(Ct[0]), int(Dl[0])
 
 
 def solve(p: np.ndarray, q: np.ndarray, idx: np.ndarray, Rt_prev=None):

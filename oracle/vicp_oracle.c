@@ -240,9 +240,9 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
               const uint32_t* off, const uint32_t* vm,
               const float* px, const float* py, const float* pz, int64_t m,
               const float Rt[12], int32_t* nn_idx, float* nn_d2, int64_t* n_fallback,
-              int64_t* cand_total)
+              int64_t* cand_total, int64_t* dilated_total)
 {
-    int64_t F = 0, C = 0;
+    int64_t F = 0, C = 0, Dl = 0;
     for (int64_t i = 0; i < m; ++i) {
         float s[3];
         transform_f32(Rt, px[i], py[i], pz[i], s);
@@ -253,7 +253,9 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
         if (voxel_of(origin, inv, dims, s[0], s[1], s[2], &v)) {
             uint32_t h = vm[off[v] + 1];
             if (h & MASK_BIT) {
+                /* a dilated voxel: its Mask(root) word sends the search to the root */
                 uint32_t root = h & ~MASK_BIT;
+                Dl += 1;
                 seg_head = off[root];
                 count = vm[seg_head + 1];
             } else {
@@ -290,6 +292,7 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
     }
     if (n_fallback) *n_fallback = F;
     if (cand_total) *cand_total = C;
+    if (dilated_total) *dilated_total = Dl;
     return VICPO_OK;
 }
 
@@ -467,7 +470,7 @@ int vicpo_register(const float* qx, const float* qy, const float* qz, int64_t n,
         float Rtf[12];
         for (int a = 0; a < 12; ++a) Rtf[a] = (float)Rt_io[a];
         int64_t F = 0;
-        vicpo_nns(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, idx, d2, &F, NULL);
+        vicpo_nns(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, idx, d2, &F, NULL, NULL);
         double acc = 0.0;
         for (int64_t i = 0; i < m; ++i) acc += (double)d2[i];
         double rmse = sqrt(acc / (double)m);
@@ -609,7 +612,7 @@ int vicpo_p2p(const float* qx, const float* qy, const float* qz, int64_t n,
     for (int a = 0; a < 3; ++a) Rtf[9 + a] = (float)t[a];
     float* d2 = (float*)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1));
     if (!d2) return VICPO_ERR_OOM;
-    vicpo_nns(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, nn_idx, d2, NULL, NULL);
+    vicpo_nns(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, nn_idx, d2, NULL, NULL, NULL);
     free(d2);
     double acc = 0.0, g[6] = {0, 0, 0, 0, 0, 0};
     double sc = m > 0 ? 2.0 / (double)m : 0.0;

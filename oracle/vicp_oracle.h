@@ -27,7 +27,7 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
               const uint32_t* off, const uint32_t* vm,
               const float* px, const float* py, const float* pz, int64_t m,
               const float Rt[12], int32_t* nn_idx, float* nn_d2, int64_t* n_fallback,
-              int64_t* cand_total);
+              int64_t* cand_total, int64_t* dilated_total);
 int vicpo_solve(const float* px, const float* py, const float* pz,
                 const float* qx, const float* qy, const float* qz,
                 const int32_t* idx, int64_t m, const double Rt_prev[12],

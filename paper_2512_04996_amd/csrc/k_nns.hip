@@ -236,8 +236,9 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     __shared__ uint32_t wred[2][kWaves];
     const uint32_t cw = row_sum_u32<LPQ>((sub == 0) ? c : 0u);
     if (row_end) cred[row] = cw;
+    const uint32_t ndil = (uint32_t)__popcll(__ballot(dil && sub == 0));   // whole wave: outside any branch
     if (lane == 0) {
-        wred[0][w] = (uint32_t)__popcll(__ballot(dil && sub == 0));
+        wred[0][w] = ndil;
         wred[1][w] = (uint32_t)__popcll(mmask);
     }
     if (kMom) {

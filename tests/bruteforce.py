@@ -57,21 +57,25 @@ def closed_form_roots(hist, dims, L):
     return roots
 
 
-def nns_rule(q, p, Rt, origin, inv, dims, hist, off, vm):
-    """Alg. 4 with exact float32 rounding, pure Python."""
+def nns_rule(q, p, Rt, origin, inv, dims, hist, off, vm, counts=False):
+    """Alg. 4 with exact float32 rounding, pure Python.  With counts, also
+    returns the candidates scanned by local searches and the number of
+    queries whose voxel holds Mask(root)."""
     q = np.asarray(q, np.float32)
     n = q.shape[1]
-    idx, d2, fb = [], [], 0
+    idx, d2, fb, nloc, ndil = [], [], 0, 0, 0
     for i in range(p.shape[1]):
         s = transform_f32(Rt, p[:, i])
         v = voxel_ids_np(np.array(s, np.float32).reshape(3, 1), origin, inv, dims)[0]
         cand = None
         if v >= 0:
             h = int(vm[off[v] + 1])
+            ndil += 1 if (h & 0x80000000) else 0
             seg = (h & 0x7FFFFFFF) if (h & 0x80000000) else v
             c = int(hist[seg])
             if c > 0:
                 cand = [int(j) for j in vm[off[seg] + 2: off[seg] + 2 + c]]
+                nloc += c
         if cand is None:
             cand = range(n)
             fb += 1
@@ -82,6 +86,8 @@ def nns_rule(q, p, Rt, origin, inv, dims, hist, off, vm):
                 best = (d, j)
         idx.append(best[1])
         d2.append(best[0])
+    if counts:
+        return np.array(idx, np.int32), np.array(d2, np.float32), fb, nloc, ndil
     return np.array(idx, np.int32), np.array(d2, np.float32), fb
 
 

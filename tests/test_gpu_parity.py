@@ -168,6 +168,23 @@ def test_register_with_global_searches_over_several_windows():
         assert np.allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
 
 
+@pytest.mark.parametrize("name", ["bumpy_40k", "room_226k"])
+def test_search_counters_match_oracle(name):
+    # the counters one iteration reports (global searches, candidates scanned
+    # by local searches, lookups through a Mask(root) word) under every
+    # lanes-per-query reduction, bucketed or not
+    P = synth.config(name)
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    og = oracle.dilate(oracle.build_grid(P.q, P.voxel, P.rings), P.rings)
+    Rt0 = random_pose(7, 2.0, 0.03)
+    F, C, D = oracle.nns_counts(og, P.q, P.p, np.asarray(Rt0, np.float32))
+    assert D > 0
+    for sched in ((128, 1, True), (256, 2, False), (256, 4, True), (512, 8, True)):
+        g.set_schedule(sched[0], sched[1], sched[2], 64)
+        r = g.register(dev(P.p), 1, Rt0=np.asarray(Rt0, np.float64), use_graph=False)
+        assert (int(r.fallbacks[0][0]), int(r.candidates[0][0]), int(r.dilated_lookups[0][0])) == (F, C, D), sched
+
+
 def test_register_deterministic_and_graph_equals_eager():
     P = synth.config("bumpy_40k")
     g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)

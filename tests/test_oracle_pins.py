@@ -206,8 +206,12 @@ def test_nns_matches_independent_rule(seed, L):
     g = oracle.dilate(oracle.build_grid(q, 0.3, L), L)
     Rt = np.array([0.98, -0.17, 0.0, 0.17, 0.98, 0.0, 0.0, 0.0, 1.0, 0.02, 0.0, -0.01], np.float32)
     idx, d2, F, _ = oracle.nns(g, q, p, Rt)
-    ridx, rd2, rF = nns_rule(q, p, Rt, g.origin, g.inv, g.dims, g.hist, g.off, g.vm)
+    ridx, rd2, rF, rC, rD = nns_rule(q, p, Rt, g.origin, g.inv, g.dims, g.hist, g.off, g.vm, counts=True)
     assert np.array_equal(idx, ridx) and np.array_equal(d2, rd2) and F == rF
+    # the counts the GPU path reports per iteration
+    assert oracle.nns_counts(g, q, p, Rt) == (rF, rC, rD)
+    if L > 0:
+        assert rD > 0
 
 
 def test_nns_never_beats_exact_and_ties_go_low():
