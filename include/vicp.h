@@ -129,13 +129,33 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz,
                             const vicp_allocator* alloc, hipStream_t stream,
                             vicp_grid** out);
 
+/* As vicp_build_grid on a given grid instead of the target's padded bounding
+ * box: `dims` voxels of edge `voxel` from `origin` (HOST arrays of 3), i.e.
+ * the setting of Sec. IV.A, 2^N voxels per axis over the unit sphere's cube
+ * [-1, 1)^3 for clouds normalised to the unit sphere.  `max_rings` bounds the
+ * rings a later vicp_dilate may apply (it plays the role of pad_rings; the
+ * grid is not padded).  Voxel indices and 1/voxel follow the same float32
+ * arithmetic as every grid.  A rebuild keeps the geometry.  Synchronises the
+ * stream once, to check that every target point lies inside the grid.
+ * Errors: n <= 0, voxel <= 0 or non-finite, non-finite origin, dims < 1,
+ * max_rings < 0, or a target point outside the grid -> INVALID_ARG (the grid
+ * then needs a successful rebuild before use); grid too large ->
+ * GRID_TOO_LARGE. */
+int vicp_build_grid_fixed(const float* qx, const float* qy, const float* qz, int64_t n,
+                          const float origin[3], float voxel, const int32_t dims[3],
+                          int32_t max_rings, const vicp_allocator* alloc,
+                          hipStream_t stream, vicp_grid** out);
+
 /* Refills an existing grid from a new target with the same per-pair point
  * counts (e.g. the next frame of a stream): the bounding box, grid
  * specification, counts, offsets and segments are recomputed exactly as by
  * vicp_build_grid, while allocations, work tables and captured graphs are
  * reused when the voxel counts are unchanged.  The grid is left undilated:
  * call vicp_dilate again.  Synchronises the stream once (bounding box).
- * Errors as vicp_build_grid; STATE for a grid that was never built. */
+ * Errors as vicp_build_grid; STATE for a grid that was never built.  After a
+ * rebuild of a given-geometry grid fails because a target point lies outside
+ * it, every other entry point returns STATE for that grid until a rebuild
+ * succeeds. */
 int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz,
                       hipStream_t stream);
 

@@ -62,6 +62,8 @@ def lib():
         L.vicpo_solve.argtypes = [f32p, f32p, f32p, f32p, f32p, f32p, i32p, i64, f64p, f64p, f64p, i32p]
         L.vicpo_register.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, C.c_float, i32, i32,
                                      C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
+        L.vicpo_register_spec.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64,
+                                          i32, i32, C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
         L.vicpo_se3_exp.argtypes = [f64p, f64p, f64p, f64p]
         L.vicpo_se3_exp.restype = None
         L.vicpo_p2p_loss_fixed.argtypes = [f32p, f32p, f32p, f64p, f64p, f64p, i64, i32p, f64p]
@@ -145,6 +147,34 @@ def build_grid(q: np.ndarray, voxel: float, rings: int) -> Grid:
                            _p(hist, C.c_uint32), _p(off, C.c_uint32), _p(vm, C.c_uint32))
     _check(rc, "build")
     return Grid(origin, np.float32(inv), np.float32(voxel), dims, V, n, hist, off, vm)
+
+
+def fixed_spec(origin, voxel: float, dims):
+    """A given grid (not the target's padded box): origin and dims as given,
+    1/voxel rounded once to float32 as for every grid."""
+    origin = np.ascontiguousarray(origin, np.float32).reshape(3)
+    dims = np.ascontiguousarray(dims, np.int32).reshape(3)
+    inv = np.float32(1.0) / np.float32(voxel)
+    return origin, inv, dims, int(np.prod(dims.astype(np.int64)))
+
+
+def build_grid_fixed(q: np.ndarray, origin, voxel: float, dims) -> Grid:
+    """build_grid on a given grid, e.g. the 2^N voxels per axis over the unit
+    sphere's cube of Sec. IV.A.  Every target point must lie inside it."""
+    q = _soa(q)
+    origin, inv, dims, V = fixed_spec(origin, voxel, dims)
+    n = q.shape[1]
+    hist = np.zeros(V, np.uint32)
+    off = np.zeros(V + 1, np.uint32)
+    vm = np.zeros(n + 2 * V, np.uint32)
+    qx, qy, qz = _rows(q)
+    rc = lib().vicpo_build(_p(qx, C.c_float), _p(qy, C.c_float), _p(qz, C.c_float), n,
+                           _p(origin, C.c_float), C.c_float(inv), _p(dims, C.c_int32), V,
+                           _p(hist, C.c_uint32), _p(off, C.c_uint32), _p(vm, C.c_uint32))
+    if rc == -5:   # VICPO_ERR_INTERNAL: a target point outside the given grid
+        raise ValueError("a target point lies outside the given grid")
+    _check(rc, "build")
+    return Grid(origin, inv, np.float32(voxel), dims, V, n, hist, off, vm)
 
 
 def dilate(g: Grid, rings: int) -> Grid:
@@ -245,6 +275,31 @@ def register(q, p, voxel: float, rings: int, iters: int, rmse_eps: float = 1e-5,
                               C.c_float(voxel), rings, iters, C.c_double(rmse_eps), int(early_stop),
                               _p(Rt, C.c_double), _p(rmse, C.c_double), _p(fb, C.c_int64), _p(done, C.c_int32),
                               _p(deg, C.c_int32), _p(idx, C.c_int32), _p(d2, C.c_float))
+    _check(rc, "register")
+    k = int(done[0])
+    return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])
+
+
+def register_fixed(q, p, origin, voxel: float, dims, rings: int, iters: int, rmse_eps: float = 1e-5,
+                   early_stop: bool = False, Rt0=None) -> IcpResult:
+    """register on a given grid (see build_grid_fixed)."""
+    q, p = _soa(q), _soa(p)
+    origin, inv, dims, V = fixed_spec(origin, voxel, dims)
+    Rt = np.ascontiguousarray(Rt0 if Rt0 is not None else identity_rt(), np.float64).reshape(12).copy()
+    K = max(iters, 1)
+    rmse = np.zeros(K, np.float64)
+    fb = np.zeros(K, np.int64)
+    deg = np.zeros(K, np.int32)
+    done = np.zeros(1, np.int32)
+    m = p.shape[1]
+    idx = np.zeros(max(m, 1), np.int32)
+    d2 = np.zeros(max(m, 1), np.float32)
+    qs, ps = _rows(q), _rows(p)
+    rc = lib().vicpo_register_spec(*(_p(a, C.c_float) for a in qs), q.shape[1], *(_p(a, C.c_float) for a in ps), m,
+                                   _p(origin, C.c_float), C.c_float(inv), _p(dims, C.c_int32), V, rings, iters,
+                                   C.c_double(rmse_eps), int(early_stop), _p(Rt, C.c_double), _p(rmse, C.c_double),
+                                   _p(fb, C.c_int64), _p(done, C.c_int32), _p(deg, C.c_int32), _p(idx, C.c_int32),
+                                   _p(d2, C.c_float))
     _check(rc, "register")
     k = int(done[0])
     return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])

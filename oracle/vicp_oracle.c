@@ -452,6 +452,24 @@ int vicpo_register(const float* qx, const float* qy, const float* qz, int64_t n,
     int64_t V;
     int rc = vicpo_grid_spec(qx, qy, qz, n, voxel, rings, origin, &inv, dims, &V);
     if (rc) return rc;
+    return vicpo_register_spec(qx, qy, qz, n, px, py, pz, m, origin, inv, dims, V, rings, max_iter, rmse_eps,
+                               early_stop, Rt_io, rmse_hist, fb_hist, iters_done, degenerate_hist, nn_idx, nn_d2);
+}
+
+/* The same on a given grid (origin, 1/voxel, dims), e.g. the fixed 2^N grid
+ * over the unit sphere's cube of Sec. IV.A. */
+int vicpo_register_spec(const float* qx, const float* qy, const float* qz, int64_t n,
+                        const float* px, const float* py, const float* pz, int64_t m,
+                        const float origin[3], float inv, const int32_t dims[3], int64_t V,
+                        int32_t rings, int32_t max_iter, double rmse_eps,
+                        int32_t early_stop, double Rt_io[12], double* rmse_hist,
+                        int64_t* fb_hist, int32_t* iters_done, int32_t* degenerate_hist,
+                        int32_t* nn_idx, float* nn_d2)
+{
+    *iters_done = 0;
+    if (m == 0) return VICPO_OK;
+    if (m < 0 || max_iter < 0 || rings < 0) return VICPO_ERR_ARG;
+    int rc = VICPO_OK;
     uint32_t* hist = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)V);
     uint32_t* off = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(V + 1));
     uint32_t* vm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n + 2 * V));

@@ -8,11 +8,11 @@ generation) imports without the built library.
 """
 import importlib
 
-__all__ = ["build_grid", "build_grid_batched", "Grid", "p2p_loss", "P2PLoss", "prof_enable", "prof_read",
+__all__ = ["build_grid", "build_grid_batched", "build_grid_fixed", "Grid", "p2p_loss", "P2PLoss", "prof_enable", "prof_read",
            "prof_reset", "synth", "VicpError"]
 
 _LAZY = {
-    "build_grid": "api", "build_grid_batched": "api", "Grid": "api", "prof_enable": "api", "prof_read": "api",
+    "build_grid": "api", "build_grid_batched": "api", "build_grid_fixed": "api", "Grid": "api", "prof_enable": "api", "prof_read": "api",
     "prof_reset": "api", "p2p_loss": "autograd", "P2PLoss": "autograd", "VicpError": "_lib",
 }
 

@@ -55,6 +55,9 @@ SYMBOLS = {
     "vicp_build_grid_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_int32,
                                           C.POINTER(C.c_float), C.c_int32, C.c_void_p, C.c_void_p,
                                           C.POINTER(C.c_void_p)]),
+    "vicp_build_grid_fixed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_float),
+                                        C.c_float, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_void_p)]),
     "vicp_grid_rebuild": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_dilate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "vicp_nns": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_float),

@@ -227,6 +227,19 @@ def build_grid(q: torch.Tensor, voxel: float, pad_rings: int) -> Grid:
     return Grid(h, q, [q.shape[1]], [voxel], pad_rings)
 
 
+def build_grid_fixed(q: torch.Tensor, origin, voxel: float, dims, max_rings: int) -> Grid:
+    """Alg. 1 + Alg. 2 on a given grid (``dims`` voxels of edge ``voxel`` from
+    ``origin``), e.g. 2^N per axis over [-1, 1)^3 for unit-sphere clouds."""
+    q = _soa(q, "q")
+    o = (C.c_float * 3)(*[float(v) for v in origin])
+    d = (C.c_int32 * 3)(*[int(v) for v in dims])
+    h = C.c_void_p()
+    qx, qy, qz = _ptrs(q)
+    check(lib().vicp_build_grid_fixed(qx, qy, qz, q.shape[1], o, C.c_float(voxel), d, int(max_rings), None,
+                                      _stream(), C.byref(h)), "vicp_build_grid_fixed")
+    return Grid(h, q, [q.shape[1]], [voxel], max_rings)
+
+
 def build_grid_batched(q: torch.Tensor, n_per_pair, voxels, pad_rings: int) -> Grid:
     """Alg. 1 + Alg. 2 on several targets concatenated along the point axis."""
     q = _soa(q, "q")

@@ -379,6 +379,11 @@ struct vicp_grid {
     void* h_res = nullptr;
     size_t h_res_cap = 0;
     uint32_t* h_box = nullptr;   // pinned: per-block bounding-box partials read back by each build
+    // a given grid geometry (single pair) instead of the target's padded box
+    bool fixed = false;
+    bool usable = true;   // false after a build whose target did not fit the given grid
+    float f_origin[3] = {0, 0, 0};
+    int32_t f_dims[3] = {0, 0, 0};
     std::vector<BlockJob> h_jobs_q8;
     void* staging = nullptr;
     int32_t* fb_count = nullptr;
@@ -633,6 +638,7 @@ int check_grid(const vicp_grid* g)
 {
     if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
     if (!g->hist) return fail(VICP_ERR_STATE, "grid not built");
+    if (!g->usable) return fail(VICP_ERR_STATE, "the last build failed: rebuild the grid first");
     return VICP_OK;
 }
 
@@ -707,6 +713,23 @@ int grid_spec(PairHost& h, const float lo[3], const float hi[3], float voxel, in
     return VICP_OK;
 }
 
+// A given grid: origin and dims as given, 1/voxel rounded once.
+int fixed_grid_spec(PairHost& h, const float origin[3], const int32_t dims[3], float voxel)
+{
+    int64_t V = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.origin[a] = origin[a];
+        h.dims[a] = dims[a];
+        V *= dims[a];
+    }
+    if (V >= (int64_t)1 << 31) return fail(VICP_ERR_GRID_TOO_LARGE, "grid has 2^31 voxels or more");
+    if (h.n + 2 * V >= (int64_t)1 << 32) return fail(VICP_ERR_GRID_TOO_LARGE, "n + 2V does not fit 32-bit offsets");
+    h.inv = 1.0f / voxel;
+    h.voxel = voxel;
+    h.V = V;
+    return VICP_OK;
+}
+
 float unordered(uint32_t k)
 {
     const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
@@ -720,6 +743,14 @@ float unordered(uint32_t k)
 int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
     const int B = g->B;
+    std::vector<PairHost> pairs = g->pairs;
+    int64_t Vt = 0, words = 0;
+    if (g->fixed) {
+        int rc = fixed_grid_spec(pairs[0], g->f_origin, g->f_dims, g->voxels[0]);
+        if (rc) return rc;
+        Vt = pairs[0].V;
+        words = pairs[0].n + 2 * pairs[0].V;
+    } else {
     {
         ProfScope ps("aabb", s, false);
         launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
@@ -743,8 +774,6 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         for (int f = 0; f < 3; ++f) d[f] = std::min(d[f], b[f]);
         for (int f = 3; f < 7; ++f) d[f] = std::max(d[f], b[f]);
     }
-    std::vector<PairHost> pairs = g->pairs;
-    int64_t Vt = 0, words = 0;
     for (int p = 0; p < B; ++p) {
         const uint32_t* b = &hbox[8 * p];
         if (b[6]) return fail(VICP_ERR_NONFINITE, "non-finite target coordinates");
@@ -759,6 +788,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         pairs[p].vm_base = words;
         Vt += pairs[p].V;
         words += pairs[p].n + 2 * pairs[p].V;
+    }
     }
     if (Vt >= ((int64_t)1 << 31) || words >= ((int64_t)1 << 32))
         return fail(VICP_ERR_GRID_TOO_LARGE, "batch exceeds 2^31 voxels or 2^32 index words");
@@ -812,6 +842,15 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         ProfScope ps("count", s, false);
         launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, s);
     }
+    if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
+        uint32_t herr = 0;
+        VICP_HIP(hipMemcpyAsync(&herr, g->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        VICP_HIP(hipStreamSynchronize(s));
+        if (herr) {
+            g->usable = false;   // until a successful rebuild
+            return fail(VICP_ERR_INVALID_ARG, "a target point lies outside the given grid");
+        }
+    }
     {
         ProfScope ps("scan", s, false);
         launch_scan(g->hist, Vt, g->off, g->vm, g->dir, g->scan_status, g->scan_ticket, s);
@@ -827,6 +866,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e));
+    g->usable = true;
     return VICP_OK;
 }
 
@@ -855,9 +895,16 @@ const char* vicp_status_str(int code)
     }
 }
 
-int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, const int64_t* n_per_pair, int32_t npairs,
-                            const float* voxel_per_pair, int32_t pad_rings, const vicp_allocator* alloc,
-                            hipStream_t s, vicp_grid** out)
+namespace {
+
+struct FixedGrid {
+    float origin[3];
+    int32_t dims[3];
+};
+
+int build_grid_impl(const float* qx, const float* qy, const float* qz, const int64_t* n_per_pair, int32_t npairs,
+                    const float* voxel_per_pair, int32_t pad_rings, const vicp_allocator* alloc, hipStream_t s,
+                    vicp_grid** out, const FixedGrid* fixed)
 {
     (void)hipGetLastError();   // an error left by other code is not ours to report
     if (!out) return fail(VICP_ERR_INVALID_ARG, "null output");
@@ -881,6 +928,13 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, c
     vicp_grid* g = new vicp_grid();
     g->B = npairs;
     g->pad = pad_rings;
+    if (fixed) {
+        g->fixed = true;
+        for (int a = 0; a < 3; ++a) {
+            g->f_origin[a] = fixed->origin[a];
+            g->f_dims[a] = fixed->dims[a];
+        }
+    }
     g->n_total = nt;
     g->pairs = pairs;
     g->voxels.assign(voxel_per_pair, voxel_per_pair + npairs);
@@ -925,17 +979,41 @@ int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, c
     return VICP_OK;
 }
 
+}  // namespace
+
+int vicp_build_grid_batched(const float* qx, const float* qy, const float* qz, const int64_t* n_per_pair, int32_t npairs,
+                            const float* voxel_per_pair, int32_t pad_rings, const vicp_allocator* alloc,
+                            hipStream_t s, vicp_grid** out)
+{
+    return build_grid_impl(qx, qy, qz, n_per_pair, npairs, voxel_per_pair, pad_rings, alloc, s, out, nullptr);
+}
+
 int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n, float voxel, int32_t pad_rings,
                     const vicp_allocator* alloc, hipStream_t s, vicp_grid** out)
 {
-    return vicp_build_grid_batched(qx, qy, qz, &n, 1, &voxel, pad_rings, alloc, s, out);
+    return build_grid_impl(qx, qy, qz, &n, 1, &voxel, pad_rings, alloc, s, out, nullptr);
+}
+
+int vicp_build_grid_fixed(const float* qx, const float* qy, const float* qz, int64_t n, const float origin[3],
+                          float voxel, const int32_t dims[3], int32_t max_rings, const vicp_allocator* alloc,
+                          hipStream_t s, vicp_grid** out)
+{
+    if (!origin || !dims) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    FixedGrid fg;
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(origin[a])) return fail(VICP_ERR_INVALID_ARG, "origin must be finite");
+        if (dims[a] < 1) return fail(VICP_ERR_INVALID_ARG, "dims must be >= 1");
+        fg.origin[a] = origin[a];
+        fg.dims[a] = dims[a];
+    }
+    return build_grid_impl(qx, qy, qz, &n, 1, &voxel, max_rings, alloc, s, out, &fg);
 }
 
 int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
     (void)hipGetLastError();   // an error left by other code is not ours to report
-    int rc = check_grid(g);
-    if (rc) return rc;
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (!g->hist) return fail(VICP_ERR_STATE, "grid not built");
     if (!qx || !qy || !qz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     return grid_fill(g, qx, qy, qz, s);
 }

@@ -1,0 +1,95 @@
+"""GPU parity in the paper's own setting (Sec. IV.A): clouds normalised to
+the unit sphere, a fixed grid of 2^N voxels per axis over [-1, 1)^3 with
+N = 4, L = 10 dilation rings, up to 50 iterations with the RMSE-difference
+stop at 1e-5.  Grids and dilation bit-exact with the oracle on the same
+given grid; registration against the oracle's; the static footprint equals
+Table 1's 0.03125 MiB."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_04996_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2512_04996_amd._lib import ERR_INVALID_ARG, VicpError  # noqa: E402
+from paper_2512_04996_amd.api import build_grid_fixed  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ROT_TOL = 1e-5
+T_TOL = 1e-6
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rot_angle(R1, R2):
+    R1 = np.asarray(R1).reshape(3, 3)
+    R2 = np.asarray(R2).reshape(3, 3)
+    return float(np.arccos(np.clip((np.trace(R1.T @ R2) - 1) / 2, -1.0, 1.0)))
+
+
+def small_room():
+    return synth.normalize_unit_sphere(synth.room_pair(seed=5, n=30000, m=25000, voxel=0.05, rings=3, iters=20),
+                                       "paper_room_30k")
+
+
+CASES = {"paper_bunny_40k": lambda: synth.config("paper_bunny_40k"), "paper_room_30k": small_room}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fixed_grid_and_dilation_bit_exact(name):
+    P = CASES[name]()
+    o, d = P.meta["grid_origin"], P.meta["grid_dims"]
+    g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings)
+    og = oracle.build_grid_fixed(P.q, o, P.voxel, d)
+    hist, off, vm = g.export(0)
+    assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm)
+    g.dilate(P.rings)
+    oracle.dilate(og, P.rings)
+    hist, off, vm = g.export(0)
+    assert np.array_equal(vm, og.vm)
+    desc = g.describe()
+    assert desc["V"] == 4096 and list(desc["dims"]) == [16, 16, 16] and desc["rings_applied"] == 10
+    t = json.load(open(os.path.join(GOLDEN, "table1_memory.json")))
+    assert desc["static_bytes"] / 2 ** 20 == t["static_mb"]          # Table 1 note 1: 0.03125 MB
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_paper_setting_registration_matches_oracle(name, use_graph):
+    P = CASES[name]()
+    o, d = P.meta["grid_origin"], P.meta["grid_dims"]
+    g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings).dilate(P.rings)
+    res = g.register(dev(P.p), P.iters, rmse_eps=P.meta["rmse_eps"], early_stop=True, use_graph=use_graph)
+    ref = oracle.register_fixed(P.q, P.p, o, P.voxel, d, P.rings, P.iters, P.meta["rmse_eps"], True)
+    assert int(res.iters[0]) == ref.iters and ref.iters < P.iters
+    assert list(res.fallbacks[0]) == list(ref.fallbacks)
+    np.testing.assert_allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
+    assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+    assert np.linalg.norm(res.Rt[9:] - ref.Rt[9:]) <= T_TOL * 2.0   # the unit sphere's extent
+
+
+def test_target_outside_the_fixed_grid_is_an_error_and_rebuild_recovers():
+    P = synth.config("paper_bunny_40k")
+    o, d = P.meta["grid_origin"], P.meta["grid_dims"]
+    bad = P.q.copy()
+    bad[1, 123] = np.float32(1.0)                                      # on the far face: outside [-1, 1)
+    with pytest.raises(VicpError) as e:
+        build_grid_fixed(dev(bad), o, P.voxel, d, P.rings)
+    assert e.value.code == ERR_INVALID_ARG
+    g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings)
+    with pytest.raises(VicpError):
+        g.rebuild(dev(bad))
+    g.rebuild(dev(P.q)).dilate(P.rings)                                # a good target makes it usable again
+    og = oracle.dilate(oracle.build_grid_fixed(P.q, o, P.voxel, d), P.rings)
+    assert np.array_equal(g.export(0)[2], og.vm)

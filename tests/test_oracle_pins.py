@@ -474,3 +474,40 @@ def test_dynamic_bytes_counts_two_header_words_per_voxel():
     q = synth.tiny_cloud(120, 500)
     g = oracle.build_grid(q, 0.2, 1)
     assert oracle.dynamic_bytes(g.n, g.V) == 4 * len(g.vm) == 4 * int(g.off[-1])
+
+
+# ---- the paper's own setting (Sec. IV.A): unit sphere, 2^N grid, L = 10 ----
+
+def test_fixed_grid_matches_independent_voxelisation_and_table1_static():
+    P = synth.config("paper_bunny_40k")
+    origin, dims = P.meta["grid_origin"], P.meta["grid_dims"]
+    g = oracle.build_grid_fixed(P.q, origin, P.voxel, dims)
+    assert g.V == 16 ** 3 and float(g.inv) == 8.0
+    vid = voxel_ids_np(P.q, g.origin, g.inv, g.dims)
+    assert (vid >= 0).all()
+    assert np.array_equal(g.hist, np.bincount(vid, minlength=g.V).astype(np.uint32))
+    _, off, vm = segments_np(P.q, g.origin, g.inv, g.dims, g.V)
+    assert np.array_equal(g.off, off) and np.array_equal(g.vm, vm)
+    # Table 1 note 1: the static footprint of the N = 4 grid
+    t = json.load(open(os.path.join(GOLDEN, "table1_memory.json")))
+    assert oracle.paper_static_bytes(g.V) / 2 ** 20 == t["static_mb"]
+
+
+def test_fixed_grid_rejects_a_target_outside():
+    q = synth.tiny_cloud(40, 100) * np.float32(0.5)
+    q[0, 7] = np.float32(1.0)                     # on the far face: floor((1 + 1) * 8) = 16 is outside
+    with pytest.raises(ValueError):
+        oracle.build_grid_fixed(q, (-1.0, -1.0, -1.0), 0.125, (16, 16, 16))
+
+
+def test_paper_setting_registration_converges_and_stops_early():
+    P = synth.config("paper_bunny_40k")
+    r = oracle.register_fixed(P.q, P.p, P.meta["grid_origin"], P.voxel, P.meta["grid_dims"], P.rings, P.iters,
+                              P.meta["rmse_eps"], True)
+    assert 2 <= r.iters < P.iters                   # the RMSE-difference rule ends it
+    assert abs(r.rmse[-1] - r.rmse[-2]) < P.meta["rmse_eps"]
+    assert r.rmse[-1] < r.rmse[0]
+    # the same grid taken through the generic entry (explicit spec) gives the same registration
+    g = oracle.dilate(oracle.build_grid_fixed(P.q, P.meta["grid_origin"], P.voxel, P.meta["grid_dims"]), P.rings)
+    idx, d2, F, _ = oracle.nns(g, P.q, P.p, np.asarray(r.Rt, np.float32))
+    assert F == 0
