@@ -223,6 +223,41 @@ def extra_figures(api, synth, torch, dev, np):
         sizes[name] = {"V": d["V"], "dynamic_bytes": d["dynamic_bytes"], "static_bytes": d["static_bytes"],
                        "vanicp_fixed_bytes": d["vanicp_bytes"],
                        "saving": round(1 - (d["dynamic_bytes"] + d["static_bytes"]) / d["vanicp_bytes"], 6)}
+    # the paper's own setting: unit-sphere clouds, 2^4 voxels per axis, L = 10,
+    # up to 50 iterations with the RMSE-difference stop; a step is the grid
+    # refill, the dilation and the registration
+    log("[bench] paper setting")
+    paper = {}
+    for name in ("paper_bunny_40k", "paper_room_226k"):
+        Pw = synth.config(name)
+        qd = torch.from_numpy(Pw.q).to(dev)
+        pd_ = torch.from_numpy(Pw.p).to(dev)
+        g = api.build_grid_fixed(qd, Pw.meta["grid_origin"], Pw.voxel, Pw.meta["grid_dims"], Pw.rings)
+        g.dilate(Pw.rings)
+        g.autotune(pd_, searches_per_plan=Pw.iters)
+
+        def run():
+            g.rebuild(qd)
+            g.dilate(Pw.rings)
+            return g.register(pd_, Pw.iters, rmse_eps=Pw.meta["rmse_eps"], early_stop=True, use_graph=True)
+
+        for _ in range(2):
+            r = run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            r = run()
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / 5
+        d = g.describe()
+        k = int(r.iters[0])
+        paper[name] = {"iters": k, "ms": round(tp * 1e3, 3), "queries_per_s": round(k * Pw.m / tp, 1),
+                       "schedule": g.schedule, "V": d["V"], "static_bytes": d["static_bytes"],
+                       "static_mib": d["static_bytes"] / 2 ** 20, "dynamic_bytes": d["dynamic_bytes"],
+                       "candidates_per_query": round(float(np.mean(r.candidates[0][:k])) / Pw.m, 1),
+                       "final_rmse": float(r.rmse[0][k - 1])}
+        g.free()
+    ex["paper_setting"] = paper
     # batched: 64 uneven pairs in one launch sequence, against a loop of single-pair runs
     log("[bench] batched workload")
     pairs = synth.config("batched_64")
