@@ -96,6 +96,8 @@ typedef struct vicp_icp_opts {
     double rmse_eps;    /* stop when |RMSE_k - RMSE_{k-1}| < rmse_eps (k >= 1) ... */
     int32_t early_stop; /* ... only if non-zero; 0 runs exactly K iterations */
     int32_t use_graph;  /* non-zero: capture the K iterations once in a hipGraph and replay it */
+    int32_t global_only; /* non-zero: every query takes the exact global search (ICP with exhaustive
+                            NNS, the "Brute" comparator of Table 2); the grid is not consulted */
 } vicp_icp_opts;
 
 /* Per-pair registration statistics.  The arrays are caller-owned HOST arrays

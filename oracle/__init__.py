@@ -11,6 +11,7 @@ file carries the details and the readings of the paper.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -303,6 +304,38 @@ def register_fixed(q, p, origin, voxel: float, dims, rings: int, iters: int, rms
     _check(rc, "register")
     k = int(done[0])
     return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])
+
+
+def register_global(q, p, iters: int, rmse_eps: float = 1e-5, early_stop: bool = False, Rt0=None) -> IcpResult:
+    """ICP with the exact global search for every query, the exhaustive-NNS
+    ("Brute") comparator of Table 2: the loop of register with Alg. 4 given
+    a one-voxel grid that no point reaches, so every query takes the exact
+    global search (same float32 distance, lowest index on ties)."""
+    q, p = _soa(q), _soa(p)
+    n, m = q.shape[1], p.shape[1]
+    far = np.float32(1e30)
+    g = Grid(np.array([far, far, far], np.float32), np.float32(1.0), np.float32(1.0), np.ones(3, np.int32), 1, n,
+             np.zeros(1, np.uint32), np.array([0, 2], np.uint32), np.zeros(n + 2, np.uint32))
+    Rt = np.ascontiguousarray(Rt0 if Rt0 is not None else identity_rt(), np.float64).reshape(12).copy()
+    rmse, fb, deg = [], [], []
+    idx = np.zeros(0, np.int32)
+    d2 = np.zeros(0, np.float32)
+    prev = 0.0
+    for k in range(iters):
+        idx, d2, F, _ = nns(g, q, p, Rt.astype(np.float32))
+        acc = 0.0
+        for v in d2.astype(np.float64):   # sequential, as the C loop
+            acc += v
+        r = math.sqrt(acc / m)
+        Rt, _, dg = solve(p, q, idx, Rt)
+        rmse.append(r)
+        fb.append(F)
+        deg.append(int(dg))
+        if early_stop and k >= 1 and abs(r - prev) < rmse_eps:
+            break
+        prev = r
+    k = len(rmse)
+    return IcpResult(Rt, np.array(rmse), np.array(fb, np.int64), np.array(deg, np.int32), k, idx, d2)
 
 
 def se3_exp(xi):

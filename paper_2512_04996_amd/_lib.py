@@ -40,7 +40,7 @@ class GridDesc(C.Structure):
 
 class IcpOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("rmse_eps", C.c_double), ("early_stop", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("global_only", C.c_int32)]
 
 
 class IcpStats(C.Structure):

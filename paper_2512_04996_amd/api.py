@@ -142,7 +142,8 @@ class Grid:
 
     # -- the ICP loop
     def register(self, p: torch.Tensor, max_iter: int, rmse_eps: float = 1e-5, early_stop: bool = False,
-                 use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False) -> IcpResult:
+                 use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False,
+                 global_only: bool = False) -> IcpResult:
         p = _soa(p, "p")
         m = p.shape[1]
         B = self.npairs
@@ -166,7 +167,7 @@ class Grid:
             stats[b].fallbacks = fbk[b].ctypes.data_as(C.POINTER(C.c_int64))
             stats[b].candidates = cnd[b].ctypes.data_as(C.POINTER(C.c_int64))
             stats[b].dilated_lookups = dil[b].ctypes.data_as(C.POINTER(C.c_int64))
-        opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)))
+        opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)), int(bool(global_only)))
         px, py, pz = _ptrs(p)
         rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
                                          rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())

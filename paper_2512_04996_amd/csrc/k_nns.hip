@@ -120,7 +120,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
                                                   int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
-                                                  unsigned long long* __restrict__ ctr, double* __restrict__ part)
+                                                  unsigned long long* __restrict__ ctr, double* __restrict__ part,
+                                                  int all_global)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
     constexpr int kWaves = BS / kWave;
@@ -153,7 +154,9 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         }
         transform(S.Rtf, x, y, z, sx, sy, sz);
         uint32_t v;
-        if (voxel_of(P, sx, sy, sz, v)) {
+        // all_global: every query takes the exact global search (the
+        // exhaustive-NNS comparator)
+        if (!all_global && voxel_of(P, sx, sy, sz, v)) {
             const uint2 e = dir[P.v_base + v];
             c = e.y & ~kMask;
             cs = e.x;
@@ -545,12 +548,12 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
                       const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
                       uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      hipStream_t s)
+                      int all_global, hipStream_t s)
 {
     if (njobs <= 0) return;
 #define VICP_NNS(BS, L, SORTED, MOM)                                                                                 \
     launch_timed(k_nns_local<BS, L, SORTED, MOM>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, ps4, st, dir,  \
-                 qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part)
+                 qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global)
 #define VICP_NNS_L(BS, SORTED, MOM)                  \
     switch (lpq) {                                   \
     case 2: VICP_NNS(BS, 2, SORTED, MOM); break;     \

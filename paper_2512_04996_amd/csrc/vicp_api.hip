@@ -659,16 +659,16 @@ void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz,
 
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
 // mom: registration form (per-block moment partials instead of per-query
-// results).
+// results).  all_global: every query takes the exact global search.
 void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
-                  hipStream_t s, bool cap, bool mom)
+                  hipStream_t s, bool cap, bool mom, bool all_global = false)
 {
     const int tab = table_of(g->nns_block / g->nns_lpq);
     {
         ProfScope ps("nns_local", s, cap, true);
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
                          pz, g->ps4, g->st, g->dir, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr,
-                         g->npart, s);
+                         g->npart, all_global ? 1 : 0, s);
     }
     {
         ProfScope ps("fallback", s, cap, true);
@@ -679,9 +679,9 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
 }
 
 void queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
-                     double eps, hipStream_t s, bool cap)
+                     double eps, hipStream_t s, bool cap, bool all_global)
 {
-    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true);
+    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true, all_global);
     ProfScope ps("solve", s, cap, true);
     const int tab = table_of(g->nns_block / g->nns_lpq);
     launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
@@ -1117,13 +1117,14 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     if (rc) return rc;
     const int early = o->early_stop ? 1 : 0;
     const double eps = o->rmse_eps;
+    const bool all_global = o->global_only != 0;
     upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, g->fb_count, g->flags, s);
     launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
-                                      (uintptr_t)g->sort_src,
+                                      (uintptr_t)g->sort_src, (uintptr_t)all_global,
                                       (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
         uint64_t eb;
         memcpy(&eb, &eps, 8);
@@ -1140,7 +1141,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                 VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
                 t_capture_events = attempt == 0 ? &g->gevents : nullptr;
                 if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
-                for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true);
+                for (int k = 0; k < K; ++k)
+                    queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global);
                 t_capture_events = nullptr;
                 hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
                 hipError_t e = ec;
@@ -1163,7 +1165,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     } else {
         const bool cap = capturing(s);
         if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-        for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap);
+        for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global);
     }
     VICP_HIP(hipMemcpyAsync(g->h_res, g->res, g->res_bytes, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));

@@ -185,6 +185,28 @@ def test_search_counters_match_oracle(name):
         assert (int(r.fallbacks[0][0]), int(r.candidates[0][0]), int(r.dilated_lookups[0][0])) == (F, C, D), sched
 
 
+@pytest.mark.parametrize("case", ["bumpy", "room"])
+def test_exhaustive_comparator_matches_oracle(case):
+    # Table 2's "Brute": ICP with the exact global search for every query
+    if case == "bumpy":
+        P = synth.bumpy_pair(seed=31, n=6000, m=5000, voxel=0.05, rings=2, iters=6)
+    else:
+        P = synth.room_pair(seed=32, n=8000, m=6000, voxel=0.1, rings=2, iters=6)
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    g.set_schedule(256, 2, True, 512)
+    for use_graph in (False, True):
+        res = g.register(dev(P.p), 6, use_graph=use_graph, global_only=True)
+        ref = oracle.register_global(P.q, P.p, 6)
+        assert list(res.fallbacks[0]) == [P.m] * 6 == list(ref.fallbacks)
+        assert int(res.candidates[0][0]) == 0
+        np.testing.assert_allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
+        assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+        assert np.linalg.norm(res.Rt[9:] - ref.Rt[9:]) <= T_TOL * P.extent
+    # the same grid still registers by the local search afterwards
+    r = g.register(dev(P.p), 6)
+    assert int(r.fallbacks[0][0]) < P.m
+
+
 def test_register_deterministic_and_graph_equals_eager():
     P = synth.config("bumpy_40k")
     g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)

@@ -511,3 +511,17 @@ def test_paper_setting_registration_converges_and_stops_early():
     g = oracle.dilate(oracle.build_grid_fixed(P.q, P.meta["grid_origin"], P.voxel, P.meta["grid_dims"]), P.rings)
     idx, d2, F, _ = oracle.nns(g, P.q, P.p, np.asarray(r.Rt, np.float32))
     assert F == 0
+
+
+def test_exhaustive_comparator_is_exact_nn_and_svd():
+    # Table 2's "Brute": every correspondence is the exact nearest target and
+    # the pose is the textbook SVD solution on them
+    q = synth.tiny_cloud(50, 400)
+    p = synth.tiny_cloud(51, 150) * np.float32(0.9)
+    r = oracle.register_global(q, p, 1)
+    assert r.iters == 1 and r.fallbacks[0] == p.shape[1]
+    for i in range(p.shape[1]):
+        d, j = _exact_nn(q, p[:, i])
+        assert r.nn_idx[i] == j and r.nn_d2[i] == d
+    R, t, _ = kabsch_svd(p.astype(np.float64), q[:, r.nn_idx].astype(np.float64))
+    assert np.abs(r.Rt[:9].reshape(3, 3) - R).max() < 1e-11 and np.abs(r.Rt[9:] - t).max() < 1e-11
