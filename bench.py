@@ -258,6 +258,34 @@ def extra_figures(api, synth, torch, dev, np):
                        "final_rmse": float(r.rmse[0][k - 1])}
         g.free()
     ex["paper_setting"] = paper
+    # the exhaustive-NNS comparator (Table 2's "Brute") on the main workload:
+    # the same 30 iterations with the exact global search for every query
+    log("[bench] exhaustive comparator")
+    Pm = synth.config("room_226k")
+    qd = torch.from_numpy(Pm.q).to(dev)
+    pd_ = torch.from_numpy(Pm.p).to(dev)
+    g = api.build_grid(qd, Pm.voxel, Pm.rings)
+    g.dilate(Pm.rings)
+    g.set_schedule(128, 2, False, 1024)
+    rb = g.register(pd_, Pm.iters, use_graph=True, global_only=True)   # warm-up and capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = g.register(pd_, Pm.iters, use_graph=True, global_only=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    g.autotune(pd_, searches_per_plan=Pm.iters)
+    rd = g.register(pd_, Pm.iters, use_graph=True)
+    g.free()
+    Rb, Rd = rb.Rt[:9].reshape(3, 3), rd.Rt[:9].reshape(3, 3)
+    Rtrue = np.asarray(Pm.R_true).T          # the registration maps p back onto q
+    ang = lambda A, B: float(np.degrees(np.arccos(np.clip((np.trace(A.T @ B) - 1) / 2, -1, 1))))
+    ex["exhaustive_comparator"] = {
+        "workload": Pm.name, "iters": Pm.iters, "ms": round(tb * 1e3, 3),
+        "queries_per_s": round(Pm.iters * Pm.m / tb, 1),
+        "distance_evals_per_s": round(Pm.iters * Pm.m * Pm.n / tb, 1),
+        "final_rmse_exhaustive": float(rb.rmse[0][-1]), "final_rmse_dilated": float(rd.rmse[0][-1]),
+        "rotation_gap_deg": ang(Rb, Rd), "translation_gap": float(np.linalg.norm(rb.Rt[9:] - rd.Rt[9:])),
+        "rotation_error_deg_exhaustive": ang(Rb, Rtrue), "rotation_error_deg_dilated": ang(Rd, Rtrue)}
     # batched: 64 uneven pairs in one launch sequence, against a loop of single-pair runs
     log("[bench] batched workload")
     pairs = synth.config("batched_64")
