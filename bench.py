@@ -258,6 +258,37 @@ def extra_figures(api, synth, torch, dev, np):
                        "final_rmse": float(r.rmse[0][k - 1])}
         g.free()
     ex["paper_setting"] = paper
+    # the Alg. 1 ablation: the paper's host-side offset scan (MOC) and fused
+    # LDS hash entry against the defaults, on the main workload's build
+    log("[bench] Alg. 1 ablation")
+    Pm = synth.config("room_226k")
+    qd = torch.from_numpy(Pm.q).to(dev)
+    g = api.build_grid(qd, Pm.voxel, Pm.rings)
+    abl = {}
+    for label, host, packed in (("default", False, False), ("packed_hash", False, True),
+                                ("host_offsets", True, False)):
+        g.set_build_options(host_offsets=host, packed_hash=packed)
+        for _ in range(2):
+            g.rebuild(qd)
+        torch.cuda.synchronize()
+        api.prof_reset()
+        api.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            g.rebuild(qd)
+        torch.cuda.synchronize()
+        tr = (time.perf_counter() - t0) / 10
+        api.prof_enable(False)
+        row = {"rebuild_ms": round(tr * 1e3, 4)}
+        for k in ("count", "scan", "moc_host"):
+            n_l, tot = api.prof_read(k)
+            if n_l:
+                row[k + "_us"] = round(1e3 * tot / n_l, 2)
+        abl[label] = row
+    g.free()
+    abl["note"] = ("rebuild = bounding box + count + offsets + scatter + order; moc_host is the serial host "
+                   "scan alone, the rebuild also pays the histogram and offset copies")
+    ex["alg1_ablation"] = abl
     # the exhaustive-NNS comparator (Table 2's "Brute") on the main workload:
     # the same 30 iterations with the exact global search for every query
     log("[bench] exhaustive comparator")

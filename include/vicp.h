@@ -161,6 +161,17 @@ int vicp_build_grid_fixed(const float* qx, const float* qy, const float* qz, int
 int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz,
                       hipStream_t stream);
 
+/* The Alg. 1 ablation, for later builds and rebuilds of this grid:
+ * host_offsets != 0 computes the offsets as the paper's CPU part does (the
+ * histogram is copied to the host, scanned there serially, and the offsets
+ * copied back; two synchronisations); packed_hash != 0 counts with the
+ * paper's fused 32-bit LDS hash entry (voxel key and count in one word;
+ * grids of 2^23 voxels or more per pair keep the default count).  The grid
+ * built either way is identical.  The host scan's time is reported by
+ * vicp_prof_read as "moc_host" while timing is enabled.
+ * Errors: null grid -> INVALID_ARG. */
+int vicp_set_build_options(vicp_grid* grid, int32_t host_offsets, int32_t packed_hash);
+
 /* ---- dilation (Alg. 3) ----------------------------------------------------
  * Applies `rings` synchronous dilation rings (0 <= rings <= pad_rings) to every
  * pair: an empty voxel within L1 distance `rings` of an occupied voxel gets

@@ -59,6 +59,7 @@ SYMBOLS = {
                                         C.c_float, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_void_p)]),
     "vicp_grid_rebuild": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vicp_set_build_options": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "vicp_dilate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "vicp_nns": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_float),
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

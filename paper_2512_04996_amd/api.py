@@ -97,6 +97,13 @@ class Grid:
         self.q = q
         return self
 
+    def set_build_options(self, host_offsets: bool = False, packed_hash: bool = False):
+        """The Alg. 1 ablation for later rebuilds: offsets scanned on the host,
+        counts with the fused 32-bit LDS hash entry (same grid either way)."""
+        check(lib().vicp_set_build_options(self.handle, int(bool(host_offsets)), int(bool(packed_hash))),
+              "vicp_set_build_options")
+        return self
+
     @property
     def schedule(self) -> dict:
         a, l, b, c = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

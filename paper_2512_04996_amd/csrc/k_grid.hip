@@ -152,6 +152,90 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
 }
 
 // --------------------------------------------------------------------------
+// The same count with Alg. 1's fused hash entry: one 32-bit LDS word holds
+// the voxel key (high kPackKeyBits bits) and its count in the block (low
+// bits), updated by compare-and-swap; the previous count is the point's
+// rank in the block.  Two changes keep it correct: the empty slot is
+// 0xFFFFFFFF (the paper's 0 aliases voxel 0 with count 0), and the key is 23
+// bits wide (the paper's 16 bits hold at most 65,536 voxels); a block's 256
+// points need 9 count bits.  Grids of 2^23 voxels or more use k_count.
+// --------------------------------------------------------------------------
+constexpr int kPackCountBits = 9;
+constexpr int kPackKeyBits = 32 - kPackCountBits;
+constexpr uint32_t kPackCountMask = (1u << kPackCountBits) - 1u;
+
+__global__ __launch_bounds__(kThreads) void k_count_packed(const float* __restrict__ qx, const float* __restrict__ qy,
+                                                           const float* __restrict__ qz,
+                                                           const PairDev* __restrict__ pd,
+                                                           const BlockJob* __restrict__ jobs,
+                                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ vox,
+                                                           uint32_t* __restrict__ rank, uint32_t* err)
+{
+    __shared__ uint32_t sent[kSlots];   // (key << kPackCountBits) | count, or empty
+    __shared__ uint32_t sbase[kSlots];
+    for (int s = threadIdx.x; s < kSlots; s += kThreads) sent[s] = kNone;
+    __syncthreads();
+    const BlockJob job = jobs[blockIdx.x];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    bool valid = i < P.n;
+    uint32_t v = 0, slot = 0, lr = 0;
+    int64_t g = 0;
+    if (valid) {
+        g = P.q_base + i;
+        if (!voxel_id(P, qx[g], qy[g], qz[g], v)) {
+            atomicOr(err, 1u);
+            valid = false;
+        }
+    }
+    if (valid) {
+        slot = (v * 2654435761u) >> 23;
+        while (true) {
+            const uint32_t cur = sent[slot];
+            if (cur == kNone) {   // claim the slot with count 1
+                if (atomicCAS(&sent[slot], kNone, (v << kPackCountBits) | 1u) == kNone) {
+                    lr = 0;
+                    break;
+                }
+                continue;   // someone else claimed it: read again
+            }
+            if ((cur >> kPackCountBits) == v) {   // this voxel's entry: count + 1
+                if (atomicCAS(&sent[slot], cur, cur + 1u) == cur) {
+                    lr = cur & kPackCountMask;
+                    break;
+                }
+                continue;
+            }
+            slot = (slot + 1) & (kSlots - 1);
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+        const uint32_t e = sent[s];
+        if (e != kNone) sbase[s] = atomicAdd(&hist[P.v_base + (e >> kPackCountBits)], e & kPackCountMask);
+    }
+    __syncthreads();
+    if (valid) {
+        vox[g] = v;
+        rank[g] = sbase[slot] + lr;
+    }
+}
+
+// Segment headers and search directory from offsets computed elsewhere (the
+// host-side offset scan of the Alg. 1 ablation): vm[off[g]] = 0,
+// vm[off[g] + 1] = hist[g], dir[g] = (off[g] - 2g, hist[g]).
+__global__ void k_seg_headers(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off, int64_t total,
+                              uint32_t* __restrict__ vm, uint2* __restrict__ dir)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = off[g], h = hist[g];
+        vm[o] = 0u;
+        vm[o + 1] = h;
+        dir[g] = make_uint2(o - 2u * (uint32_t)g, h);
+    }
+}
+
+// --------------------------------------------------------------------------
 // offsets: off[g] = sum_{u<g} (hist[u] + 2), off[total] = n + 2V, and the
 // segment headers vm[off[g]] = 0, vm[off[g] + 1] = hist[g] (kSeg), or a
 // plain exclusive scan of hist (!kSeg, for bucketing source points).  Single
@@ -371,10 +455,24 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
 }
 
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
-                  int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, hipStream_t s)
+                  int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, bool packed, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_count, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
+    if (packed)
+        hipLaunchKernelGGL(k_count_packed, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
+                           err);
+    else
+        hipLaunchKernelGGL(k_count, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
+}
+
+bool count_packed_fits(int64_t voxels) { return voxels < ((int64_t)1 << kPackKeyBits); }
+
+void launch_seg_headers(const uint32_t* hist, const uint32_t* off, int64_t total, uint32_t* vm, uint2* dir,
+                        hipStream_t s)
+{
+    if (total <= 0) return;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_seg_headers, dim3(blocks), dim3(256), 0, s, hist, off, total, vm, dir);
 }
 
 int scan_tiles(int64_t total) { return (int)((total + kScanTile - 1) / kScanTile); }

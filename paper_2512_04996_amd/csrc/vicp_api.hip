@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
@@ -104,6 +105,16 @@ struct Prof {
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<int64_t, double>> acc;
 } g_prof;
+
+// Host-side work timed on the host clock (e.g. the host offset scan).
+void prof_add_host(const char* name, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on) return;
+    auto& x = g_prof.acc[name];
+    x.first += 1;
+    x.second += ms;
+}
 
 hipEvent_t prof_event()
 {
@@ -382,6 +393,9 @@ struct vicp_grid {
     // a given grid geometry (single pair) instead of the target's padded box
     bool fixed = false;
     bool usable = true;   // false after a build whose target did not fit the given grid
+    // the Alg. 1 ablation: host-side offset scan, fused 32-bit LDS hash entries
+    bool host_offsets = false, packed_hash = false;
+    std::vector<uint32_t> h_hist, h_off;
     float f_origin[3] = {0, 0, 0};
     int32_t f_dims[3] = {0, 0, 0};
     std::vector<BlockJob> h_jobs_q8;
@@ -838,9 +852,11 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     fill_pairdev(g, pd);
     VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
     launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    bool packed = g->packed_hash;
+    for (int p = 0; p < B && packed; ++p) packed = count_packed_fits(pairs[p].V);
     {
         ProfScope ps("count", s, false);
-        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, s);
+        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, packed, s);
     }
     if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
         uint32_t herr = 0;
@@ -851,7 +867,27 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
             return fail(VICP_ERR_INVALID_ARG, "a target point lies outside the given grid");
         }
     }
-    {
+    if (g->host_offsets) {
+        // Alg. 1's CPU part as the paper runs it: the histogram comes to the
+        // host, the offsets are a serial running sum of count + 2 there, and
+        // go back; a kernel then writes the segment headers and directory
+        g->h_hist.resize((size_t)Vt);
+        g->h_off.resize((size_t)Vt + 1);
+        VICP_HIP(hipMemcpyAsync(g->h_hist.data(), g->hist, sizeof(uint32_t) * Vt, hipMemcpyDeviceToHost, s));
+        VICP_HIP(hipStreamSynchronize(s));
+        const auto t0 = std::chrono::steady_clock::now();
+        uint64_t head = 0;
+        for (int64_t v = 0; v < Vt; ++v) {
+            g->h_off[v] = (uint32_t)head;
+            head += (uint64_t)g->h_hist[v] + 2;
+        }
+        g->h_off[Vt] = (uint32_t)head;
+        const auto t1 = std::chrono::steady_clock::now();
+        prof_add_host("moc_host", std::chrono::duration<double, std::milli>(t1 - t0).count());
+        VICP_HIP(hipMemcpyAsync(g->off, g->h_off.data(), sizeof(uint32_t) * (Vt + 1), hipMemcpyHostToDevice, s));
+        launch_seg_headers(g->hist, g->off, Vt, g->vm, g->dir, s);
+        VICP_HIP(hipStreamSynchronize(s));   // the host arrays are reused by the next build
+    } else {
         ProfScope ps("scan", s, false);
         launch_scan(g->hist, Vt, g->off, g->vm, g->dir, g->scan_status, g->scan_ticket, s);
     }
@@ -1019,6 +1055,14 @@ int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const floa
 }
 
 int vicp_grid_npairs(const vicp_grid* g) { return g ? g->B : 0; }
+
+int vicp_set_build_options(vicp_grid* g, int32_t host_offsets, int32_t packed_hash)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    g->host_offsets = host_offsets != 0;
+    g->packed_hash = packed_hash != 0;
+    return VICP_OK;
+}
 
 int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
 {

@@ -232,7 +232,10 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
                  const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd,
                   const BlockJob* jobs, int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank,
-                  uint32_t* err, hipStream_t s);
+                  uint32_t* err, bool packed, hipStream_t s);
+bool count_packed_fits(int64_t voxels);
+void launch_seg_headers(const uint32_t* hist, const uint32_t* off, int64_t total, uint32_t* vm, uint2* dir,
+                        hipStream_t s);
 int scan_tiles(int64_t total);
 void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, uint2* dir,
                  unsigned long long* status, uint32_t* ticket, hipStream_t s);

@@ -207,6 +207,23 @@ def test_exhaustive_comparator_matches_oracle(case):
     assert int(r.fallbacks[0][0]) < P.m
 
 
+@pytest.mark.parametrize("name", ["bumpy_40k", "room_226k"])
+def test_alg1_ablation_builds_the_same_grid(name):
+    # the paper's CPU-side offset scan and fused 32-bit LDS hash entry give
+    # the same grid (hence bit-identical registrations) as the defaults
+    P = synth.config(name)
+    og = oracle.dilate(oracle.build_grid(P.q, P.voxel, P.rings), P.rings)
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    r0 = g.register(p, 5)
+    for host_offsets, packed in ((True, False), (False, True), (True, True)):
+        g.set_build_options(host_offsets=host_offsets, packed_hash=packed)
+        g.rebuild(dev(P.q)).dilate(P.rings)
+        check_grid(g, og)
+        r = g.register(p, 5)
+        assert np.array_equal(r.Rt, r0.Rt) and np.array_equal(r.rmse[0], r0.rmse[0]), (host_offsets, packed)
+
+
 def test_register_deterministic_and_graph_equals_eager():
     P = synth.config("bumpy_40k")
     g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
