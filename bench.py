@@ -423,7 +423,7 @@ def cpu_baseline(P):
         r = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters)
         reps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 8:
+        if el > 10.0 or reps >= 40:
             break
     cpu = "unknown"
     try:
