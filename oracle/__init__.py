@@ -60,11 +60,15 @@ def lib():
         L.vicpo_dilate.argtypes = [i32p, i64, u32p, u32p, i32, u32p, u32p]
         L.vicpo_nns.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, u32p, u32p,
                                 f32p, f32p, f32p, i64, f32p, i32p, f32p, i64p, i64p, i64p]
+        L.vicpo_nns_cap.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, u32p, u32p,
+                                    f32p, f32p, f32p, i64, f32p, i64, i32p, f32p, i64p, i64p, i64p]
         L.vicpo_solve.argtypes = [f32p, f32p, f32p, f32p, f32p, f32p, i32p, i64, f64p, f64p, f64p, i32p]
         L.vicpo_register.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, C.c_float, i32, i32,
                                      C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
         L.vicpo_register_spec.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64,
                                           i32, i32, C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
+        L.vicpo_register_cap.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64,
+                                         i32, i64, i32, C.c_double, i32, f64p, f64p, i64p, i32p, i32p, i32p, f32p]
         L.vicpo_se3_exp.argtypes = [f64p, f64p, f64p, f64p]
         L.vicpo_se3_exp.restype = None
         L.vicpo_p2p_loss_fixed.argtypes = [f32p, f32p, f32p, f64p, f64p, f64p, i64, i32p, f64p]
@@ -188,25 +192,27 @@ def dilate(g: Grid, rings: int) -> Grid:
     return g
 
 
-def nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
+def nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray, capacity: int = 0):
     """Alg. 4 for every source point; ``Rt`` = float32 row-major R then t.
+    ``capacity`` > 0: VANICP's per-voxel block capacity (see direct_capacity);
+    a query whose points would not fit one block takes the global search.
 
     Returns (idx int32[m], d2 float32[m], n_fallback, candidates_total).
     """
-    idx, d2, F, Ct, _ = _nns(g, q, p, Rt)
+    idx, d2, F, Ct, _ = _nns(g, q, p, Rt, capacity)
     return idx, d2, F, Ct
 
 
-def nns_counts(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
+def nns_counts(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray, capacity: int = 0):
     """Counts of one Alg. 4 pass: (queries sent to the global search,
-    candidates scanned by the local searches, queries whose voxel is a
-    dilated one, i.e. whose count word holds Mask(root))."""
+    candidates scanned by the local searches, queries resolved through a
+    dilated voxel, i.e. one whose count word holds Mask(root))."""
     q, p = _soa(q), _soa(p)
-    _, _, F, Ct, Dl = _nns(g, q, p, Rt)
+    _, _, F, Ct, Dl = _nns(g, q, p, Rt, capacity)
     return F, Ct - F * q.shape[1], Dl
 
 
-def _nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
+def _nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray, capacity: int = 0):
     q, p = _soa(q), _soa(p)
     Rt = np.ascontiguousarray(Rt, np.float32).reshape(12)
     m = p.shape[1]
@@ -216,10 +222,11 @@ def _nns(g: Grid, q: np.ndarray, p: np.ndarray, Rt: np.ndarray):
     Ct = np.zeros(1, np.int64)
     Dl = np.zeros(1, np.int64)
     qs, ps = _rows(q), _rows(p)
-    rc = lib().vicpo_nns(*(_p(a, C.c_float) for a in qs), q.shape[1], _p(g.origin, C.c_float), C.c_float(g.inv),
-                         _p(g.dims, C.c_int32), _p(g.off, C.c_uint32), _p(g.vm, C.c_uint32),
-                         *(_p(a, C.c_float) for a in ps), m, _p(Rt, C.c_float), _p(idx, C.c_int32),
-                         _p(d2, C.c_float), _p(F, C.c_int64), _p(Ct, C.c_int64), _p(Dl, C.c_int64))
+    rc = lib().vicpo_nns_cap(*(_p(a, C.c_float) for a in qs), q.shape[1], _p(g.origin, C.c_float),
+                             C.c_float(g.inv), _p(g.dims, C.c_int32), _p(g.off, C.c_uint32), _p(g.vm, C.c_uint32),
+                             *(_p(a, C.c_float) for a in ps), m, _p(Rt, C.c_float), int(capacity),
+                             _p(idx, C.c_int32), _p(d2, C.c_float), _p(F, C.c_int64), _p(Ct, C.c_int64),
+                             _p(Dl, C.c_int64))
     _check(rc, "nns")
     return idx[:m], d2[:m], int(F[0]), int(Ct[0]), int(Dl[0])
 
@@ -301,6 +308,43 @@ def register_fixed(q, p, origin, voxel: float, dims, rings: int, iters: int, rms
                                    C.c_double(rmse_eps), int(early_stop), _p(Rt, C.c_double), _p(rmse, C.c_double),
                                    _p(fb, C.c_int64), _p(done, C.c_int32), _p(deg, C.c_int32), _p(idx, C.c_int32),
                                    _p(d2, C.c_float))
+    _check(rc, "register")
+    k = int(done[0])
+    return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])
+
+
+# A block record is three float32 coordinates and the point index.
+RECORD_BYTES = 16
+
+
+def direct_capacity(block_bytes: int) -> int:
+    """Points one voxel's block holds in VANICP's layout (a fixed memory
+    block per voxel, Sec. II.B; 64 KiB there, so 4096 points)."""
+    return int(block_bytes) // RECORD_BYTES
+
+
+def register_direct(q, p, voxel: float, rings: int, iters: int, block_bytes: int = 65536,
+                    rmse_eps: float = 1e-5, early_stop: bool = False, Rt0=None) -> IcpResult:
+    """register with VANICP's per-voxel block capacity: a query whose voxel,
+    or whose dilated voxel's root, holds more points than one block does
+    takes the global search (Sec. IV.B)."""
+    q, p = _soa(q), _soa(p)
+    origin, inv, dims, V = grid_spec(q, voxel, rings)
+    Rt = np.ascontiguousarray(Rt0 if Rt0 is not None else identity_rt(), np.float64).reshape(12).copy()
+    K = max(iters, 1)
+    rmse = np.zeros(K, np.float64)
+    fb = np.zeros(K, np.int64)
+    deg = np.zeros(K, np.int32)
+    done = np.zeros(1, np.int32)
+    m = p.shape[1]
+    idx = np.zeros(max(m, 1), np.int32)
+    d2 = np.zeros(max(m, 1), np.float32)
+    qs, ps = _rows(q), _rows(p)
+    rc = lib().vicpo_register_cap(*(_p(a, C.c_float) for a in qs), q.shape[1], *(_p(a, C.c_float) for a in ps), m,
+                                  _p(origin, C.c_float), C.c_float(inv), _p(dims, C.c_int32), V, rings,
+                                  direct_capacity(block_bytes), iters, C.c_double(rmse_eps), int(early_stop),
+                                  _p(Rt, C.c_double), _p(rmse, C.c_double), _p(fb, C.c_int64), _p(done, C.c_int32),
+                                  _p(deg, C.c_int32), _p(idx, C.c_int32), _p(d2, C.c_float))
     _check(rc, "register")
     k = int(done[0])
     return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])

@@ -242,6 +242,24 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
               const float Rt[12], int32_t* nn_idx, float* nn_d2, int64_t* n_fallback,
               int64_t* cand_total, int64_t* dilated_total)
 {
+    return vicpo_nns_cap(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rt, 0, nn_idx, nn_d2,
+                         n_fallback, cand_total, dilated_total);
+}
+
+/* Alg. 4 under a per-voxel capacity (VANICP's fixed memory block per voxel,
+ * Sec. II.B): when the points a query would search (its own voxel's, or its
+ * root's for a dilated voxel) number more than `capacity`, they do not fit a
+ * block, and the query takes the global search instead (Sec. IV.B: points
+ * beyond a voxel's capacity force the global search).  capacity <= 0: no
+ * limit, which is Alg. 4 itself.  A query counts as dilated only when it is
+ * resolved through its root's points. */
+int vicpo_nns_cap(const float* qx, const float* qy, const float* qz, int64_t n,
+                  const float origin[3], float inv, const int32_t dims[3],
+                  const uint32_t* off, const uint32_t* vm,
+                  const float* px, const float* py, const float* pz, int64_t m,
+                  const float Rt[12], int64_t capacity, int32_t* nn_idx, float* nn_d2,
+                  int64_t* n_fallback, int64_t* cand_total, int64_t* dilated_total)
+{
     int64_t F = 0, C = 0, Dl = 0;
     for (int64_t i = 0; i < m; ++i) {
         float s[3];
@@ -252,17 +270,18 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
         uint32_t seg_head = 0, count = 0;
         if (voxel_of(origin, inv, dims, s[0], s[1], s[2], &v)) {
             uint32_t h = vm[off[v] + 1];
-            if (h & MASK_BIT) {
+            int dilated = (h & MASK_BIT) != 0;
+            if (dilated) {
                 /* a dilated voxel: its Mask(root) word sends the search to the root */
                 uint32_t root = h & ~MASK_BIT;
-                Dl += 1;
                 seg_head = off[root];
                 count = vm[seg_head + 1];
             } else {
                 seg_head = off[v];
                 count = h;
             }
-            local = count > 0;
+            local = count > 0 && (capacity <= 0 || (int64_t)count <= capacity);
+            if (local && dilated) Dl += 1;
         }
         float bd = INFINITY;
         int64_t bj = -1;
@@ -466,6 +485,20 @@ int vicpo_register_spec(const float* qx, const float* qy, const float* qz, int64
                         int64_t* fb_hist, int32_t* iters_done, int32_t* degenerate_hist,
                         int32_t* nn_idx, float* nn_d2)
 {
+    return vicpo_register_cap(qx, qy, qz, n, px, py, pz, m, origin, inv, dims, V, rings, 0, max_iter, rmse_eps,
+                              early_stop, Rt_io, rmse_hist, fb_hist, iters_done, degenerate_hist, nn_idx, nn_d2);
+}
+
+/* The same with the per-voxel capacity of vicpo_nns_cap (VANICP's fixed
+ * blocks; capacity <= 0: no limit). */
+int vicpo_register_cap(const float* qx, const float* qy, const float* qz, int64_t n,
+                       const float* px, const float* py, const float* pz, int64_t m,
+                       const float origin[3], float inv, const int32_t dims[3], int64_t V,
+                       int32_t rings, int64_t capacity, int32_t max_iter, double rmse_eps,
+                       int32_t early_stop, double Rt_io[12], double* rmse_hist,
+                       int64_t* fb_hist, int32_t* iters_done, int32_t* degenerate_hist,
+                       int32_t* nn_idx, float* nn_d2)
+{
     *iters_done = 0;
     if (m == 0) return VICPO_OK;
     if (m < 0 || max_iter < 0 || rings < 0) return VICPO_ERR_ARG;
@@ -488,7 +521,8 @@ int vicpo_register_spec(const float* qx, const float* qy, const float* qz, int64
         float Rtf[12];
         for (int a = 0; a < 12; ++a) Rtf[a] = (float)Rt_io[a];
         int64_t F = 0;
-        vicpo_nns(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, idx, d2, &F, NULL, NULL);
+        vicpo_nns_cap(qx, qy, qz, n, origin, inv, dims, off, vm, px, py, pz, m, Rtf, capacity, idx, d2, &F, NULL,
+                      NULL);
         double acc = 0.0;
         for (int64_t i = 0; i < m; ++i) acc += (double)d2[i];
         double rmse = sqrt(acc / (double)m);

@@ -28,6 +28,12 @@ int vicpo_nns(const float* qx, const float* qy, const float* qz, int64_t n,
               const float* px, const float* py, const float* pz, int64_t m,
               const float Rt[12], int32_t* nn_idx, float* nn_d2, int64_t* n_fallback,
               int64_t* cand_total, int64_t* dilated_total);
+int vicpo_nns_cap(const float* qx, const float* qy, const float* qz, int64_t n,
+                  const float origin[3], float inv, const int32_t dims[3],
+                  const uint32_t* off, const uint32_t* vm,
+                  const float* px, const float* py, const float* pz, int64_t m,
+                  const float Rt[12], int64_t capacity, int32_t* nn_idx, float* nn_d2,
+                  int64_t* n_fallback, int64_t* cand_total, int64_t* dilated_total);
 int vicpo_solve(const float* px, const float* py, const float* pz,
                 const float* qx, const float* qy, const float* qz,
                 const int32_t* idx, int64_t m, const double Rt_prev[12],
@@ -45,6 +51,13 @@ int vicpo_register_spec(const float* qx, const float* qy, const float* qz, int64
                         int32_t early_stop, double Rt_io[12], double* rmse_hist,
                         int64_t* fb_hist, int32_t* iters_done, int32_t* degenerate_hist,
                         int32_t* nn_idx, float* nn_d2);
+int vicpo_register_cap(const float* qx, const float* qy, const float* qz, int64_t n,
+                       const float* px, const float* py, const float* pz, int64_t m,
+                       const float origin[3], float inv, const int32_t dims[3], int64_t V,
+                       int32_t rings, int64_t capacity, int32_t max_iter, double rmse_eps,
+                       int32_t early_stop, double Rt_io[12], double* rmse_hist,
+                       int64_t* fb_hist, int32_t* iters_done, int32_t* degenerate_hist,
+                       int32_t* nn_idx, float* nn_d2);
 void vicpo_se3_exp(const double xi[6], double R[9], double t[3], double Jl6[36]);
 double vicpo_p2p_loss_fixed(const float* qx, const float* qy, const float* qz,
                             const double* px, const double* py, const double* pz, int64_t m,

@@ -91,6 +91,44 @@ def nns_rule(q, p, Rt, origin, inv, dims, hist, off, vm, counts=False):
     return np.array(idx, np.int32), np.array(d2, np.float32), fb
 
 
+def direct_layout_nns(q, p, Rt, origin, inv, dims, roots, capacity):
+    """VANICP's layout written out literally: every voxel owns a block of
+    ``capacity`` point records, filled in point order; a block that would
+    take more points is marked overflowed; a dilated voxel's block is a copy
+    of its root's (overflow included).  A query searches its voxel's block,
+    or the whole target when the block is empty, overflowed or the point is
+    outside the grid.  Returns (idx, d2, number of global searches)."""
+    q = np.asarray(q, np.float32)
+    n = q.shape[1]
+    vid = voxel_ids_np(q, origin, inv, dims)
+    blocks, over = {}, set()
+    for i in range(n):
+        v = int(vid[i])
+        b = blocks.setdefault(v, [])
+        if len(b) < capacity:
+            b.append(i)
+        else:
+            over.add(v)
+    for v in range(len(roots)):
+        r = int(roots[v])
+        if r != 0xFFFFFFFF and v not in blocks and r in blocks:
+            blocks[v] = list(blocks[r])
+            if r in over:
+                over.add(v)
+    idx, d2, fb = [], [], 0
+    for i in range(p.shape[1]):
+        s = transform_f32(Rt, p[:, i])
+        v = int(voxel_ids_np(np.array(s, np.float32).reshape(3, 1), origin, inv, dims)[0])
+        cand = blocks.get(v) if (v >= 0 and v not in over) else None
+        if not cand:
+            cand = range(n)
+            fb += 1
+        best = min((dist2_f32(s, q[:, j]), j) for j in cand)
+        idx.append(best[1])
+        d2.append(best[0])
+    return np.array(idx, np.int32), np.array(d2, np.float32), fb
+
+
 def kabsch_svd(p, q):
     """Textbook SVD solution of Eq. 1 (numpy), float64."""
     p = np.asarray(p, np.float64)

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from bruteforce import closed_form_roots, kabsch_svd, nns_rule, segments_np, voxel_ids_np
+from bruteforce import closed_form_roots, direct_layout_nns, kabsch_svd, nns_rule, segments_np, voxel_ids_np
 from exact_f32 import dist2_f32, transform_f32
 from paper_2512_04996_amd import synth
 
@@ -212,6 +212,40 @@ def test_nns_matches_independent_rule(seed, L):
     assert oracle.nns_counts(g, q, p, Rt) == (rF, rC, rD)
     if L > 0:
         assert rD > 0
+
+
+@pytest.mark.parametrize("seed,L,cap", [(23, 0, 1), (24, 1, 2), (25, 2, 3), (26, 2, 5), (27, 1, 10 ** 6)])
+def test_capacity_nns_matches_literal_direct_layout(seed, L, cap):
+    """VANICP's fixed blocks (Sec. II.B) with the global search for points
+    beyond a block (Sec. IV.B): the oracle's capacity rule on the segmented
+    grid against the block layout built literally, with roots from the
+    closed form of the dilation."""
+    q = synth.tiny_cloud(seed, 220, dup=25)
+    p = synth.tiny_cloud(seed + 100, 90, scale=1.15)
+    g = oracle.dilate(oracle.build_grid(q, 0.3, L), L)
+    Rt = np.array([0.98, -0.17, 0.0, 0.17, 0.98, 0.0, 0.0, 0.0, 1.0, 0.02, 0.0, -0.01], np.float32)
+    roots = closed_form_roots(g.hist, g.dims, L)
+    idx, d2, F, _ = oracle.nns(g, q, p, Rt, capacity=cap)
+    ridx, rd2, rF = direct_layout_nns(q, p, Rt, g.origin, g.inv, g.dims, roots, cap)
+    assert np.array_equal(idx, ridx) and np.array_equal(d2, rd2) and F == rF
+    base = oracle.nns(g, q, p, Rt)
+    if cap >= int(g.hist.max()):
+        assert np.array_equal(idx, base[0]) and F == base[2]
+    else:
+        assert F > base[2]          # some block overflowed and sent its queries to the global search
+
+
+def test_register_direct_capacity():
+    q = synth.tiny_cloud(28, 300, dup=40)
+    p = synth.tiny_cloud(29, 120, scale=1.1)
+    a = oracle.register(q, p, 0.3, 2, 6)
+    b = oracle.register_direct(q, p, 0.3, 2, 6)                 # 64 KiB blocks: nothing overflows
+    assert np.array_equal(a.Rt, b.Rt) and np.array_equal(a.fallbacks, b.fallbacks)
+    c = oracle.register_direct(q, p, 0.3, 2, 6, block_bytes=2 * oracle.RECORD_BYTES)
+    g = oracle.dilate(oracle.build_grid(q, 0.3, 2), 2)
+    roots = closed_form_roots(g.hist, g.dims, 2)
+    _, _, rF = direct_layout_nns(q, p, oracle.identity_rt().astype(np.float32), g.origin, g.inv, g.dims, roots, 2)
+    assert c.fallbacks[0] == rF and rF > a.fallbacks[0]
 
 
 def test_nns_never_beats_exact_and_ties_go_low():
