@@ -97,7 +97,7 @@ def main():
         g.set_schedule(bs, lpq, bool(srt), fg)
     schedule = g.schedule
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
-                   f"{'true' if schedule['sort_source'] else 'false'}, true>")
+                   f"{'true' if schedule['sort_source'] else 'false'}, true, false>")
     nns_blocks = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block'])
 
     def step():
@@ -317,6 +317,7 @@ def extra_figures(api, synth, torch, dev, np):
         "final_rmse_exhaustive": float(rb.rmse[0][-1]), "final_rmse_dilated": float(rd.rmse[0][-1]),
         "rotation_gap_deg": ang(Rb, Rd), "translation_gap": float(np.linalg.norm(rb.Rt[9:] - rd.Rt[9:])),
         "rotation_error_deg_exhaustive": ang(Rb, Rtrue), "rotation_error_deg_dilated": ang(Rd, Rtrue)}
+    ex["vanicp_comparator"] = vanicp_comparator(api, synth, torch, dev, np)
     # batched: 64 uneven pairs in one launch sequence, against a loop of single-pair runs
     log("[bench] batched workload")
     pairs = synth.config("batched_64")
@@ -408,6 +409,72 @@ def extra_figures(api, synth, torch, dev, np):
                          "fwd_bwd_pairs_per_s": round(B / td, 1)}
     ex["dilation_buffer_other"] = sizes
     return ex
+
+
+def vanicp_comparator(api, synth, torch, dev, np):
+    """VANICP's monolithic layout (64 KiB per voxel, points copied into
+    every occupied and dilated voxel's block) against the segmented layout,
+    on the same grid, rings and search schedule: build time, registration
+    time, search-kernel time and bytes.  On the paper's fixed 16^3 grid the
+    densest voxels overflow their blocks and send queries to the global
+    search."""
+    log("[bench] VANICP layout comparator")
+    out = {}
+    for name in ("room_226k", "paper_room_226k"):
+        Pw = synth.config(name)
+        qd = torch.from_numpy(Pw.q).to(dev)
+        pd_ = torch.from_numpy(Pw.p).to(dev)
+        paper = name.startswith("paper")
+        if paper:
+            g = api.build_grid_fixed(qd, Pw.meta["grid_origin"], Pw.voxel, Pw.meta["grid_dims"], Pw.rings)
+            kw = {"rmse_eps": Pw.meta["rmse_eps"], "early_stop": True}
+        else:
+            g = api.build_grid(qd, Pw.voxel, Pw.rings)
+            kw = {}
+        g.dilate(Pw.rings)
+        g.autotune(pd_, searches_per_plan=Pw.iters)
+
+        def avg(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps, r
+
+        t_seg_build, _ = avg(lambda: g.rebuild(qd).dilate(Pw.rings), 5)
+        t_dir_build, _ = avg(lambda: g.build_direct(65536), 5)
+        t_seg, rs = avg(lambda: g.register(pd_, Pw.iters, use_graph=True, **kw), 5)
+        t_dir, rd = avg(lambda: g.register(pd_, Pw.iters, use_graph=True, layout="direct", **kw), 5)
+        api.prof_reset()
+        api.prof_enable(True)
+        g.build_direct(65536)
+        g.register(pd_, Pw.iters, use_graph=False, **kw)
+        g.register(pd_, Pw.iters, use_graph=False, layout="direct", **kw)
+        torch.cuda.synchronize()
+        api.prof_enable(False)
+        kus = {}
+        for k in ("nns_local", "nns_direct", "direct_count", "direct_dilate_ring", "direct_replicate"):
+            n_l, tot = api.prof_read(k)
+            if n_l:
+                kus[k + "_us"] = round(1e3 * tot / n_l, 2)
+        d = g.describe()
+        sched = g.schedule
+        g.free()
+        ks, kd = int(rs.iters[0]), int(rd.iters[0])
+        out[name] = {
+            "V": d["V"], "block_bytes": 65536,
+            "bytes_vanicp": d["V"] * 65536 + 4 * d["V"],
+            "bytes_segmented": d["static_bytes"] + d["dynamic_bytes"],
+            "build_ms_segmented": round(t_seg_build * 1e3, 3), "build_ms_vanicp": round(t_dir_build * 1e3, 3),
+            "register_ms_segmented": round(t_seg * 1e3, 3), "register_ms_vanicp": round(t_dir * 1e3, 3),
+            "iters_segmented": ks, "iters_vanicp": kd,
+            "global_searches_iter0_segmented": int(rs.fallbacks[0][0]),
+            "global_searches_iter0_vanicp": int(rd.fallbacks[0][0]),
+            "final_rmse_segmented": float(rs.rmse[0][ks - 1]), "final_rmse_vanicp": float(rd.rmse[0][kd - 1]),
+            "same_pose": bool(np.array_equal(rs.Rt, rd.Rt)), "schedule": sched, **kus}
+    return out
 
 
 def cpu_baseline(P):

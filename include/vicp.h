@@ -98,6 +98,9 @@ typedef struct vicp_icp_opts {
     int32_t use_graph;  /* non-zero: capture the K iterations once in a hipGraph and replay it */
     int32_t global_only; /* non-zero: every query takes the exact global search (ICP with exhaustive
                             NNS, the "Brute" comparator of Table 2); the grid is not consulted */
+    int32_t layout;      /* 0: the segmented, offset-addressed layout (Alg. 2-4); 1: VANICP's
+                            monolithic direct-addressed layout built by vicp_direct_build (the
+                            comparator); excludes global_only */
 } vicp_icp_opts;
 
 /* Per-pair registration statistics.  The arrays are caller-owned HOST arrays
@@ -171,6 +174,36 @@ int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const floa
  * vicp_prof_read as "moc_host" while timing is enabled.
  * Errors: null grid -> INVALID_ARG. */
 int vicp_set_build_options(vicp_grid* grid, int32_t host_offsets, int32_t packed_hash);
+
+/* ---- VANICP's monolithic layout (the comparator) -------------------------
+ * Sec. II.B describes the layout the paper replaces: a fixed memory block per
+ * voxel (64 KiB) into which voxelisation copies the voxel's points and
+ * dilation copies the root's points, so that the search addresses a voxel's
+ * candidates directly; Sec. IV.B notes that points beyond a block's capacity
+ * send the search to the global fallback.  vicp_direct_build builds that
+ * layout for a built and dilated single-pair grid, on the same geometry and
+ * with the same rings (roots as Alg. 3):
+ *   - blocks: V * block_bytes device bytes, allocated here with hipMalloc and
+ *     owned by the grid (about 21.8 GB for 332k voxels at 64 KiB); records of
+ *     16 bytes (float32 x, y, z and the point index as 32 bits), so a block
+ *     holds block_bytes / 16 points, in no particular order;
+ *   - a count word per voxel: the voxel's own point count, or its root's
+ *     count with bit 31 set for a dilated voxel;
+ *   - a voxel whose count exceeds the capacity keeps only what fitted, and
+ *     its queries, and those of voxels dilated from it, take the global
+ *     search.
+ * A registration with opts.layout = 1 then searches these blocks.  Without
+ * overflow it returns exactly what the segmented layout returns (ties go to
+ * the lowest index in both).  Asynchronous except when it (re)allocates.
+ * Errors: null grid -> INVALID_ARG; grid not built, failed or not dilated ->
+ * STATE; more than one pair, block_bytes not a positive multiple of 16 ->
+ * INVALID_ARG; the device allocation fails -> OOM.  Any rebuild of the grid
+ * invalidates the layout (STATE until it is built again). */
+int vicp_direct_build(vicp_grid* g, int64_t block_bytes, hipStream_t stream);
+
+/* Frees the blocks of vicp_direct_build (synchronises the device).  No-op
+ * when there are none.  Errors: null grid -> INVALID_ARG. */
+int vicp_direct_free(vicp_grid* g);
 
 /* ---- dilation (Alg. 3) ----------------------------------------------------
  * Applies `rings` synchronous dilation rings (0 <= rings <= pad_rings) to every

@@ -289,8 +289,9 @@ def register(q, p, voxel: float, rings: int, iters: int, rmse_eps: float = 1e-5,
 
 
 def register_fixed(q, p, origin, voxel: float, dims, rings: int, iters: int, rmse_eps: float = 1e-5,
-                   early_stop: bool = False, Rt0=None) -> IcpResult:
-    """register on a given grid (see build_grid_fixed)."""
+                   early_stop: bool = False, Rt0=None, block_bytes: int = 0) -> IcpResult:
+    """register on a given grid (see build_grid_fixed); ``block_bytes`` > 0
+    adds VANICP's per-voxel block capacity (see register_direct)."""
     q, p = _soa(q), _soa(p)
     origin, inv, dims, V = fixed_spec(origin, voxel, dims)
     Rt = np.ascontiguousarray(Rt0 if Rt0 is not None else identity_rt(), np.float64).reshape(12).copy()
@@ -303,11 +304,11 @@ def register_fixed(q, p, origin, voxel: float, dims, rings: int, iters: int, rms
     idx = np.zeros(max(m, 1), np.int32)
     d2 = np.zeros(max(m, 1), np.float32)
     qs, ps = _rows(q), _rows(p)
-    rc = lib().vicpo_register_spec(*(_p(a, C.c_float) for a in qs), q.shape[1], *(_p(a, C.c_float) for a in ps), m,
-                                   _p(origin, C.c_float), C.c_float(inv), _p(dims, C.c_int32), V, rings, iters,
-                                   C.c_double(rmse_eps), int(early_stop), _p(Rt, C.c_double), _p(rmse, C.c_double),
-                                   _p(fb, C.c_int64), _p(done, C.c_int32), _p(deg, C.c_int32), _p(idx, C.c_int32),
-                                   _p(d2, C.c_float))
+    rc = lib().vicpo_register_cap(*(_p(a, C.c_float) for a in qs), q.shape[1], *(_p(a, C.c_float) for a in ps), m,
+                                  _p(origin, C.c_float), C.c_float(inv), _p(dims, C.c_int32), V, rings,
+                                  direct_capacity(block_bytes), iters, C.c_double(rmse_eps), int(early_stop),
+                                  _p(Rt, C.c_double), _p(rmse, C.c_double), _p(fb, C.c_int64), _p(done, C.c_int32),
+                                  _p(deg, C.c_int32), _p(idx, C.c_int32), _p(d2, C.c_float))
     _check(rc, "register")
     k = int(done[0])
     return IcpResult(Rt, rmse[:k], fb[:k], deg[:k], k, idx[:m], d2[:m])

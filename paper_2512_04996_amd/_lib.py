@@ -40,7 +40,7 @@ class GridDesc(C.Structure):
 
 class IcpOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("rmse_eps", C.c_double), ("early_stop", C.c_int32),
-                ("use_graph", C.c_int32), ("global_only", C.c_int32)]
+                ("use_graph", C.c_int32), ("global_only", C.c_int32), ("layout", C.c_int32)]
 
 
 class IcpStats(C.Structure):
@@ -61,6 +61,8 @@ SYMBOLS = {
     "vicp_grid_rebuild": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_set_build_options": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "vicp_dilate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "vicp_direct_build": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "vicp_direct_free": (C.c_int, [C.c_void_p]),
     "vicp_nns": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_float),
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_nns_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),

@@ -97,6 +97,19 @@ class Grid:
         self.q = q
         return self
 
+    def build_direct(self, block_bytes: int = 65536):
+        """VANICP's monolithic layout beside this grid, for comparison: a fixed
+        block of ``block_bytes`` per voxel (V * block_bytes device bytes) holding
+        copies of the voxel's points, or of its root's for a dilated voxel.
+        Needs a dilated single-pair grid; ``register(..., layout="direct")``
+        then searches it."""
+        check(lib().vicp_direct_build(self.handle, int(block_bytes), _stream()), "vicp_direct_build")
+        return self
+
+    def free_direct(self):
+        """Release the blocks of build_direct."""
+        check(lib().vicp_direct_free(self.handle), "vicp_direct_free")
+
     def set_build_options(self, host_offsets: bool = False, packed_hash: bool = False):
         """The Alg. 1 ablation for later rebuilds: offsets scanned on the host,
         counts with the fused 32-bit LDS hash entry (same grid either way)."""
@@ -150,7 +163,7 @@ class Grid:
     # -- the ICP loop
     def register(self, p: torch.Tensor, max_iter: int, rmse_eps: float = 1e-5, early_stop: bool = False,
                  use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False,
-                 global_only: bool = False) -> IcpResult:
+                 global_only: bool = False, layout: str = "segmented") -> IcpResult:
         p = _soa(p, "p")
         m = p.shape[1]
         B = self.npairs
@@ -174,7 +187,10 @@ class Grid:
             stats[b].fallbacks = fbk[b].ctypes.data_as(C.POINTER(C.c_int64))
             stats[b].candidates = cnd[b].ctypes.data_as(C.POINTER(C.c_int64))
             stats[b].dilated_lookups = dil[b].ctypes.data_as(C.POINTER(C.c_int64))
-        opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)), int(bool(global_only)))
+        if layout not in ("segmented", "direct"):
+            raise ValueError("layout must be 'segmented' or 'direct'")
+        opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)), int(bool(global_only)),
+                       int(layout == "direct"))
         px, py, pz = _ptrs(p)
         rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
                                          rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())

@@ -53,7 +53,56 @@ __global__ __launch_bounds__(BS) void k_dilate_ring(const PairDev* __restrict__ 
     }
 }
 
+// VANICP's dilation writes points, not a reference: once the rings have
+// run (state = own id for an occupied voxel, root id for a dilated one), the
+// fixed block of every dilated voxel receives a copy of its root's records,
+// and its count word the root's count with the mask bit.  A root whose block
+// overflowed (count above cap) has no complete copy to give: nothing is
+// copied and the count word alone tells the search to go global.  Four lanes
+// per voxel, four 16-byte records each in flight.  Roots are occupied voxels
+// and only empty voxels are written, so no count word is read and written by
+// different lanes.
+constexpr int kRepLanes = 4;
+constexpr int kRepUnroll = 4;
+
+__global__ __launch_bounds__(256) void k_replicate(const PairDev* __restrict__ pd, const uint32_t* __restrict__ state,
+                                                   uint32_t* __restrict__ cnt, float4* __restrict__ blk, uint32_t cap)
+{
+    const PairDev& P = pd[0];
+    const int64_t v = (int64_t)blockIdx.x * (256 / kRepLanes) + threadIdx.x / kRepLanes;
+    if (v >= P.V) return;
+    const uint32_t sub = threadIdx.x % kRepLanes;
+    const uint32_t r = state[P.v_base + v];
+    if (r == kNone || (int64_t)r == v) return;
+    const uint32_t c = cnt[P.v_base + r];
+    if (sub == 0) cnt[P.v_base + v] = c | kMask;
+    if (c > cap) return;
+    const float4* src = blk + (P.v_base + (int64_t)r) * cap;
+    float4* dst = blk + (P.v_base + v) * cap;
+    for (uint32_t k = sub; k < c; k += kRepLanes * kRepUnroll) {
+        float4 a[kRepUnroll];
+#pragma unroll
+        for (int u = 0; u < kRepUnroll; ++u) {
+            const uint32_t j = k + (uint32_t)(u * kRepLanes);
+            if (j < c) a[u] = src[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kRepUnroll; ++u) {
+            const uint32_t j = k + (uint32_t)(u * kRepLanes);
+            if (j < c) dst[j] = a[u];
+        }
+    }
+}
+
 }  // namespace
+
+void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint32_t* cnt, float4* blk, uint32_t cap,
+                      hipStream_t s)
+{
+    if (V <= 0 || !state) return;
+    const int64_t blocks = (V + 256 / kRepLanes - 1) / (256 / kRepLanes);
+    hipLaunchKernelGGL(k_replicate, dim3((unsigned)blocks), dim3(256), 0, s, pd, state, cnt, blk, cap);
+}
 
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block, const uint32_t* hist,
                         const uint32_t* off, uint32_t* vm, uint2* dir, const uint32_t* src, uint32_t* dst, int first,

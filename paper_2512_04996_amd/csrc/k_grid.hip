@@ -103,11 +103,18 @@ __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx,
 // --------------------------------------------------------------------------
 constexpr int kSlots = 2 * kThreads;
 
+//
+// kDirect: VANICP's monolithic layout instead.  The point's slot is its
+// position in the voxel's fixed block of `cap` records, and the point is
+// copied there as (x, y, z, index) when the block has room; `hist` then
+// counts every point of the voxel, so a count above `cap` marks a block that
+// overflowed.
+template <bool kDirect>
 __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const float* __restrict__ qz, const PairDev* __restrict__ pd,
                                                     const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
                                                     uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
-                                                    uint32_t* err)
+                                                    uint32_t* err, float4* __restrict__ blk, uint32_t cap)
 {
     __shared__ uint32_t skey[kSlots];
     __shared__ uint32_t scnt[kSlots];
@@ -123,9 +130,13 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
     bool valid = i < P.n;
     uint32_t v = 0, slot = 0, lr = 0;
     int64_t g = 0;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
     if (valid) {
         g = P.q_base + i;
-        if (!voxel_id(P, qx[g], qy[g], qz[g], v)) {
+        x = qx[g];
+        y = qy[g];
+        z = qz[g];
+        if (!voxel_id(P, x, y, z, v)) {
             atomicOr(err, 1u);   // cannot happen for a target inside its own box
             valid = false;
         }
@@ -146,8 +157,13 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
     }
     __syncthreads();
     if (valid) {
-        vox[g] = v;
-        rank[g] = sbase[slot] + lr;
+        const uint32_t r = sbase[slot] + lr;
+        if (kDirect) {
+            if (r < cap) blk[(P.v_base + v) * (int64_t)cap + r] = make_float4(x, y, z, __uint_as_float((uint32_t)i));
+        } else {
+            vox[g] = v;
+            rank[g] = r;
+        }
     }
 }
 
@@ -462,7 +478,16 @@ void launch_count(const float* qx, const float* qy, const float* qz, const PairD
         hipLaunchKernelGGL(k_count_packed, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
                            err);
     else
-        hipLaunchKernelGGL(k_count, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
+        hipLaunchKernelGGL(k_count<false>, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
+                           err, (float4*)nullptr, 0u);
+}
+
+void launch_count_direct(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
+                         int njobs, uint32_t* cnt, uint32_t* err, float4* blk, uint32_t cap, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_count<true>, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, cnt,
+                       (uint32_t*)nullptr, (uint32_t*)nullptr, err, blk, cap);
 }
 
 bool count_packed_fits(int64_t voxels) { return voxels < ((int64_t)1 << kPackKeyBits); }

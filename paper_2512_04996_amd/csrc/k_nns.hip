@@ -74,21 +74,24 @@ __device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int d)
 __device__ __forceinline__ float xor_lanes(float x, int d) { return __uint_as_float(xor_lanes(__float_as_uint(x), d)); }
 
 // Selects, not branches: a branch lets the compiler sink the index load into
-// the taken path and then wait for every load in flight.
+// the taken path and then wait for every load in flight.  kTies: candidates
+// come in no particular order, so equal distances compare indices.
+template <bool kTies>
 __device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj)
 {
     const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-    const bool better = d < bd;
+    const bool better = d < bd || (kTies && d == bd && __float_as_uint(q.w) < bj);
     bd = better ? d : bd;
     bj = better ? __float_as_uint(q.w) : bj;
 }
 
 // The same, also keeping the best candidate's coordinates.
+template <bool kTies>
 __device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj,
                                          float& bx, float& by, float& bz)
 {
     const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
-    const bool better = d < bd;
+    const bool better = d < bd || (kTies && d == bd && __float_as_uint(q.w) < bj);
     bd = better ? d : bd;
     bj = better ? __float_as_uint(q.w) : bj;
     bx = better ? q.x : bx;
@@ -111,7 +114,14 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // b at [b * kMoments + j], counter k at [b * 3 + k], one contiguous record per
 // block.  Queries sent to the global search add their moments later, once
 // resolved.  Launch blocks are mapped to jobs XCD by XCD (xcd_job).
-template <int BS, int LPQ, bool kSorted, bool kMom>
+//
+// kDirect: VANICP's monolithic layout (the comparator).  Voxel g's
+// candidates are the records of its own fixed block, at g * cap, and its
+// count word dcnt[g] (the root's count with the mask bit for a dilated
+// voxel); a count above cap means an overflowed block and sends the query to
+// the global search.  Records are in the order the voxelisation's atomics
+// gave them, so ties compare indices.
+template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -121,7 +131,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
                                                   unsigned long long* __restrict__ ctr, double* __restrict__ part,
-                                                  int all_global)
+                                                  int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
     constexpr int kWaves = BS / kWave;
@@ -157,10 +167,18 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         // all_global: every query takes the exact global search (the
         // exhaustive-NNS comparator)
         if (!all_global && voxel_of(P, sx, sy, sz, v)) {
-            const uint2 e = dir[P.v_base + v];
-            c = e.y & ~kMask;
-            cs = e.x;
-            dil = (e.y & kMask) != 0u;
+            if (kDirect) {
+                const uint32_t e = dcnt[P.v_base + v];
+                const uint32_t cn = e & ~kMask;
+                c = cn <= cap ? cn : 0u;
+                cs = (P.v_base + (int64_t)v) * (int64_t)cap;
+                dil = (e & kMask) != 0u && c != 0u;
+            } else {
+                const uint2 e = dir[P.v_base + v];
+                c = e.y & ~kMask;
+                cs = e.x;
+                dil = (e.y & kMask) != 0u;
+            }
         }
     }
     const int64_t gp = P.p_base + i;
@@ -195,8 +213,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             for (int u = 0; u < U; ++u) a[u] = seg[min(k + (uint32_t)(u * LPQ), last)];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (kMom) consider(a[u], sx, sy, sz, bd, bj, bx, by, bz);
-                else consider(a[u], sx, sy, sz, bd, bj);
+                if (kMom) consider<kDirect>(a[u], sx, sy, sz, bd, bj, bx, by, bz);
+                else consider<kDirect>(a[u], sx, sy, sz, bd, bj);
             }
         }
     }
@@ -548,36 +566,43 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
                       const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
                       uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      int all_global, hipStream_t s)
+                      int all_global, const uint32_t* dcnt, uint32_t cap, hipStream_t s)
 {
     if (njobs <= 0) return;
-#define VICP_NNS(BS, L, SORTED, MOM)                                                                                 \
-    launch_timed(k_nns_local<BS, L, SORTED, MOM>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, ps4, st, dir,  \
-                 qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global)
-#define VICP_NNS_L(BS, SORTED, MOM)                  \
-    switch (lpq) {                                   \
-    case 2: VICP_NNS(BS, 2, SORTED, MOM); break;     \
-    case 4: VICP_NNS(BS, 4, SORTED, MOM); break;     \
-    case 8: VICP_NNS(BS, 8, SORTED, MOM); break;     \
-    default: VICP_NNS(BS, 1, SORTED, MOM); break;    \
+#define VICP_NNS(BS, L, SORTED, MOM, DIRECT)                                                                       \
+    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, ps4,  \
+                 st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
+#define VICP_NNS_L(BS, SORTED, MOM, DIRECT)                  \
+    switch (lpq) {                                           \
+    case 2: VICP_NNS(BS, 2, SORTED, MOM, DIRECT); break;     \
+    case 4: VICP_NNS(BS, 4, SORTED, MOM, DIRECT); break;     \
+    case 8: VICP_NNS(BS, 8, SORTED, MOM, DIRECT); break;     \
+    default: VICP_NNS(BS, 1, SORTED, MOM, DIRECT); break;    \
     }
-#define VICP_NNS_BS(SORTED, MOM)                     \
-    switch (block) {                                 \
-    case 128: VICP_NNS_L(128, SORTED, MOM); break;   \
-    case 512: VICP_NNS_L(512, SORTED, MOM); break;   \
-    default: VICP_NNS_L(256, SORTED, MOM); break;    \
+#define VICP_NNS_BS(SORTED, MOM, DIRECT)                     \
+    switch (block) {                                         \
+    case 128: VICP_NNS_L(128, SORTED, MOM, DIRECT); break;   \
+    case 512: VICP_NNS_L(512, SORTED, MOM, DIRECT); break;   \
+    default: VICP_NNS_L(256, SORTED, MOM, DIRECT); break;    \
     }
-    if (mom) {
+    // the direct layout serves registrations only
+    if (dcnt && mom) {
         if (sorted) {
-            VICP_NNS_BS(true, true)
+            VICP_NNS_BS(true, true, true)
         } else {
-            VICP_NNS_BS(false, true)
+            VICP_NNS_BS(false, true, true)
+        }
+    } else if (mom) {
+        if (sorted) {
+            VICP_NNS_BS(true, true, false)
+        } else {
+            VICP_NNS_BS(false, true, false)
         }
     } else {
         if (sorted) {
-            VICP_NNS_BS(true, false)
+            VICP_NNS_BS(true, false, false)
         } else {
-            VICP_NNS_BS(false, false)
+            VICP_NNS_BS(false, false, false)
         }
     }
 #undef VICP_NNS_BS

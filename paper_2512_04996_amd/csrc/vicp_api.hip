@@ -398,6 +398,16 @@ struct vicp_grid {
     std::vector<uint32_t> h_hist, h_off;
     float f_origin[3] = {0, 0, 0};
     int32_t f_dims[3] = {0, 0, 0};
+    // VANICP's monolithic layout, built beside the segmented one as a
+    // comparator (single pair): V fixed blocks of dcap 16-byte records and a
+    // count word per voxel.  Allocated directly (tens of GB at 64 KiB per
+    // voxel), freed by vicp_direct_free or with the grid.
+    float4* dblk = nullptr;
+    size_t dblk_bytes = 0;
+    uint32_t* dcnt = nullptr;
+    size_t dcnt_bytes = 0;
+    uint32_t dcap = 0;
+    bool direct_ready = false;   // false again after any rebuild
     std::vector<BlockJob> h_jobs_q8;
     void* staging = nullptr;
     int32_t* fb_count = nullptr;
@@ -674,15 +684,16 @@ void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz,
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
 // mom: registration form (per-block moment partials instead of per-query
 // results).  all_global: every query takes the exact global search.
+// direct: search VANICP's monolithic layout instead (registration form).
 void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
-                  hipStream_t s, bool cap, bool mom, bool all_global = false)
+                  hipStream_t s, bool cap, bool mom, bool all_global = false, bool direct = false)
 {
     const int tab = table_of(g->nns_block / g->nns_lpq);
     {
-        ProfScope ps("nns_local", s, cap, true);
+        ProfScope ps(direct ? "nns_direct" : "nns_local", s, cap, true);
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
-                         pz, g->ps4, g->st, g->dir, g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list, g->fb_key, g->ctr,
-                         g->npart, all_global ? 1 : 0, s);
+                         pz, g->ps4, g->st, g->dir, direct ? g->dblk : g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list,
+                         g->fb_key, g->ctr, g->npart, all_global ? 1 : 0, direct ? g->dcnt : nullptr, g->dcap, s);
     }
     {
         ProfScope ps("fallback", s, cap, true);
@@ -693,9 +704,9 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
 }
 
 void queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
-                     double eps, hipStream_t s, bool cap, bool all_global)
+                     double eps, hipStream_t s, bool cap, bool all_global, bool direct)
 {
-    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true, all_global);
+    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true, all_global, direct);
     ProfScope ps("solve", s, cap, true);
     const int tab = table_of(g->nns_block / g->nns_lpq);
     launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
@@ -757,6 +768,7 @@ float unordered(uint32_t k)
 int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
     const int B = g->B;
+    g->direct_ready = false;
     std::vector<PairHost> pairs = g->pairs;
     int64_t Vt = 0, words = 0;
     if (g->fixed) {
@@ -1064,6 +1076,82 @@ int vicp_set_build_options(vicp_grid* g, int32_t host_offsets, int32_t packed_ha
     return VICP_OK;
 }
 
+// VANICP's layout for the comparison (Sec. II.B; Sec. III and Fig. 1
+// contrast it with the segmented layout): the target is voxelised straight
+// into fixed per-voxel blocks, the same rings of dilation run on the block
+// counts, and every dilated voxel's block receives a copy of its root's
+// records.
+int vicp_direct_build(vicp_grid* g, int64_t block_bytes, hipStream_t s)
+{
+    (void)hipGetLastError();   // an error left by other code is not ours to report
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (g->B != 1) return fail(VICP_ERR_INVALID_ARG, "the direct layout needs a single-pair grid");
+    if (!g->dilated) return fail(VICP_ERR_STATE, "dilate the grid first (the direct layout uses the same rings)");
+    if (block_bytes < 16 || block_bytes % 16 != 0 || block_bytes / 16 > 0x7FFFFFFF)
+        return fail(VICP_ERR_INVALID_ARG, "block_bytes must be a positive multiple of 16 below 2^35");
+    const int64_t V = g->V_total;
+    if (V > (int64_t)(SIZE_MAX / 2) / block_bytes) return fail(VICP_ERR_GRID_TOO_LARGE, "direct layout too large");
+    const size_t need = (size_t)V * (size_t)block_bytes, need_c = sizeof(uint32_t) * (size_t)V;
+    g->direct_ready = false;
+    if (g->dblk_bytes != need || g->dcnt_bytes != need_c) {
+        VICP_HIP(hipStreamSynchronize(s));
+        vicp_direct_free(g);
+        void* b = nullptr;
+        void* c = nullptr;
+        if (hipMalloc(&b, need) != hipSuccess || hipMalloc(&c, need_c) != hipSuccess) {
+            (void)hipGetLastError();
+            if (b) (void)hipFree(b);
+            return fail(VICP_ERR_OOM, "direct layout: device allocation of " + std::to_string(need) + " bytes failed");
+        }
+        g->dblk = (float4*)b;
+        g->dblk_bytes = need;
+        g->dcnt = (uint32_t*)c;
+        g->dcnt_bytes = need_c;
+    }
+    g->dcap = (uint32_t)(block_bytes / 16);
+    const bool cap = capturing(s);
+    {
+        ProfScope ps("direct_count", s, cap);
+        launch_fill_u32(g->dcnt, 0u, V, s);
+        launch_count_direct(g->qx, g->qy, g->qz, g->d_pd, g->jobs_q, g->njobs_q, g->dcnt, g->err, g->dblk, g->dcap,
+                            s);
+    }
+    // the segmented grid's ring-state arrays are free once it is dilated
+    uint32_t* a = g->dil_a;
+    uint32_t* b = g->dil_b;
+    const int rings = g->rings_applied;
+    for (int r = 1; r <= rings; ++r) {
+        ProfScope ps("direct_dilate_ring", s, cap);
+        launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, 256, g->dcnt, nullptr, nullptr, nullptr,
+                           r == 1 ? nullptr : a, b, r == 1, 0, s);
+        std::swap(a, b);
+    }
+    {
+        ProfScope ps("direct_replicate", s, cap);
+        launch_replicate(g->d_pd, V, rings > 0 ? a : nullptr, g->dcnt, g->dblk, g->dcap, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("direct build: ") + hipGetErrorString(e));
+    g->direct_ready = true;
+    return VICP_OK;
+}
+
+int vicp_direct_free(vicp_grid* g)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (!g->dblk && !g->dcnt) return VICP_OK;
+    (void)hipDeviceSynchronize();
+    g->drop_graph();   // a captured registration may point at the blocks
+    if (g->dblk) (void)hipFree(g->dblk);
+    if (g->dcnt) (void)hipFree(g->dcnt);
+    g->dblk = nullptr;
+    g->dcnt = nullptr;
+    g->dblk_bytes = g->dcnt_bytes = 0;
+    g->direct_ready = false;
+    return VICP_OK;
+}
+
 int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
 {
     (void)hipGetLastError();   // an error left by other code is not ours to report
@@ -1162,13 +1250,17 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     const int early = o->early_stop ? 1 : 0;
     const double eps = o->rmse_eps;
     const bool all_global = o->global_only != 0;
+    const bool direct = o->layout != 0;
+    if (direct && all_global) return fail(VICP_ERR_INVALID_ARG, "global_only and the direct layout exclude each other");
+    if (direct && !g->direct_ready) return fail(VICP_ERR_STATE, "no direct layout: call vicp_direct_build first");
     upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
     launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, g->fb_count, g->flags, s);
     launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
-                                      (uintptr_t)g->sort_src, (uintptr_t)all_global,
+                                      (uintptr_t)g->sort_src, (uintptr_t)all_global, (uintptr_t)direct,
+                                      (uintptr_t)g->dblk,
                                       (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
         uint64_t eb;
         memcpy(&eb, &eps, 8);
@@ -1186,7 +1278,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                 t_capture_events = attempt == 0 ? &g->gevents : nullptr;
                 if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
                 for (int k = 0; k < K; ++k)
-                    queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global);
+                    queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global, direct);
                 t_capture_events = nullptr;
                 hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
                 hipError_t e = ec;
@@ -1209,7 +1301,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     } else {
         const bool cap = capturing(s);
         if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-        for (int k = 0; k < K; ++k) queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global);
+        for (int k = 0; k < K; ++k)
+            queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global, direct);
     }
     VICP_HIP(hipMemcpyAsync(g->h_res, g->res, g->res_bytes, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
@@ -1378,6 +1471,7 @@ int vicp_grid_free(vicp_grid* g)
     if (!g) return VICP_OK;
     (void)hipDeviceSynchronize();
     g->drop_graph();
+    (void)vicp_direct_free(g);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->release(g->ws_bufs, nullptr);
     g->release(g->vbufs, nullptr);

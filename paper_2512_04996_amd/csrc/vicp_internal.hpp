@@ -234,6 +234,11 @@ void launch_count(const float* qx, const float* qy, const float* qz, const PairD
                   const BlockJob* jobs, int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank,
                   uint32_t* err, bool packed, hipStream_t s);
 bool count_packed_fits(int64_t voxels);
+// VANICP's layout: counts every point of a voxel into cnt and copies it into
+// the voxel's block of cap records when it fits
+void launch_count_direct(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                         const BlockJob* jobs, int njobs, uint32_t* cnt, uint32_t* err, float4* blk,
+                         uint32_t cap, hipStream_t s);
 void launch_seg_headers(const uint32_t* hist, const uint32_t* off, int64_t total, uint32_t* vm, uint2* dir,
                         hipStream_t s);
 int scan_tiles(int64_t total);
@@ -254,6 +259,10 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
                         const uint32_t* hist, const uint32_t* off, uint32_t* vm, uint2* dir,
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
+// VANICP's layout (single pair): copies each dilated voxel's root records
+// into its block, from the ring state (own id, root id or none per voxel)
+void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint32_t* cnt, float4* blk,
+                      uint32_t cap, hipStream_t s);
 
 // search and moments
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
@@ -261,7 +270,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const PairState* st, const uint2* dir, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
                       unsigned long long* fb_key, unsigned long long* ctr, double* part, int all_global,
-                      hipStream_t s);
+                      const uint32_t* dcnt, uint32_t cap, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
                        int32_t* sbig, hipStream_t s);
