@@ -58,17 +58,31 @@ __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx,
     const PairDev& P = pd[job.pair];
     uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u}, bad = 0;
     const int64_t end = min((int64_t)job.start + items, P.n);
-    for (int64_t i = job.start + threadIdx.x; i < end; i += kThreads) {
-        const int64_t g = P.q_base + i;
-        float c[3] = {qx[g], qy[g], qz[g]};
-        for (int a = 0; a < 3; ++a) {
-            if (!isfinite(c[a])) {
-                bad = 1;
-                continue;
+    // kAabbUnroll points per thread per round, every load issued before the
+    // first compare (a load-compare loop waits for each point in turn)
+    constexpr int kAabbUnroll = 8;
+    for (int64_t i0 = job.start + threadIdx.x; i0 < end; i0 += (int64_t)kAabbUnroll * kThreads) {
+        float c[kAabbUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kAabbUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kThreads;
+            const int64_t g = P.q_base + (i < end ? i : job.start);
+            c[u][0] = qx[g];
+            c[u][1] = qy[g];
+            c[u][2] = qz[g];
+        }
+#pragma unroll
+        for (int u = 0; u < kAabbUnroll; ++u) {
+            if (i0 + (int64_t)u * kThreads >= end) continue;
+            for (int a = 0; a < 3; ++a) {
+                if (!isfinite(c[u][a])) {
+                    bad = 1;
+                    continue;
+                }
+                uint32_t o = ordered(c[u][a]);
+                mn[a] = min(mn[a], o);
+                mx[a] = max(mx[a], o);
             }
-            uint32_t o = ordered(c[a]);
-            mn[a] = min(mn[a], o);
-            mx[a] = max(mx[a], o);
         }
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -371,10 +385,6 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
         const int64_t g = base + k;
         s_o[threadIdx.x * kPad + k] = run;
         if (g < total) {
-            if (kSeg) {
-                vm[run] = 0u;
-                vm[run + 1] = h[k];
-            }
             run += h[k] + (kSeg ? 2u : 0u);
             if (g == total - 1) off[total] = run;
         }
@@ -387,7 +397,14 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
         if (g < total) {
             const uint32_t o = s_o[lds(idx)];
             off[g] = o;
-            if (kSeg) dir[g] = make_uint2(o - 2u * (uint32_t)g, s_h[lds(idx)]);
+            if (kSeg) {
+                // segment headers from the striped layout too: neighbouring
+                // lanes write neighbouring segments
+                const uint32_t c = s_h[lds(idx)];
+                vm[o] = 0u;
+                vm[o + 1] = c;
+                dir[g] = make_uint2(o - 2u * (uint32_t)g, c);
+            }
         }
     }
 }

@@ -452,13 +452,30 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
             const FoldJob fj = fjobs[u];
             if (st[fj.pair].done) continue;   // uniform over the block
             const int cnt = fj.b1 - fj.b0;
-            for (int e = threadIdx.x; e < kMoments * cnt; e += kFbThreads) {
-                const int bb = e / kMoments, j = e - bb * kMoments;
-                fv[j][bb] = part[(int64_t)fj.b0 * kMoments + e];
+            // every load in flight before the first LDS store (a load-store
+            // loop waits for each load in turn)
+            constexpr int kLoads = (kMoments * kFoldChunk + kFbThreads - 1) / kFbThreads;
+            static_assert(3 * kFoldChunk <= kFbThreads, "one counter load per thread");
+            const double* src = part + (int64_t)fj.b0 * kMoments;
+            double v[kLoads];
+#pragma unroll
+            for (int r = 0; r < kLoads; ++r) {
+                const int e = threadIdx.x + r * kFbThreads;
+                v[r] = e < kMoments * cnt ? src[e] : 0.0;
             }
-            for (int e = threadIdx.x; e < 3 * cnt; e += kFbThreads) {
-                const int bb = e / 3, j = e - bb * 3;
-                if (j < 2) fc[j][bb] = ctr[(int64_t)fj.b0 * 3 + e];
+            const int ec = threadIdx.x;
+            const unsigned long long cv = ec < 3 * cnt ? ctr[(int64_t)fj.b0 * 3 + ec] : 0ull;
+#pragma unroll
+            for (int r = 0; r < kLoads; ++r) {
+                const int e = threadIdx.x + r * kFbThreads;
+                if (e < kMoments * cnt) {
+                    const int bb = e / kMoments, j = e - bb * kMoments;
+                    fv[j][bb] = v[r];
+                }
+            }
+            if (ec < 3 * cnt) {
+                const int bb = ec / 3, j = ec - bb * 3;
+                if (j < 2) fc[j][bb] = cv;
             }
             __syncthreads();
             if (threadIdx.x < kMoments) {
