@@ -57,7 +57,8 @@ __device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, f
     const float fx = (sx - P.ox) * P.inv;
     const float fy = (sy - P.oy) * P.inv;
     const float fz = (sz - P.oz) * P.inv;
-    const bool in = (fx >= 0.0f) && (fx < P.fDx) && (fy >= 0.0f) && (fy < P.fDy) && (fz >= 0.0f) && (fz < P.fDz);
+    // non-short-circuit: no branch waits on each bound's load in turn
+    const bool in = (fx >= 0.0f) & (fx < P.fDx) & (fy >= 0.0f) & (fy < P.fDy) & (fz >= 0.0f) & (fz < P.fDz);
     if (in) v = (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
     return in;
 }
@@ -139,29 +140,39 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     const BlockJob job = jobs[jb];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
-    if (S.done) return;   // uniform over the block
     const int sub = threadIdx.x % LPQ;
     const int64_t t = (int64_t)job.start + threadIdx.x / LPQ;
-    const bool active = t < P.m;
+    const bool inrange = t < P.m;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t c = 0, i = 0;
     int64_t cs = 0;
     float x = 0.0f, y = 0.0f, z = 0.0f;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     bool dil = false;
-    if (active) {
+    // The query's load goes out unconditionally (a lane past the end reads
+    // the block's first query, which exists) and does not wait for the
+    // pair's done flag, so the two latencies overlap.  A finished pair's
+    // block runs with no active lane: it searches nothing and appends
+    // nothing, and its partials are never read (the fold and the solve skip
+    // finished pairs).  An early return would let the compiler sink the load
+    // below the flag's test.
+    {
+        const int64_t tl = P.p_base + (inrange ? t : (int64_t)job.start);
         if (kSorted) {
-            const float4 pp = ps4[P.p_base + t];
+            const float4 pp = ps4[tl];
             x = pp.x;
             y = pp.y;
             z = pp.z;
             i = __float_as_uint(pp.w);
         } else {
-            x = px[P.p_base + t];
-            y = py[P.p_base + t];
-            z = pz[P.p_base + t];
-            i = (uint32_t)t;
+            x = px[tl];
+            y = py[tl];
+            z = pz[tl];
+            i = (uint32_t)(tl - P.p_base);
         }
+    }
+    const bool active = inrange && S.done == 0;
+    if (active) {
         transform(S.Rtf, x, y, z, sx, sy, sz);
         uint32_t v;
         // all_global: every query takes the exact global search (the
@@ -244,12 +255,9 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         nn_idx[gp] = (int32_t)bj;
         nn_d2[gp] = bd;
     }
-    // Reductions over the block in a fixed order: values live in the lanes
-    // that hold a query (multiples of LPQ), so each row of 16 lanes is summed
-    // with DPP steps of LPQ, 2 LPQ, ... 8 and its total (in lane 16 - LPQ)
-    // goes to LDS; then one thread per entry adds the rows in order.
-    // Counters are exact integers (candidates scanned per row, dilated
-    // lookups and global-search queries per wave by popcount).
+    // Reductions over the block in a fixed order.  Counters are exact
+    // integers (candidates scanned per 16-lane row by DPP, dilated lookups and
+    // global-search queries per wave by popcount).
     constexpr int kRows = 4 * kWaves;
     const int row = w * 4 + (lane >> 4);
     const bool row_end = (lane & 15) == 16 - LPQ;
@@ -263,47 +271,58 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         wred[1][w] = (uint32_t)__popcll(mmask);
     }
     if (kMom) {
-        // moments of this lane's query about the grid centre; zero for lanes
-        // that hold no resolved query (selects, so nothing else is read).
-        // The two squared norms only set the solve's rounding floor and are
-        // summed in float32; the count is a popcount.
-        __shared__ double mred[kMoments - 1][kRows];
+        // Moments of this lane's query about the grid centre, zero for a
+        // query not resolved here (selects, so nothing else is read).  Each
+        // query's first lane stores its 18 values in LDS (LDS stores, not
+        // vector instructions: cross-lane float64 sums by DPP cost the search
+        // more issue slots than its gather), one row of kStride (odd) words
+        // per query so that neither the row stores nor the column reads
+        // below fall on one bank; then kSlices threads per entry each add an
+        // interleaved slice of the queries in order, and one thread per entry
+        // adds its slices in order.  The count is a popcount.
+        constexpr int kQ = BS / LPQ;
+        constexpr int kSums = kMoments - 1;
+        constexpr int kSlices = 18 * 16 <= BS ? 16 : (18 * 8 <= BS ? 8 : 4);
+        static_assert(kSums * kSlices <= BS && kQ % kSlices == 0, "slice layout");
+        constexpr int kStride = kSums | 1;
+        __shared__ double mq[kQ * kStride];
+        __shared__ double ms[kSums][kSlices];
         __shared__ uint32_t mcnt[kWaves];
         const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
         const double p[3] = {found ? (double)x - c0 : 0.0, found ? (double)y - c1 : 0.0,
                              found ? (double)z - c2 : 0.0};
         const double q[3] = {found ? (double)bx - c0 : 0.0, found ? (double)by - c1 : 0.0,
                              found ? (double)bz - c2 : 0.0};
-        double a[16];   // sum p, sum q, sum p q^T, sum d
+        if (sub == 0) {
+            double* row = mq + (threadIdx.x / LPQ) * kStride;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            a[r] = p[r];
-            a[3 + r] = q[r];
+            for (int r = 0; r < 3; ++r) {
+                row[r] = p[r];
+                row[3 + r] = q[r];
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) a[6 + 3 * r + cc] = p[r] * q[cc];
-        }
-        a[15] = found ? (double)bd : 0.0;
-        const float np = (float)(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-        const float nq = (float)(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double sm = row_sum_f64<LPQ>(a[j]);
-            if (row_end) mred[j == 15 ? 17 : j][row] = sm;
-        }
-        const float snp = row_sum_f32<LPQ>(np), snq = row_sum_f32<LPQ>(nq);
-        if (row_end) {
-            mred[15][row] = (double)snp;
-            mred[16][row] = (double)snq;
+                for (int cc = 0; cc < 3; ++cc) row[6 + 3 * r + cc] = p[r] * q[cc];
+            }
+            row[15] = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+            row[16] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+            row[17] = found ? (double)bd : 0.0;
         }
         const uint32_t nfound = (uint32_t)__popcll(__ballot(found));
         if (lane == 0) mcnt[w] = nfound;
         __syncthreads();
-        if (threadIdx.x < kMoments - 1) {
-            double sm = mred[threadIdx.x][0];
+        if (threadIdx.x < kSums * kSlices) {
+            const int j = threadIdx.x / kSlices, sl = threadIdx.x % kSlices;
+            double sm = mq[sl * kStride + j];
 #pragma unroll
-            for (int r = 1; r < kRows; ++r) sm += mred[threadIdx.x][r];
+            for (int e = 1; e < kQ / kSlices; ++e) sm += mq[(sl + e * kSlices) * kStride + j];
+            ms[j][sl] = sm;
+        }
+        __syncthreads();
+        if (threadIdx.x < kSums) {
+            double sm = ms[threadIdx.x][0];
+#pragma unroll
+            for (int e = 1; e < kSlices; ++e) sm += ms[threadIdx.x][e];
             part[(int64_t)jb * kMoments + threadIdx.x] = sm;
-        } else if (threadIdx.x == kMoments - 1) {
+        } else if (threadIdx.x == kSums) {
             uint32_t cn = 0;
             for (int q2 = 0; q2 < kWaves; ++q2) cn += mcnt[q2];
             part[(int64_t)jb * kMoments + kMoments - 1] = (double)cn;
@@ -449,8 +468,9 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
         __shared__ double fv[kMoments][kFoldChunk];
         __shared__ unsigned long long fc[2][kFoldChunk];
         for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+            // a finished pair's units are folded too (their sums go unused):
+            // testing its flag first would delay every load behind it
             const FoldJob fj = fjobs[u];
-            if (st[fj.pair].done) continue;   // uniform over the block
             const int cnt = fj.b1 - fj.b0;
             // every load in flight before the first LDS store (a load-store
             // loop waits for each load in turn)

@@ -329,10 +329,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const int32_t u0 = fold_begin[pair], u1 = fold_begin[pair + 1];
     const int32_t nfb = fb_count[pair];
     const double prev = S.prev_rmse;
-    double Rp[9];   // the current rotation: the start of the polar refinement
+    // the current rotation, the start of the polar refinement: read by every
+    // thread (uniform loads, all in flight together; a per-thread condition
+    // made the compiler wait for each in turn), used by thread 0
+    double Rp[9];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) Rp[j] = threadIdx.x == 0 ? S.Rt[j] : 0.0;
-    if (done) return;   // uniform over the block
+    for (int j = 0; j < 9; ++j) Rp[j] = S.Rt[j];
     if (threadIdx.x < kMoments) {
         const double* row = fpart + (int64_t)threadIdx.x * nunits;
         double sm = 0.0;
@@ -356,6 +358,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
         }
         ctot[threadIdx.x - kMoments] = sm;
     }
+    // tested after the fold, whose loads do not depend on it, so that the
+    // flag's latency overlaps theirs (a finished pair's fold units hold
+    // stale sums that are never used)
+    if (done) return;   // uniform over the block
     const double cen[3] = {P.cx, P.cy, P.cz};
     if (nfb > 0) {   // uniform over the block
         const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;

@@ -116,42 +116,15 @@ __device__ __forceinline__ double dpp_add(double x)
     return x + __hiloint2double(hi, lo);
 }
 
-// Sum inside each row of 16 lanes in a fixed order (an inclusive scan) of
-// values held in the lanes that are multiples of STRIDE (the others hold
-// zero): steps of STRIDE, 2 STRIDE, ... 8, and the row's total ends in lane
-// 16 - STRIDE of the row.
-template <int STRIDE>
-__device__ __forceinline__ double row_sum_f64(double x)
-{
-    if (STRIDE <= 1) x = dpp_add<0x111, 0xF>(x);   // row_shr:1
-    if (STRIDE <= 2) x = dpp_add<0x112, 0xF>(x);   // row_shr:2
-    if (STRIDE <= 4) x = dpp_add<0x114, 0xF>(x);   // row_shr:4
-    x = dpp_add<0x118, 0xF>(x);                    // row_shr:8
-    return x;
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_add_f32(float x)
-{
-    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
-}
-
-template <int STRIDE>
-__device__ __forceinline__ float row_sum_f32(float x)
-{
-    if (STRIDE <= 1) x = dpp_add_f32<0x111, 0xF>(x);
-    if (STRIDE <= 2) x = dpp_add_f32<0x112, 0xF>(x);
-    if (STRIDE <= 4) x = dpp_add_f32<0x114, 0xF>(x);
-    x = dpp_add_f32<0x118, 0xF>(x);
-    return x;
-}
-
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp_add_u32(uint32_t x)
 {
     return x + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, true);
 }
 
+// Sum inside each row of 16 lanes (an inclusive scan) of values held in the
+// lanes that are multiples of STRIDE (the others hold zero): steps of
+// STRIDE, 2 STRIDE, ... 8; the row's total ends in lane 16 - STRIDE.
 template <int STRIDE>
 __device__ __forceinline__ uint32_t row_sum_u32(uint32_t x)
 {
