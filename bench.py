@@ -113,13 +113,31 @@ def main():
         res = step()
     log("[bench] warmup done")
     torch.cuda.synchronize()
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        res = step()
+        ts = time.perf_counter()
+        res = step()   # ends with the registration's result copy, a stream synchronisation
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("[bench] timed region done")
     ms = (t1 - t0) * 1e3 / a.steps
+    # the two parts of a step on their own: the grid refill + dilation, and
+    # the registration (one graph replay of the K iterations)
+    reps = max(5, min(a.steps, 20))
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(reps):
+        g.rebuild(q)
+        g.dilate(P.rings)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3 / reps
+    reg_ms = []
+    for _ in range(reps):
+        ts = time.perf_counter()
+        g.register(p, P.iters, use_graph=bool(a.graph))
+        reg_ms.append((time.perf_counter() - ts) * 1e3)
     K = int(res.iters[0])
     queries_per_s = K * P.m / (ms * 1e-3)
     kernels = {}
@@ -168,11 +186,55 @@ def main():
 
     desc = g.describe()
     g.free()
+    ours = desc["dynamic_bytes"] + desc["static_bytes"]
     dil_bytes = {"workload": P.name, "V": desc["V"], "occupied": desc["occupied"], "dilated": desc["dilated"],
                  "dynamic_bytes": desc["dynamic_bytes"], "static_bytes": desc["static_bytes"],
                  "vanicp_fixed_bytes": desc["vanicp_bytes"],
-                 "saving": round(1.0 - (desc["dynamic_bytes"] + desc["static_bytes"]) / desc["vanicp_bytes"], 6),
+                 "saving": round(1.0 - ours / desc["vanicp_bytes"], 6),
+                 # not graded: 64 KiB for the occupied and dilated voxels only,
+                 # and a tight uniform block of (largest count + 2) words per voxel
+                 "vanicp_occupied_dilated_bytes": 65536 * (desc["occupied"] + desc["dilated"]),
+                 "saving_vs_occupied_dilated": round(1.0 - ours / (65536 * (desc["occupied"] + desc["dilated"])), 6),
+                 "tight_uniform_bytes": (desc["max_count"] + 2) * 4 * desc["V"],
                  "extra_device_bytes": desc["extra_bytes"]}
+    # global atomics of the count: one per distinct (256-point block, voxel)
+    # after the LDS hash, against one per point without it (float32
+    # quantisation as the kernel's, computed here with numpy)
+    o32 = np.asarray(desc["origin"], np.float32)
+    inv32 = np.float32(desc["inv"])
+    f = (P.q - o32[:, None]) * inv32
+    ijk = np.floor(f).astype(np.int64)
+    dims = np.asarray(desc["dims"], np.int64)
+    vox = ijk[0] + dims[0] * (ijk[1] + dims[1] * ijk[2])
+    blk = np.arange(P.n) // 256
+    atomics = int(np.unique(blk * desc["V"] + vox).size)
+    # the dilation ring's compulsory bytes: 8 per voxel (own state in, state
+    # or result out) and 4 per newly dilated voxel
+    dilation_roof = None
+    if "dilate_ring" in kernels:
+        ring_bytes = 8 * desc["V"] + 4 * desc["dilated"] / max(P.rings, 1)
+        ach = ring_bytes / (kernels["dilate_ring"]["avg_us"] * 1e-6) / 1e9
+        dilation_roof = {"kernel": "k_dilate_ring<256>", "bound": "hbm", "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "compulsory_bytes_per_ring": int(ring_bytes)}
+    search_qps = None
+    if "nns_local" in kernels and "fallback" in kernels:
+        it_us = kernels["nns_local"]["avg_us"] + kernels["fallback"]["avg_us"]
+        search_qps = round(P.m / (it_us * 1e-6), 1)
+    # attainable bandwidth: a plain device-to-device copy of 1 GiB (with the
+    # timing pass only: profiler runs keep their copies to the calibration one)
+    if roofline is not None:
+        nel = (1 << 30) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        roofline["attainable_copy_gbs"] = round(2.0 * (1 << 30) * 10 / (time.perf_counter() - tc) / 1e9, 1)
+        del src, dst
 
     out = {
         "metric": METRIC, "value": round(queries_per_s, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
@@ -184,7 +246,17 @@ def main():
                    "schedule_source": "autotuned" if a.schedule == "auto" else "given",
                    "kernel_timing": timing_pass},
         "icp_iters_per_s": round(K / (ms * 1e-3), 2),
+        "step_ms_median": round(float(np.median(step_ms)), 4),
+        "step_ms_p90": round(float(np.percentile(step_ms, 90)), 4),
+        "build_ms": round(build_ms, 4),
+        "register_ms_median": round(float(np.median(reg_ms)), 4),
+        "register_ms_p90": round(float(np.percentile(reg_ms, 90)), 4),
+        "icp_iters_per_s_registration": round(K / (float(np.median(reg_ms)) * 1e-3), 2),
+        "search_queries_per_s": search_qps,
+        "global_searches_per_iter": [int(x) for x in F],
+        "count_global_atomics": {"with_lds_hash": atomics, "one_per_point": P.n},
         "roofline": roofline,
+        "roofline_dilation": dilation_roof,
         "kernels": kernels,
         "dilation_buffer": dil_bytes,
     }
