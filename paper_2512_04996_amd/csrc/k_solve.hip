@@ -277,7 +277,7 @@ constexpr int kWave = 64;
 constexpr int kSolveThreads = 256;
 constexpr int kSolveWaves = kSolveThreads / kWave;
 constexpr int kFbWindow = 32 * kSolveThreads;   // queries per pass over the global-search list
-constexpr int kFoldBatch = 32;                  // fold-unit loads in flight per thread
+constexpr int kFoldBatch = 64;                  // fold-unit loads in flight per thread
 
 // Adds the moments of one correspondence (p, q about the centre c, squared
 // distance d) to a[].
@@ -326,7 +326,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     PairState& S = st[pair];
     const PairDev& P = pd[pair];
     const int done = S.done;
-    const int32_t u0 = fold_begin[pair], u1 = fold_begin[pair + 1];
+    // a single pair owns every fold unit: its range needs no table load
+    const bool one = gridDim.x == 1;
+    const int32_t u0 = one ? 0 : fold_begin[pair], u1 = one ? nunits : fold_begin[pair + 1];
     const int32_t nfb = fb_count[pair];
     const double prev = S.prev_rmse;
     // the current rotation, the start of the polar refinement: read by every
