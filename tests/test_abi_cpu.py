@@ -68,3 +68,26 @@ def test_product_path_never_imports_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "vicp_oracle" not in src, f
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # the product path has no CPU fallback: without the HIP library every
+    # entry point raises
+    from paper_2512_04996_amd import _lib, api
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libvicp.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()
+    # and host tensors are refused, never computed on the CPU
+    import torch
+    with pytest.raises(TypeError):
+        api.build_grid(torch.zeros(3, 8), 0.1, 1)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
