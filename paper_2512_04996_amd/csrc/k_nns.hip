@@ -373,8 +373,12 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
         float sx, sy, sz;
         transform(st[job.pair].Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
         uint32_t v;
-        if (!voxel_of(P, sx, sy, sz, v)) v = (uint32_t)(P.V + (i >> kOutShift));
-        key = (uint32_t)(P.s_base + v);
+        int64_t b;
+        if (voxel_of(P, sx, sy, sz, v))
+            b = (int64_t)v * P.s_chunks + (P.s_shift < 62 ? (i >> P.s_shift) : 0);
+        else
+            b = P.V * P.s_chunks + (i >> kOutShift);
+        key = (uint32_t)(P.s_base + b);
         slot = (key * 2654435761u) >> 23;
         while (true) {
             const uint32_t prev = atomicCAS(&key_[slot], kNone, key);

@@ -515,19 +515,23 @@ void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
         if ((int)g->m.size() == g->B) {
             d.p_base = pb;
             d.m = g->m[p];
+            const SrcChunks sc = src_chunks(h.V, g->m[p]);
             d.s_base = sb;
+            d.s_chunks = sc.chunks;
+            d.s_shift = sc.shift;
             pb += g->m[p];
-            sb += h.V + (g->m[p] + kOutChunk - 1) / kOutChunk;
+            sb += h.V * sc.chunks + (g->m[p] + kOutChunk - 1) / kOutChunk;
         }
     }
 }
 
-// Source buckets of a layout: per pair, V voxel buckets and the "outside"
-// chunks.
+// Source buckets of a layout: per pair, V voxel buckets (times the index
+// chunks of a coarse grid) and the "outside" chunks.
 int64_t source_buckets(const vicp_grid* g, const std::vector<int64_t>& m)
 {
     int64_t nb = 0;
-    for (int p = 0; p < g->B; ++p) nb += g->pairs[p].V + (m[p] + kOutChunk - 1) / kOutChunk;
+    for (int p = 0; p < g->B; ++p)
+        nb += g->pairs[p].V * src_chunks(g->pairs[p].V, m[p]).chunks + (m[p] + kOutChunk - 1) / kOutChunk;
     return nb;
 }
 

@@ -26,14 +26,38 @@ constexpr uint32_t kMask = 0x80000000u;   // Mask(root) of Alg. 3
 constexpr uint32_t kNone = 0xFFFFFFFFu;   // no root (dilation state)
 constexpr int kMoments = 19;              // about the pair's centre c: sum p (3), sum q (3), sum p q^T (9),
                                           // sum |p|^2, sum |q|^2, sum d, count
-constexpr int kGradTerms = 8;
+constexpr int kGradTerms = 8;                  // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
 // Source bucketing: points outside the grid go to buckets of kOutChunk
 // consecutive indices, and a bucket larger than kRankCap turns the pair's
 // bucketing off (identity order), so that ranking a point within its bucket
-// costs at most kRankCap reads.
+// costs at most kRankCap reads.  On a coarse grid (fewer than
+// kChunkGridVoxels voxels, such as the 2^N grids of the paper's setting) a
+// voxel's points are further split by index into chunks of kRankCap
+// (s_shift = 10), as long as the buckets stay within kChunkBuckets, so that
+// dense voxels keep their queries together instead of turning bucketing off.
 constexpr int kOutShift = 6;
 constexpr int64_t kOutChunk = (int64_t)1 << kOutShift;
-constexpr uint32_t kRankCap = 1024;             // sum r (3), sum s x r (3), sum |r|^2 (1), count (1)
+constexpr uint32_t kRankCap = 1024;
+constexpr int kRankShift = 10;                   // log2(kRankCap)
+constexpr int64_t kChunkGridVoxels = 65536;
+constexpr int64_t kChunkBuckets = (int64_t)1 << 20;
+
+// Index chunking of a pair's voxel buckets: bucket of (voxel v, index i) is
+// v * chunks + (i >> shift).
+struct SrcChunks {
+    int shift;
+    int64_t chunks;
+};
+inline SrcChunks src_chunks(int64_t V, int64_t m)
+{
+    SrcChunks c{62, 1};
+    if (V <= 0 || V >= kChunkGridVoxels || m <= (int64_t)kRankCap) return c;
+    for (int s = kRankShift; s < 62; ++s) {
+        const int64_t ch = (m + ((int64_t)1 << s) - 1) >> s;
+        if (V * ch <= kChunkBuckets) return SrcChunks{s, ch};
+    }
+    return c;
+}
 
 // One pair: where its data lives and its grid (Sec. II.A Step 1).
 struct PairDev {
@@ -48,7 +72,10 @@ struct PairDev {
     float cx, cy, cz;       // centre of the grid: reference point of the moment sums
     int32_t Dx, Dy, Dz;     // dims
     int32_t pad;
-    int64_t s_base;   // first source bucket: V voxel buckets, then ceil(m / kOutChunk) "outside" buckets
+    int64_t s_base;   // first source bucket: V * s_chunks voxel buckets, then ceil(m / kOutChunk) "outside" buckets
+    int64_t s_chunks; // index chunks per voxel bucket (1 on fine grids)
+    int32_t s_shift;  // a source point's chunk is its index >> s_shift
+    int32_t s_pad;
 };
 
 // A block's work: the pair it serves and its first item within the pair.
