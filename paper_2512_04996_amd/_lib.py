@@ -83,8 +83,8 @@ SYMBOLS = {
     "vicp_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_int32,
                                 C.c_void_p]),
     "vicp_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                    C.POINTER(C.c_int32)]),
-    "vicp_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vicp_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "vicp_prof_enable": (C.c_int, [C.c_int32]),
     "vicp_prof_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "vicp_prof_reset": (C.c_int, []),

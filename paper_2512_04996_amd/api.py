@@ -119,16 +119,16 @@ class Grid:
 
     @property
     def schedule(self) -> dict:
-        a, l, b, c = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(l), C.byref(b), C.byref(c)),
+        a, l, b, c, r = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(l), C.byref(b), C.byref(c), C.byref(r)),
               "vicp_get_schedule")
         return {"nns_block": a.value, "lanes_per_query": l.value, "sort_source": bool(b.value),
-                "fallback_grid": c.value}
+                "fallback_grid": c.value, "reload_winner": bool(r.value)}
 
     def set_schedule(self, nns_block: int = 256, lanes_per_query: int = 4, sort_source: bool = True,
-                     fallback_grid: int = 128):
+                     fallback_grid: int = 128, reload_winner: bool = False):
         check(lib().vicp_set_schedule(self.handle, int(nns_block), int(lanes_per_query), int(bool(sort_source)),
-                                      int(fallback_grid)), "vicp_set_schedule")
+                                      int(fallback_grid), int(bool(reload_winner))), "vicp_set_schedule")
         return self
 
     # -- Alg. 3

@@ -86,6 +86,19 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
     bj = better ? __float_as_uint(q.w) : bj;
 }
 
+// The same, keeping the candidate's position in the segment instead of its
+// index (positions ascend with indices in a segment), so that a lane carries
+// two values per candidate instead of five; the winner's coordinates are
+// read once at the end.
+__device__ __forceinline__ void consider_pos(const float4& q, uint32_t pos, float sx, float sy, float sz, float& bd,
+                                             uint32_t& bk)
+{
+    const float d = dist2(sx, sy, sz, q.x, q.y, q.z);
+    const bool better = d < bd;
+    bd = better ? d : bd;
+    bk = better ? pos : bk;
+}
+
 // The same, also keeping the best candidate's coordinates.
 template <bool kTies>
 __device__ __forceinline__ void consider(const float4& q, float sx, float sy, float sz, float& bd, uint32_t& bj,
@@ -122,7 +135,12 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // voxel); a count above cap means an overflowed block and sends the query to
 // the global search.  Records are in the order the voxelisation's atomics
 // gave them, so ties compare indices.
-template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect>
+//
+// kReload (registration over segments, for many candidates per query): each
+// lane keeps the best distance and segment position only, and the winner's
+// record is read once after the lanes combine (one more dependent load per
+// query, three fewer selects per candidate).
+template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, bool kReload>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -135,6 +153,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
+    static_assert(!kReload || (kMom && !kDirect), "position tracking needs index-ordered segments");
     constexpr int kWaves = BS / kWave;
     const int jb = xcd_job((int)blockIdx.x, (int)gridDim.x);
     const BlockJob job = jobs[jb];
@@ -224,7 +243,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             for (int u = 0; u < U; ++u) a[u] = seg[min(k + (uint32_t)(u * LPQ), last)];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (kMom) consider<kDirect>(a[u], sx, sy, sz, bd, bj, bx, by, bz);
+                if (kReload) consider_pos(a[u], min(k + (uint32_t)(u * LPQ), last), sx, sy, sz, bd, bj);
+                else if (kMom) consider<kDirect>(a[u], sx, sy, sz, bd, bj, bx, by, bz);
                 else consider<kDirect>(a[u], sx, sy, sz, bd, bj);
             }
         }
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             const float od = xor_lanes(bd, d);
             const uint32_t oj = xor_lanes(bj, d);
             float ox = 0.0f, oy = 0.0f, oz = 0.0f;
-            if (kMom) {
+            if (kMom && !kReload) {
                 ox = xor_lanes(bx, d);
                 oy = xor_lanes(by, d);
                 oz = xor_lanes(bz, d);
@@ -243,12 +263,18 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             const bool take = od < bd || (od == bd && oj < bj);
             bd = take ? od : bd;
             bj = take ? oj : bj;
-            if (kMom) {
+            if (kMom && !kReload) {
                 bx = take ? ox : bx;
                 by = take ? oy : by;
                 bz = take ? oz : bz;
             }
         }
+    }
+    if (kReload && active && c > 0 && sub == 0) {
+        const float4 wv = qs4[cs + bj];
+        bx = wv.x;
+        by = wv.y;
+        bz = wv.z;
     }
     const bool found = active && c > 0 && sub == 0;
     if (!kMom && found) {
@@ -607,12 +633,36 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
                       const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
                       uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      int all_global, const uint32_t* dcnt, uint32_t cap, hipStream_t s)
+                      int all_global, const uint32_t* dcnt, uint32_t cap, bool reload, hipStream_t s)
 {
     if (njobs <= 0) return;
+    // the position-tracking form, for many candidates per query: 4 or 8
+    // lanes per query, registration over segments
+    if (reload && mom && !dcnt && (lpq == 4 || lpq == 8)) {
+#define VICP_NNS_R(BS, L, SORTED)                                                                                  \
+    launch_timed(k_nns_local<BS, L, SORTED, true, false, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,  \
+                 ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
+#define VICP_NNS_RL(BS, SORTED)                                     \
+    if (lpq == 4) VICP_NNS_R(BS, 4, SORTED); else VICP_NNS_R(BS, 8, SORTED);
+#define VICP_NNS_RB(SORTED)                                         \
+    switch (block) {                                                \
+    case 128: { VICP_NNS_RL(128, SORTED) } break;                   \
+    case 512: { VICP_NNS_RL(512, SORTED) } break;                   \
+    default: { VICP_NNS_RL(256, SORTED) } break;                    \
+    }
+        if (sorted) {
+            VICP_NNS_RB(true)
+        } else {
+            VICP_NNS_RB(false)
+        }
+#undef VICP_NNS_RB
+#undef VICP_NNS_RL
+#undef VICP_NNS_R
+        return;
+    }
 #define VICP_NNS(BS, L, SORTED, MOM, DIRECT)                                                                       \
-    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, ps4,  \
-                 st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
+    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, \
+                 ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
 #define VICP_NNS_L(BS, SORTED, MOM, DIRECT)                  \
     switch (lpq) {                                           \
     case 2: VICP_NNS(BS, 2, SORTED, MOM, DIRECT); break;     \

@@ -93,3 +93,20 @@ def test_target_outside_the_fixed_grid_is_an_error_and_rebuild_recovers():
     g.rebuild(dev(P.q)).dilate(P.rings)                                # a good target makes it usable again
     og = oracle.dilate(oracle.build_grid_fixed(P.q, o, P.voxel, d), P.rings)
     assert np.array_equal(g.export(0)[2], og.vm)
+
+
+def test_position_tracking_search_is_bit_identical():
+    # many candidates per query (about 50 on the 16^3 grid): keeping each
+    # lane's best segment position and reading the winner once gives the
+    # same registration bit for bit, bucketed or not
+    P = synth.config("paper_bunny_40k")
+    o, d = P.meta["grid_origin"], P.meta["grid_dims"]
+    g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    for sort_source in (True, False):
+        for lpq in (4, 8):
+            g.set_schedule(128, lpq, sort_source, 64, reload_winner=False)
+            a = g.register(p, 10)
+            g.set_schedule(128, lpq, sort_source, 64, reload_winner=True)
+            b = g.register(p, 10)
+            assert np.array_equal(a.Rt, b.Rt) and np.array_equal(a.rmse[0], b.rmse[0]), (sort_source, lpq)
