@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
                                                           const float* __restrict__ pz,
                                                           const PairState* __restrict__ st, uint32_t* __restrict__ sh,
                                                           uint32_t* __restrict__ skey, uint32_t* __restrict__ srank,
-                                                          int32_t* __restrict__ sbig)
+                                                          int32_t* __restrict__ sbig, int32_t* __restrict__ flags)
 {
     __shared__ uint32_t key_[kBSlots];
     __shared__ uint32_t cnt_[kBSlots];
@@ -396,8 +396,12 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
     uint32_t key = 0, slot = 0, lr = 0;
     if (valid) {
         const int64_t gp = P.p_base + i;
+        const float x = px[gp], y = py[gp], z = pz[gp];
+        // this pass reads every source point, so it also flags non-finite
+        // coordinates (bit 0 of the pair's fault flags)
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(&flags[job.pair], 1);
         float sx, sy, sz;
-        transform(st[job.pair].Rtf, px[gp], py[gp], pz[gp], sx, sy, sz);
+        transform(st[job.pair].Rtf, x, y, z, sx, sy, sz);
         uint32_t v;
         int64_t b;
         if (voxel_of(P, sx, sy, sz, v))
@@ -703,11 +707,11 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
-                       int32_t* sbig, hipStream_t s)
+                       int32_t* sbig, int32_t* flags, hipStream_t s)
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank,
-                       sbig);
+                       sbig, flags);
 }
 
 void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,

@@ -440,23 +440,42 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
 // Initial state: pose rounded to float32 for the search; pairs with no
 // source points are done from the start; the global-search counts and the
 // fault flags start at zero.
-__global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restrict__ st, const double* __restrict__ rt64,
-                            int npairs, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
+struct PoseBlob {
+    double rt[12 * kInlinePairs];
+};
+
+__device__ __forceinline__ void set_state_one(const PairDev* __restrict__ pd, PairState* __restrict__ st, int p,
+                                              const double* rt, int32_t* __restrict__ fb_count,
+                                              int32_t* __restrict__ flags)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
     fb_count[p] = 0;
     flags[p] = 0;
     PairState& S = st[p];
     S.done = pd[p].m > 0 ? 0 : 1;
     for (int j = 0; j < 12; ++j) {
-        S.Rt[j] = rt64[12 * p + j];
-        S.Rtf[j] = (float)rt64[12 * p + j];
+        S.Rt[j] = rt[j];
+        S.Rtf[j] = (float)rt[j];
     }
     S.prev_rmse = 0.0;
     S.iters = 0;
     S.degenerate = 0;
     S.status = 0;
+}
+
+// The poses travel in the launch's arguments (up to kInlinePairs pairs).
+__global__ void k_set_state_inline(const PairDev* __restrict__ pd, PairState* __restrict__ st, PoseBlob b,
+                                   int npairs, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
+{
+    const int p = threadIdx.x;
+    if (p < npairs) set_state_one(pd, st, p, b.rt + 12 * p, fb_count, flags);
+}
+
+__global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restrict__ st, const double* __restrict__ rt64,
+                            int npairs, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    set_state_one(pd, st, p, rt64 + 12 * p, fb_count, flags);
 }
 
 }  // namespace
@@ -472,6 +491,15 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
     launch_timed(k_solve, dim3(npairs), dim3(kSolveThreads), s, pd, fold_begin, nunits, fpart, fctr, st, fb_count,
                  fb_list, fb_key, px, py, pz, qx, qy, qz, flags, rmse_hist, fb_hist, deg_hist, ctr_hist, k, K,
                  early_stop, eps);
+}
+
+void launch_set_state_inline(const PairDev* pd, PairState* st, const double* host_rt, int npairs,
+                             int32_t* fb_count, int32_t* flags, hipStream_t s)
+{
+    if (npairs <= 0 || npairs > kInlinePairs) return;
+    PoseBlob b{};
+    for (int i = 0; i < 12 * npairs; ++i) b.rt[i] = host_rt[i];
+    hipLaunchKernelGGL(k_set_state_inline, dim3(1), dim3(64), 0, s, pd, st, b, npairs, fb_count, flags);
 }
 
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, int32_t* fb_count,

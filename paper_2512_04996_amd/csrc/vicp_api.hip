@@ -679,11 +679,28 @@ void queue_plan(vicp_grid* g, const float* px, const float* py, const float* pz,
     const int64_t nb = source_buckets(g, g->m);
     launch_clear4(g->sh, nb, g->s_status, scan_tiles(nb), g->s_ticket, 4, (uint32_t*)g->sbig, g->B, s);
     launch_src_bucket(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->st, g->sh, g->skey, g->srank,
-                      g->sbig, s);
+                      g->sbig, g->flags, s);
     launch_scan(g->sh, nb, g->soff, nullptr, nullptr, g->s_status, g->s_ticket, s);
     launch_src_place(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->skey, g->srank, g->soff, g->sidx, s);
     launch_src_rank(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->skey, g->soff, g->sidx, g->sbig,
                     g->ps4, s);
+}
+
+// Per-pair state at the given host poses (12 per pair), with the
+// global-search counts and fault flags zeroed, and the source's finiteness
+// check.  Up to kInlinePairs poses travel in the launch itself; the check
+// rides on the bucketing pass when the search buckets the source (that pass
+// then follows).
+void queue_start(vicp_grid* g, const double* rt_host, const float* px, const float* py, const float* pz,
+                 hipStream_t s)
+{
+    if (g->B <= kInlinePairs) {
+        launch_set_state_inline(g->d_pd, g->st, rt_host, g->B, g->fb_count, g->flags, s);
+    } else {
+        upload(rt_host, sizeof(double) * 12 * g->B, g->staging, s);
+        launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, g->fb_count, g->flags, s);
+    }
+    if (!g->sort_src) launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
 }
 
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
@@ -1203,9 +1220,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     const bool cap = capturing(s);
     std::vector<double> rt64(12 * g->B);
     for (int i = 0; i < 12 * g->B; ++i) rt64[i] = (double)Rt[i];
-    upload(rt64.data(), sizeof(double) * 12 * g->B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, g->fb_count, g->flags, s);
-    launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
+    queue_start(g, rt64.data(), px, py, pz, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, false);
     {
@@ -1259,9 +1274,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     const bool direct = o->layout != 0;
     if (direct && all_global) return fail(VICP_ERR_INVALID_ARG, "global_only and the direct layout exclude each other");
     if (direct && !g->direct_ready) return fail(VICP_ERR_STATE, "no direct layout: call vicp_direct_build first");
-    upload(Rt_io, sizeof(double) * 12 * B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, B, g->fb_count, g->flags, s);
-    launch_check_finite(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], px, py, pz, g->flags, s);
+    queue_start(g, Rt_io, px, py, pz, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
@@ -1510,8 +1523,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     if (!px || !py || !pz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     std::vector<double> rt(12 * g->B, 0.0);
     for (int p = 0; p < g->B; ++p) rt[12 * p] = rt[12 * p + 4] = rt[12 * p + 8] = 1.0;
-    upload(rt.data(), sizeof(double) * 12 * g->B, g->staging, s);
-    launch_set_state(g->d_pd, g->st, (const double*)g->staging, g->B, g->fb_count, g->flags, s);
+    queue_start(g, rt.data(), px, py, pz, s);
     hipEvent_t a, b;
     VICP_HIP(hipEventCreate(&a));
     VICP_HIP(hipEventCreate(&b));

@@ -273,7 +273,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const uint32_t* dcnt, uint32_t cap, bool reload, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
-                       int32_t* sbig, hipStream_t s);
+                       int32_t* sbig, int32_t* flags, hipStream_t s);
 void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,
                       const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s);
 void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
@@ -293,6 +293,11 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                   const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
                   double eps, hipStream_t s);
+// the same with the poses of up to kInlinePairs pairs passed in the launch
+// itself (host array), so no upload precedes it
+constexpr int kInlinePairs = 8;
+void launch_set_state_inline(const PairDev* pd, PairState* st, const double* host_rt, int npairs,
+                             int32_t* fb_count, int32_t* flags, hipStream_t s);
 void launch_set_state(const PairDev* pd, PairState* st, const double* rt64, int npairs, int32_t* fb_count,
                       int32_t* flags, hipStream_t s);
 void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
