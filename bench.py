@@ -157,7 +157,7 @@ def main():
         timing_pass = (f"eager pass of {prof_steps} steps after the timed region: search, global search and solve "
                        "timed by start/stop HIP events recorded at the kernel (hipExtLaunchKernelGGL), other "
                        "kernels by HIP events around the launch")
-        for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate_ring", "src_plan", "nns_local",
+        for name in ("aabb", "count", "scan", "place", "rank_sort", "dilate", "dilate_ring", "src_plan", "nns_local",
                      "fallback", "solve"):
             n_launch, tot = api.prof_read(name)
             if n_launch:
@@ -210,10 +210,18 @@ def main():
     vox = ijk[0] + dims[0] * (ijk[1] + dims[1] * ijk[2])
     blk = np.arange(P.n) // 256
     atomics = int(np.unique(blk * desc["V"] + vox).size)
-    # the dilation ring's compulsory bytes: 8 per voxel (own state in, state
-    # or result out) and 4 per newly dilated voxel
+    # the dilation's compulsory bytes: all rings in one launch read each
+    # voxel's count once (4) and, per dilated voxel, read its offset (4) and
+    # write its count word (4) and directory entry (8); a ring-per-launch
+    # run also moves 8 per voxel per ring for the ring state
     dilation_roof = None
-    if "dilate_ring" in kernels:
+    if "dilate" in kernels:
+        dbytes = 4 * desc["V"] + 16 * desc["dilated"]
+        ach = dbytes / (kernels["dilate"]["avg_us"] * 1e-6) / 1e9
+        dilation_roof = {"kernel": f"k_dilate_fused<{P.rings}>", "bound": "hbm", "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "compulsory_bytes_per_launch": int(dbytes)}
+    elif "dilate_ring" in kernels:
         ring_bytes = 8 * desc["V"] + 4 * desc["dilated"] / max(P.rings, 1)
         ach = ring_bytes / (kernels["dilate_ring"]["avg_us"] * 1e-6) / 1e9
         dilation_roof = {"kernel": "k_dilate_ring<256>", "bound": "hbm", "achieved": round(ach, 1),

@@ -366,6 +366,8 @@ struct vicp_grid {
     uint2* dir = nullptr;   // per voxel: (start in qs4, count | mask), root's entry for a dilated voxel
     BlockJob* jobs_v = nullptr;
     int njobs_v = 0;
+    BlockJob* jobs_t = nullptr;   // voxel tiles of the one-launch dilation
+    int njobs_t = 0;
     unsigned long long* scan_status = nullptr;
     uint32_t* scan_ticket = nullptr;
     uint32_t *dil_a = nullptr, *dil_b = nullptr;
@@ -862,8 +864,11 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         g->vm_words = words;
         std::vector<int64_t> vcount(B);
         for (int p = 0; p < B; ++p) vcount[p] = pairs[p].V;
-        std::vector<BlockJob> jv;
+        std::vector<BlockJob> jv, jt;
         make_jobs(vcount, 256, jv, nullptr);
+        std::vector<int64_t> tcount(B);
+        for (int p = 0; p < B; ++p) tcount[p] = dilate_tiles(pairs[p].dims[0], pairs[p].dims[1], pairs[p].dims[2]);
+        make_jobs(tcount, 1, jt, nullptr);
         const int tiles = scan_tiles(Vt);
         bool ok = true;
         g->hist = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
@@ -871,6 +876,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         g->vm = (uint32_t*)g->take(sizeof(uint32_t) * words, s, g->vbufs, ok);
         g->dir = (uint2*)g->take(sizeof(uint2) * Vt, s, g->vbufs, ok);
         g->jobs_v = (BlockJob*)g->take(sizeof(BlockJob) * jv.size(), s, g->vbufs, ok);
+        g->jobs_t = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jt.size(), 1), s, g->vbufs, ok);
         g->scan_status = (unsigned long long*)g->take(sizeof(unsigned long long) * tiles, s, g->vbufs, ok);
         g->scan_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->vbufs, ok);
         g->dil_a = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
@@ -882,6 +888,9 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         }
         g->njobs_v = (int)jv.size();
         VICP_HIP(hipMemcpyAsync(g->jobs_v, jv.data(), sizeof(BlockJob) * jv.size(), hipMemcpyHostToDevice, s));
+        g->njobs_t = (int)jt.size();
+        if (!jt.empty())
+            VICP_HIP(hipMemcpyAsync(g->jobs_t, jt.data(), sizeof(BlockJob) * jt.size(), hipMemcpyHostToDevice, s));
     }
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
@@ -1187,11 +1196,17 @@ int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
     uint32_t* a = g->dil_a;
     uint32_t* b = g->dil_b;
     const bool cap = capturing(s);
-    for (int r = 1; r <= rings; ++r) {
-        ProfScope ps("dilate_ring", s, cap);
-        launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, 256, g->hist, g->off, g->vm, g->dir, r == 1 ? nullptr : a,
-                           r == rings ? nullptr : b, r == 1, r == rings, s);
-        std::swap(a, b);
+    if (rings >= 1 && rings <= kFusedRings) {
+        // every ring in one launch, on LDS tiles with an L-voxel halo
+        ProfScope ps("dilate", s, cap);
+        launch_dilate_fused(g->d_pd, g->jobs_t, g->njobs_t, rings, g->hist, g->off, g->vm, g->dir, s);
+    } else {
+        for (int r = 1; r <= rings; ++r) {
+            ProfScope ps("dilate_ring", s, cap);
+            launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, 256, g->hist, g->off, g->vm, g->dir,
+                               r == 1 ? nullptr : a, r == rings ? nullptr : b, r == 1, r == rings, s);
+            std::swap(a, b);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("dilate: ") + hipGetErrorString(e));

@@ -259,6 +259,12 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
                         const uint32_t* hist, const uint32_t* off, uint32_t* vm, uint2* dir,
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
+// all rings in one launch for rings <= kFusedRings, over a table of voxel
+// tiles (dilate_tiles per pair); returns false (nothing launched) otherwise
+constexpr int kFusedRings = 4;
+int64_t dilate_tiles(int Dx, int Dy, int Dz);
+bool launch_dilate_fused(const PairDev* pd, const BlockJob* jobs, int njobs, int rings, const uint32_t* hist,
+                         const uint32_t* off, uint32_t* vm, uint2* dir, hipStream_t s);
 // VANICP's layout (single pair): copies each dilated voxel's root records
 // into its block, from the ring state (own id, root id or none per voxel)
 void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint32_t* cnt, float4* blk,
