@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--graph", type=int, default=1, help="replay the ICP iterations from a hipGraph")
     ap.add_argument("--schedule", default="auto",
                     help="search schedule: 'auto' (tuned on this workload first) or "
-                         "'BLOCK,LANES,SORT,FALLBACK_GRID[,RELOAD]', e.g. 128,2,0,64")
+                         "'BLOCK,LANES,SORT,FALLBACK_GRID[,SEARCH_MODE]', e.g. 128,2,0,64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
@@ -95,11 +95,11 @@ def main():
     else:
         vals = [int(x) for x in a.schedule.split(",")]
         bs, lpq, srt, fg = vals[:4]
-        g.set_schedule(bs, lpq, bool(srt), fg, bool(vals[4]) if len(vals) > 4 else False)
+        g.set_schedule(bs, lpq, bool(srt), fg, vals[4] if len(vals) > 4 else 0)
     schedule = g.schedule
     tf = lambda b: "true" if b else "false"
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
-                   f"{tf(schedule['sort_source'])}, true, false, {tf(schedule['reload_winner'])}>")
+                   f"{tf(schedule['sort_source'])}, true, false, {schedule['search_mode']}>")
     nns_blocks = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block'])
 
     def step():

@@ -288,15 +288,17 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
 /* The current search schedule of a grid: threads per block of the local
  * search (128, 256 or 512), lanes cooperating on one query (1, 2, 4 or 8),
  * whether the source is bucketed by target voxel before searching (0/1), the
- * number of blocks of the global search, and whether a registration's search
- * keeps each lane's best segment position and reads the winner's record once
- * (0/1; 4 or 8 lanes per query only: fewer instructions per candidate, one
- * more dependent load per query).  Setting it never changes a result.
- * INVALID_ARG for an unsupported value. */
+ * number of blocks of the global search, and the candidate loop of a
+ * registration's search (search_mode): 0 each lane keeps its best
+ * candidate's index and coordinates; 1 (4 or 8 lanes per query) each lane
+ * keeps its best segment position and the winner's record is read once,
+ * fewer instructions per candidate and one more dependent load per query.
+ * Setting it never changes a result.  INVALID_ARG for an unsupported value
+ * or combination. */
 int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per_query,
-                      int32_t* sort_source, int32_t* fallback_grid, int32_t* reload_winner);
+                      int32_t* sort_source, int32_t* fallback_grid, int32_t* search_mode);
 int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, int32_t sort_source,
-                      int32_t fallback_grid, int32_t reload_winner);
+                      int32_t fallback_grid, int32_t search_mode);
 
 /* Per-kernel timing with HIP events on the launch stream (0 = off).  While on,
  * every launch of a named kernel is bracketed by events; vicp_prof_read gives

@@ -123,12 +123,12 @@ class Grid:
         check(lib().vicp_get_schedule(self.handle, C.byref(a), C.byref(l), C.byref(b), C.byref(c), C.byref(r)),
               "vicp_get_schedule")
         return {"nns_block": a.value, "lanes_per_query": l.value, "sort_source": bool(b.value),
-                "fallback_grid": c.value, "reload_winner": bool(r.value)}
+                "fallback_grid": c.value, "search_mode": r.value}
 
     def set_schedule(self, nns_block: int = 256, lanes_per_query: int = 4, sort_source: bool = True,
-                     fallback_grid: int = 128, reload_winner: bool = False):
+                     fallback_grid: int = 128, search_mode: int = 0):
         check(lib().vicp_set_schedule(self.handle, int(nns_block), int(lanes_per_query), int(bool(sort_source)),
-                                      int(fallback_grid), int(bool(reload_winner))), "vicp_set_schedule")
+                                      int(fallback_grid), int(search_mode)), "vicp_set_schedule")
         return self
 
     # -- Alg. 3

@@ -136,11 +136,11 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // the global search.  Records are in the order the voxelisation's atomics
 // gave them, so ties compare indices.
 //
-// kReload (registration over segments, for many candidates per query): each
+// kMode 1 (registration over segments, for many candidates per query): each
 // lane keeps the best distance and segment position only, and the winner's
 // record is read once after the lanes combine (one more dependent load per
 // query, three fewer selects per candidate).
-template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, bool kReload>
+template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, int kMode>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -153,6 +153,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
+    constexpr bool kReload = kMode == 1;
+    static_assert(kMode == 0 || kMode == 1, "search mode");
     static_assert(!kReload || (kMom && !kDirect), "position tracking needs index-ordered segments");
     constexpr int kWaves = BS / kWave;
     const int jb = xcd_job((int)blockIdx.x, (int)gridDim.x);
@@ -637,14 +639,14 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
                       const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
                       uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      int all_global, const uint32_t* dcnt, uint32_t cap, bool reload, hipStream_t s)
+                      int all_global, const uint32_t* dcnt, uint32_t cap, int mode, hipStream_t s)
 {
     if (njobs <= 0) return;
     // the position-tracking form, for many candidates per query: 4 or 8
     // lanes per query, registration over segments
-    if (reload && mom && !dcnt && (lpq == 4 || lpq == 8)) {
+    if (mode == 1 && mom && !dcnt && (lpq == 4 || lpq == 8)) {
 #define VICP_NNS_R(BS, L, SORTED)                                                                                  \
-    launch_timed(k_nns_local<BS, L, SORTED, true, false, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,  \
+    launch_timed(k_nns_local<BS, L, SORTED, true, false, 1>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,     \
                  ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
 #define VICP_NNS_RL(BS, SORTED)                                     \
     if (lpq == 4) VICP_NNS_R(BS, 4, SORTED); else VICP_NNS_R(BS, 8, SORTED);
@@ -665,7 +667,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
         return;
     }
 #define VICP_NNS(BS, L, SORTED, MOM, DIRECT)                                                                       \
-    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz, \
+    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,     \
                  ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
 #define VICP_NNS_L(BS, SORTED, MOM, DIRECT)                  \
     switch (lpq) {                                           \

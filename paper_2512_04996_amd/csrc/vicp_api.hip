@@ -377,7 +377,7 @@ struct vicp_grid {
     int nns_lpq = 4;
     int fb_grid = 128;
     bool sort_src = true;
-    bool reload = false;   // position-tracking search (4 or 8 lanes per query only)
+    int search_mode = 0;   // 0 gather, 1 position tracking (4 or 8 lanes per query)
 
     // source workspace
     std::vector<int64_t> m;   // source layout currently in d_pd / tables
@@ -718,7 +718,7 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
                          pz, g->ps4, g->st, g->dir, direct ? g->dblk : g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list,
                          g->fb_key, g->ctr, g->npart, all_global ? 1 : 0, direct ? g->dcnt : nullptr, g->dcap,
-                         g->reload, s);
+                         g->search_mode, s);
     }
     {
         ProfScope ps("fallback", s, cap, true);
@@ -1293,7 +1293,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
-                                      (uintptr_t)g->reload,
+                                      (uintptr_t)g->search_mode,
                                       (uintptr_t)g->sort_src, (uintptr_t)all_global, (uintptr_t)direct,
                                       (uintptr_t)g->dblk,
                                       (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
@@ -1586,13 +1586,16 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     g->nns_block = best_bs;
     g->nns_lpq = best_lpq;
     g->sort_src = best_sorted;
-    g->reload = false;
+    g->search_mode = 0;
     if (best_lpq >= 4) {
         // many candidates per query: try the position-tracking search
-        g->reload = true;
+        g->search_mode = 1;
         const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
                         (best_sorted ? plan_ms / (float)searches_per_plan : 0.0f);
-        g->reload = t < kMargin * best;
+        if (t < kMargin * best)
+            best = t;
+        else
+            g->search_mode = 0;
     }
     best = 1e30f;
     for (int fg : {64, 128, 256, 512, 1024}) {
@@ -1614,19 +1617,19 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
 }
 
 int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per_query, int32_t* sort_source,
-                      int32_t* fallback_grid, int32_t* reload_winner)
+                      int32_t* fallback_grid, int32_t* search_mode)
 {
     if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
     if (nns_block) *nns_block = g->nns_block;
     if (lanes_per_query) *lanes_per_query = g->nns_lpq;
     if (sort_source) *sort_source = g->sort_src ? 1 : 0;
     if (fallback_grid) *fallback_grid = g->fb_grid;
-    if (reload_winner) *reload_winner = g->reload ? 1 : 0;
+    if (search_mode) *search_mode = g->search_mode;
     return VICP_OK;
 }
 
 int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, int32_t sort_source,
-                      int32_t fallback_grid, int32_t reload_winner)
+                      int32_t fallback_grid, int32_t search_mode)
 {
     if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
     if (nns_block != 128 && nns_block != 256 && nns_block != 512)
@@ -1634,9 +1637,10 @@ int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, 
     if (lanes_per_query != 1 && lanes_per_query != 2 && lanes_per_query != 4 && lanes_per_query != 8)
         return fail(VICP_ERR_INVALID_ARG, "lanes_per_query must be 1, 2, 4 or 8");
     if (fallback_grid < 1 || fallback_grid > 65536) return fail(VICP_ERR_INVALID_ARG, "fallback_grid out of range");
-    if (reload_winner && lanes_per_query < 4)
-        return fail(VICP_ERR_INVALID_ARG, "reload_winner needs 4 or 8 lanes per query");
-    g->reload = reload_winner != 0;
+    if (search_mode < 0 || search_mode > 1) return fail(VICP_ERR_INVALID_ARG, "search_mode must be 0 or 1");
+    if (search_mode == 1 && lanes_per_query < 4)
+        return fail(VICP_ERR_INVALID_ARG, "search_mode 1 needs 4 or 8 lanes per query");
+    g->search_mode = search_mode;
     g->nns_block = nns_block;
     g->nns_lpq = lanes_per_query;
     g->sort_src = sort_source != 0;

@@ -276,7 +276,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const PairState* st, const uint2* dir, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
                       unsigned long long* fb_key, unsigned long long* ctr, double* part, int all_global,
-                      const uint32_t* dcnt, uint32_t cap, bool reload, hipStream_t s);
+                      const uint32_t* dcnt, uint32_t cap, int mode, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
                        int32_t* sbig, int32_t* flags, hipStream_t s);

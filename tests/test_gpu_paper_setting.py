@@ -95,7 +95,7 @@ def test_target_outside_the_fixed_grid_is_an_error_and_rebuild_recovers():
     assert np.array_equal(g.export(0)[2], og.vm)
 
 
-def test_position_tracking_search_is_bit_identical():
+def test_search_modes_are_bit_identical():
     # many candidates per query (about 50 on the 16^3 grid): keeping each
     # lane's best segment position and reading the winner once gives the
     # same registration bit for bit, bucketed or not
@@ -105,8 +105,8 @@ def test_position_tracking_search_is_bit_identical():
     p = dev(P.p)
     for sort_source in (True, False):
         for lpq in (4, 8):
-            g.set_schedule(128, lpq, sort_source, 64, reload_winner=False)
+            g.set_schedule(128, lpq, sort_source, 64, search_mode=0)
             a = g.register(p, 10)
-            g.set_schedule(128, lpq, sort_source, 64, reload_winner=True)
+            g.set_schedule(128, lpq, sort_source, 64, search_mode=1)
             b = g.register(p, 10)
             assert np.array_equal(a.Rt, b.Rt) and np.array_equal(a.rmse[0], b.rmse[0]), (sort_source, lpq)
