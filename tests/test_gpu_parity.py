@@ -78,9 +78,10 @@ def test_build_and_dilate_bit_exact(case):
     assert d["dynamic_bytes"] == 4 * (og.n + 2 * og.V) and d["static_bytes"] == 8 * og.V
 
 
-@pytest.mark.parametrize("rings", [0, 1, 3])
+@pytest.mark.parametrize("rings", [0, 1, 2, 3, 4, 5])
 def test_partial_dilation(rings):
-    q, p, voxel, L = tiny(4, 400, 10, 0.15, 3)
+    # 1-4 rings run in one launch on LDS tiles, 5 ring by ring
+    q, p, voxel, L = tiny(4, 400, 10, 0.15, 5)
     g = build_grid(dev(q), voxel, L).dilate(rings)
     og = oracle.dilate(oracle.build_grid(q, voxel, L), rings)
     check_grid(g, og)
