@@ -16,8 +16,6 @@ namespace vicp {
 
 namespace {
 
-constexpr int kThreads = 256;
-
 __host__ __device__ void svd3(double A[3][3], double U[3][3], double sig[3], double V[3][3])
 {
     for (int i = 0; i < 3; ++i)
