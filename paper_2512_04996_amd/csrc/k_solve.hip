@@ -97,6 +97,9 @@ __host__ __device__ double det3(const double M[3][3])
 // singular or the iteration does not settle; the caller then uses the SVD.
 __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
 {
+    // float64 only and compared within tolerance: fused multiply-adds allowed
+    // (the float32 search keeps every rounding as written)
+#pragma clang fp contract(fast)
     double X[3][3];
     double na = 0.0;
     for (int i = 0; i < 3; ++i)
@@ -156,6 +159,9 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
 // and Q0 was orthogonal; otherwise returns false.
 __host__ __device__ bool polar_refine(const double A[3][3], double fro, const double Q0[3][3], double Q[3][3])
 {
+    // float64 only and compared within tolerance: fused multiply-adds allowed
+    // (the float32 search keeps every rounding as written)
+#pragma clang fp contract(fast)
     double R[3][3], An[3][3];
     double orth = 0.0;
     const double ifro = 1.0 / fro;
@@ -221,6 +227,9 @@ __host__ __device__ bool polar_refine(const double A[3][3], double fro, const do
 // every correspondence on one target point) never yields a rotation.
 __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12], const double* Rprev)
 {
+    // float64 only and compared within tolerance: fused multiply-adds allowed
+    // (the float32 search keeps every rounding as written)
+#pragma clang fp contract(fast)
     const double m = mom[18];
     if (!(m > 0.0)) return false;
     double pb[3], qb[3], H[3][3];
