@@ -6,7 +6,9 @@
 // root gets Mask(root) in the count word of its segment, found through the
 // offsets.  The ring state lives in a compact V-word array (root or none).
 // The same pass points the voxel's search-directory entry at its root's
-// points (start and count, with the mask bit set in the count).
+// points (start and count, with the mask bit set in the count).  Up to
+// kFusedRings rings run in one launch on LDS tiles (k_dilate_fused), more
+// ring by ring (k_dilate_ring); both give the same result.
 #include "vicp_internal.hpp"
 
 namespace vicp {
