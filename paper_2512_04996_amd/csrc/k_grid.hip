@@ -277,7 +277,10 @@ __global__ void k_seg_headers(const uint32_t* __restrict__ hist, const uint32_t*
 // and its count, so that a search reaches its candidates with one load (the
 // last dilation ring points empty voxels at their root's entry).
 // --------------------------------------------------------------------------
-constexpr int kScanItems = 16;
+#ifndef VICP_SCAN_ITEMS
+#define VICP_SCAN_ITEMS 8
+#endif
+constexpr int kScanItems = VICP_SCAN_ITEMS;
 constexpr int kScanTile = kThreads * kScanItems;
 constexpr unsigned long long kFlagAgg = 1ull << 32;
 constexpr unsigned long long kFlagIncl = 2ull << 32;
