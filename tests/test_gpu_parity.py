@@ -20,8 +20,9 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():   # collected on CPU machines, skipped there
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2512_04996_amd._lib import ERR_DEGENERATE, ERR_INVALID_ARG, ERR_NONFINITE, ERR_STATE, VicpError  # noqa: E402
-from paper_2512_04996_amd.api import build_grid, build_grid_batched  # noqa: E402
+from paper_2512_04996_amd._lib import (ERR_DEGENERATE, ERR_GRID_TOO_LARGE, ERR_INVALID_ARG, ERR_NONFINITE,  # noqa: E402
+                                      ERR_STATE, VicpError)
+from paper_2512_04996_amd.api import build_grid, build_grid_batched, build_grid_fixed  # noqa: E402
 
 ROT_TOL = 1e-5
 T_TOL = 1e-6
@@ -85,6 +86,27 @@ def test_partial_dilation(rings):
     g = build_grid(dev(q), voxel, L).dilate(rings)
     og = oracle.dilate(oracle.build_grid(q, voxel, L), rings)
     check_grid(g, og)
+
+
+@pytest.mark.parametrize("dims", [(2047, 1, 1), (16, 16, 8), (2049, 1, 1), (4095, 1, 1), (4097, 3, 1),
+                                  (64, 32, 64), (33, 65, 61)])
+def test_offsets_across_scan_tiles(dims):
+    # a given grid fixes V exactly: one voxel short of, exactly at and one
+    # past multiples of 2048 and 4096 entries, and a ragged 130,845, so the
+    # single-pass scan's look-back and its last partial tile are exercised
+    rng = np.random.default_rng(int(np.prod(dims)))
+    voxel = 0.25
+    origin = np.array([-1.0, -2.0, 0.5], np.float32)
+    ext = np.array(dims, np.float64) * voxel * 0.999
+    q = (origin[:, None] + rng.random((3, 3000)) * ext[:, None]).astype(np.float32)
+    g = build_grid_fixed(dev(q), origin, voxel, dims, 2)
+    og = oracle.build_grid_fixed(q, origin, voxel, dims)
+    assert g.describe()["V"] == og.V == int(np.prod(dims))
+    hist, off, vm = g.export()
+    assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm)
+    g.dilate(2)
+    oracle.dilate(og, 2)
+    assert np.array_equal(g.export()[2], og.vm)
 
 
 def random_pose(seed, deg, t):
@@ -286,8 +308,12 @@ def test_errors_and_empty_inputs():
     with pytest.raises(VicpError) as e:
         build_grid(dev(bad), 0.1, 1)
     assert e.value.code == ERR_NONFINITE
-    with pytest.raises(VicpError):
+    with pytest.raises(VicpError) as e:
         build_grid(dev(q), 1e-6, 1)                       # too many voxels
+    assert e.value.code == ERR_GRID_TOO_LARGE
+    with pytest.raises(VicpError) as e:                   # V = 2^31 - 1 fits, n + 2V does not fit 32 bits
+        build_grid_fixed(dev(q), (-1000.0, -50.0, -50.0), 100.0, (2147483647, 1, 1), 0)
+    assert e.value.code == ERR_GRID_TOO_LARGE
     g = build_grid(dev(q), 0.2, 1)
     with pytest.raises(VicpError) as e:
         g.dilate(2)                                        # more rings than padding
