@@ -497,6 +497,11 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
 {
     __shared__ int32_t s_pref[kMaxPairs + 1];
     __shared__ float tx[kFbT], ty[kFbT], tz[kFbT];
+    // the first kFbThreads pairs' list lengths and target counts do not
+    // depend on the fold: loaded before it, used after it
+    const bool own0 = (int)threadIdx.x < npairs;
+    const int64_t F0 = own0 ? fb_count[threadIdx.x] : 0;
+    const int64_t n0 = own0 ? pd[threadIdx.x].n : 0;
     // registration: first fold the search blocks' moment partials, kFoldChunk
     // blocks per unit, each summed in block order (the launch runs anyway,
     // and the fold does not depend on the global search)
@@ -549,8 +554,10 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
     }
     // items per pair, loaded in parallel, then an in-LDS running sum
     for (int p = threadIdx.x; p < npairs; p += kFbThreads) {
-        const int64_t F = fb_count[p];
-        s_pref[p + 1] = F > 0 ? (int32_t)(((F + kFbQ - 1) / kFbQ) * ((pd[p].n + kFbT - 1) / kFbT)) : 0;
+        const bool first = p == (int)threadIdx.x;
+        const int64_t F = first ? F0 : fb_count[p];
+        const int64_t n = first ? n0 : pd[p].n;
+        s_pref[p + 1] = F > 0 ? (int32_t)(((F + kFbQ - 1) / kFbQ) * ((n + kFbT - 1) / kFbT)) : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
