@@ -506,8 +506,10 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
     // blocks per unit, each summed in block order (the launch runs anyway,
     // and the fold does not depend on the global search)
     if (fjobs) {
-        __shared__ double fv[kMoments][kFoldChunk];
-        __shared__ unsigned long long fc[2][kFoldChunk];
+        // rows padded by one element: the moment rows then start in different
+        // banks, so neither the transposing stores nor the row sums conflict
+        __shared__ double fv[kMoments][kFoldChunk + 1];
+        __shared__ unsigned long long fc[2][kFoldChunk + 1];
         for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
             // a finished pair's units are folded too (their sums go unused):
             // testing its flag first would delay every load behind it
