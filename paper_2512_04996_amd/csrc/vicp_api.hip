@@ -75,20 +75,28 @@ __global__ void k_export_off(const uint32_t* __restrict__ off, int64_t count, ui
 __global__ void k_grid_stats(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
                              const uint32_t* __restrict__ vm, int64_t V, unsigned long long* out)
 {
-    unsigned long long occ = 0, dil = 0;
-    uint32_t mx = 0;
+    unsigned long long occ = 0, dil = 0, mx = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t h = hist[v];
+        const uint32_t o = off[v];   // loaded with the count, not after it
         if (h) {
             occ += 1;
-            mx = max(mx, h);
-        } else if (vm[(int64_t)off[v] + 1] & kMask) {
+            mx = max(mx, (unsigned long long)h);
+        } else if (vm[(int64_t)o + 1] & kMask) {
             dil += 1;
         }
     }
-    if (occ) atomicAdd(&out[0], occ);
-    if (dil) atomicAdd(&out[1], dil);
-    if (mx) atomicMax(&out[2], (unsigned long long)mx);
+    // one set of atomics per wave
+    for (int d = 32; d > 0; d >>= 1) {
+        occ += __shfl_xor(occ, d, 64);
+        dil += __shfl_xor(dil, d, 64);
+        mx = max(mx, __shfl_xor(mx, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (occ) atomicAdd(&out[0], occ);
+        if (dil) atomicAdd(&out[1], dil);
+        if (mx) atomicMax(&out[2], mx);
+    }
 }
 
 // ----------------------------------------------------------- per-kernel timing
@@ -1468,7 +1476,7 @@ int vicp_grid_describe(const vicp_grid* g, int32_t pair, vicp_grid_desc* out)
     unsigned long long* cnt = nullptr;
     VICP_HIP(hipMalloc(&cnt, sizeof(unsigned long long) * 4));
     VICP_HIP(hipMemset(cnt, 0, sizeof(unsigned long long) * 4));
-    hipLaunchKernelGGL(k_grid_stats, dim3(std::max<int64_t>(1, std::min<int64_t>((h.V + 255) / 256, 2048))), dim3(256),
+    hipLaunchKernelGGL(k_grid_stats, dim3(std::max<int64_t>(1, std::min<int64_t>((h.V + 255) / 256, 1 << 20))), dim3(256),
                        0, nullptr, g->hist + h.v_base, g->off + h.v_base, g->vm, h.V, cnt);
     unsigned long long hc[4] = {0, 0, 0, 0};
     uint32_t herr = 0;
