@@ -276,12 +276,13 @@ int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t*
 /* Releases the grid and everything it owns (after its queued work). */
 int vicp_grid_free(vicp_grid* g);
 
-/* Autotuning: times the result-invariant schedules of the search (see
- * vicp_get_schedule) on this grid and source at the identity pose and keeps the
- * fastest in the grid.  The source-bucketing pass serves `searches_per_plan`
- * searches (1 for vicp_nns, the iteration count for vicp_register) and is
- * charged at that rate.  Results never depend on the schedule.  Synchronises
- * the stream. */
+/* Autotuning: times the schedules of the search (see vicp_get_schedule) on
+ * this grid and source at the identity pose and keeps the fastest in the
+ * grid.  The source-bucketing pass serves `searches_per_plan` searches (1 for
+ * vicp_nns, the iteration count for vicp_register) and is charged at that
+ * rate.  Correspondences and counts never depend on the schedule; a pose may
+ * differ in its last bits (see vicp_get_schedule).  Synchronises the
+ * stream. */
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz,
                   const int64_t* m_per_pair, int32_t searches_per_plan, hipStream_t stream);
 

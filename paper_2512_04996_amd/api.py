@@ -231,7 +231,8 @@ class Grid:
         return u(hist), u(off), u(vm)
 
     def autotune(self, p: torch.Tensor, m_per_pair=None, searches_per_plan: int = 1):
-        """Pick the fastest result-invariant search schedule for this source."""
+        """Pick the fastest search schedule for this source (correspondences and
+        counts never change; a pose may change in its last bits)."""
         p = _soa(p, "p")
         if m_per_pair is None:
             m_per_pair = [p.shape[1]]
