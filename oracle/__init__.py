@@ -35,7 +35,7 @@ class OracleError(RuntimeError):
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no contraction, so float32 rounds as written)."""
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True, cwd=HERE)
         os.replace(LIB + ".tmp", LIB)
@@ -54,6 +54,8 @@ def lib():
         f32p, f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
         u32p, i32p, i64p = C.POINTER(C.c_uint32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
         i64, i32 = C.c_int64, C.c_int32
+        L.vicpo_set_threads.argtypes = [i32]
+        L.vicpo_set_threads.restype = C.c_int
         L.vicpo_grid_spec.argtypes = [f32p, f32p, f32p, i64, C.c_float, i32, f32p, f32p, i32p, i64p]
         L.vicpo_voxel_ids.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64p]
         L.vicpo_build.argtypes = [f32p, f32p, f32p, i64, f32p, C.c_float, i32p, i64, u32p, u32p, u32p]
@@ -77,6 +79,12 @@ def lib():
                                 f32p, f32p, f32p, i64, f64p, f64p, f64p, f64p, f64p, f64p, i32p]
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> int:
+    """Threads of Alg. 4's per-query loop (default 1); returns the count in
+    force.  Results do not depend on it."""
+    return int(lib().vicpo_set_threads(int(k)))
 
 
 def _p(a: np.ndarray, ct):

@@ -9,8 +9,12 @@
  * CPU-baseline leg may load it.  It shares no code, header, table or helper
  * with the HIP library, and the HIP library never calls it.
  *
- * Every step is single-threaded, in the order the paper states it, with no
- * blocking or fusion.  Build with -ffp-contract=off so that every float32
+ * Every step runs in the order the paper states it, with no blocking or
+ * fusion, single-threaded by default.  The one exception is optional: the
+ * per-query loop of Alg. 4 may run on several threads (vicpo_set_threads,
+ * OpenMP), because each query's search reads only the grid and writes only
+ * its own result slot; the counters are integer sums, so every output is the
+ * same for any thread count.  Build with -ffp-contract=off so that every float32
  * expression rounds exactly as written: the voxel quantisation and the
  * float32 distances decide integers (voxel ids, nearest-neighbour indices),
  * so they are evaluated in float32, the precision the GPU kernels use.
@@ -46,8 +50,27 @@
 
 #include "vicp_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define MASK_BIT 0x80000000u
 #define NONE_ROOT 0xFFFFFFFFu
+
+static int g_threads = 1;
+
+/* Threads of the per-query loop of Alg. 4 (1 = single-threaded, the
+ * default); returns the count in force (always 1 without OpenMP). */
+int vicpo_set_threads(int32_t k)
+{
+#ifdef _OPENMP
+    g_threads = k < 1 ? 1 : k;
+#else
+    (void)k;
+    g_threads = 1;
+#endif
+    return g_threads;
+}
 
 /* ------------------------------------------------------------------------ */
 /* grid specification (Sec. II.A Step 1; Alg. 1 "Quantize")                  */
@@ -261,6 +284,9 @@ int vicpo_nns_cap(const float* qx, const float* qy, const float* qz, int64_t n,
                   int64_t* n_fallback, int64_t* cand_total, int64_t* dilated_total)
 {
     int64_t F = 0, C = 0, Dl = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : F, C, Dl) num_threads(g_threads) if (g_threads > 1)
+#endif
     for (int64_t i = 0; i < m; ++i) {
         float s[3];
         transform_f32(Rt, px[i], py[i], pz[i], s);

@@ -12,6 +12,7 @@
 #define VICPO_ERR_NONFINITE (-4)
 #define VICPO_ERR_INTERNAL (-5)
 
+int vicpo_set_threads(int32_t k);
 int vicpo_grid_spec(const float* qx, const float* qy, const float* qz, int64_t n,
                     float voxel, int32_t rings, float origin[3], float* inv,
                     int32_t dims[3], int64_t* V);

@@ -391,6 +391,67 @@ def test_icp_stop_rule():
     assert np.array_equal(early.rmse, full.rmse[:k])
 
 
+def _dilated_vm_np(hist, off, vm, roots):
+    """vm with Mask(root) written into the count word of every empty voxel
+    that has a root (Alg. 3), from the closed-form roots."""
+    vm = vm.copy()
+    for v in np.nonzero((hist == 0) & (roots != np.uint32(0xFFFFFFFF)))[0]:
+        vm[int(off[v]) + 1] = roots[v] | np.uint32(0x80000000)
+    return vm
+
+
+@pytest.mark.parametrize("seed,n,m,voxel,L", [(90, 300, 200, 0.25, 2), (91, 250, 180, 0.4, 1)])
+def test_icp_rmse_is_root_mean_of_the_iterations_squared_distances(seed, n, m, voxel, L):
+    # Sec. IV.A's stop rule compares RMSE values: RMSE_k = sqrt((1/m) sum_i d_i),
+    # d_i the squared distance of query i to its Alg. 4 correspondence at
+    # iteration k's float32 pose.  The d_i come from the independent rule
+    # (exact rational float32 rounding), the grid from bincount/argsort and
+    # the closed form of dilation, the sum is exact (fsum); iteration k's pose
+    # is the pose after k iterations.  The last iteration's correspondences,
+    # which a registration reports, are pinned the same way.
+    q = synth.tiny_cloud(seed, n, dup=n // 10)
+    p = synth.tiny_cloud(seed + 1, m, scale=1.2)
+    K = 4
+    ref = oracle.register(q, p, voxel, L, K)
+    origin, inv, dims, V = oracle.grid_spec(q, voxel, L)
+    hist, off, vm = segments_np(q, origin, inv, dims, V)
+    vm = _dilated_vm_np(hist, off, vm, closed_form_roots(hist, dims, L))
+    fallbacks = 0
+    for k in range(K):
+        pose = oracle.register(q, p, voxel, L, k).Rt if k else oracle.identity_rt()
+        idx, d2, fb = nns_rule(q, p, pose.astype(np.float32), origin, inv, dims, hist, off, vm)
+        want = math.sqrt(math.fsum(float(d) for d in d2.astype(np.float64)) / m)
+        assert ref.rmse[k] == pytest.approx(want, rel=1e-12, abs=0), k
+        assert ref.fallbacks[k] == fb, k
+        fallbacks += fb
+    assert fallbacks > 0                      # the source reaches outside the grid
+    assert np.array_equal(ref.nn_idx, idx) and np.array_equal(ref.nn_d2.view(np.uint32), d2.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", ["sphere_2k", "bumpy_40k"])
+def test_threaded_search_gives_identical_results(name):
+    # Alg. 4's per-query loop on several threads (the oracle's one parallel
+    # loop) returns the same registration, bit for bit, as one thread
+    P = synth.config(name)
+    K = 6
+    try:
+        assert oracle.set_threads(1) == 1
+        a = oracle.register(P.q, P.p, P.voxel, P.rings, K)
+        assert oracle.set_threads(8) in (1, 8)
+        b = oracle.register(P.q, P.p, P.voxel, P.rings, K)
+        og = oracle.dilate(oracle.build_grid(P.q, P.voxel, P.rings), P.rings)
+        Rt = np.asarray(a.Rt, np.float32)
+        n8 = oracle.nns_counts(og, P.q, P.p, Rt)
+        oracle.set_threads(1)
+        n1 = oracle.nns_counts(og, P.q, P.p, Rt)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(a.Rt, b.Rt) and np.array_equal(a.rmse, b.rmse)
+    assert np.array_equal(a.fallbacks, b.fallbacks)
+    assert np.array_equal(a.nn_idx, b.nn_idx) and np.array_equal(a.nn_d2, b.nn_d2)
+    assert n1 == n8
+
+
 def test_icp_empty_source_is_noop():
     q = synth.tiny_cloud(80, 10)
     r = oracle.register(q, np.zeros((3, 0), np.float32), 0.2, 1, 5)
