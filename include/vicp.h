@@ -230,6 +230,26 @@ int vicp_nns_batched(const vicp_grid* g, const float* px, const float* py, const
                      const int64_t* m_per_pair, const float* Rt, int32_t* nn_idx,
                      float* nn_d2, int32_t* n_fallback, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): vicp_nns
+ * with every intermediate (the pose, the work tables, the global-search list
+ * and its keys, the per-block counters) in one fixed device array that the
+ * library holds on each GPU it runs on until the process ends
+ * (14,713,600 bytes, sized for VICP_NOALLOC_MAX_QUERIES source points),
+ * instead of the grid's workspace.  Same arguments, outputs and results as vicp_nns (bit for bit:
+ * the same search kernels, over the source in index order); the grid must
+ * have been built beforehand (building allocates).  Allocates nothing: no
+ * hipMalloc, no hipFree, no allocating library routine.  Every call on one
+ * GPU shares that GPU's array and overwrites what the last call left there,
+ * so calls that overlap on one GPU (other streams or host threads) race:
+ * the caller serialises them.  Asynchronous.  Errors: as vicp_nns;
+ * m > VICP_NOALLOC_MAX_QUERIES -> INVALID_ARG; a HIP error while locating
+ * the array on first use on a device -> HIP. */
+#define VICP_NOALLOC_MAX_QUERIES (1 << 20)
+int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                     int64_t m, const float Rt[12], int32_t* nn_idx, float* nn_d2,
+                     int32_t* n_fallback, hipStream_t stream);
+
 /* ---- registration (Sec. II.A loop, Eq. 1) ---------------------------------
  * Runs the ICP loop on a single-pair grid: correspondences by Alg. 4 at the
  * float32-rounded pose, then the closed-form rigid transform of Eq. 1 on

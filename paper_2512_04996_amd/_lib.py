@@ -20,6 +20,7 @@ ERR_STATE = -5
 ERR_NONFINITE = -6
 ERR_DEGENERATE = -7
 MASK_BIT = 0x80000000
+NOALLOC_MAX_QUERIES = 1 << 20
 
 
 class VicpError(RuntimeError):
@@ -67,6 +68,8 @@ SYMBOLS = {
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_nns_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_float), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vicp_nns_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_float),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_register": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(IcpOpts),
                                 C.POINTER(C.c_double), C.POINTER(IcpStats), C.c_void_p]),
     "vicp_register_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),

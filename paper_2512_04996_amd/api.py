@@ -160,6 +160,25 @@ class Grid:
               "vicp_nns_batched")
         return idx[:m], d2[:m], fb
 
+    def nns_noalloc(self, p: torch.Tensor, Rt, nn_idx: torch.Tensor, nn_d2: torch.Tensor,
+                    n_fallback: torch.Tensor = None):
+        """The search of ``nns`` into caller-allocated outputs (int32[m],
+        float32[m], int32[1] or None) through the entry point that allocates
+        nothing: its intermediates live in the library's fixed per-GPU
+        array, so calls on one GPU must not overlap."""
+        p = _soa(p, "p")
+        m = p.shape[1]
+        rt = np.ascontiguousarray(np.asarray(Rt, np.float32).reshape(12))
+        for t, dt in ((nn_idx, torch.int32), (nn_d2, torch.float32)):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()
+                    and t.numel() >= m):
+                raise TypeError("outputs must be contiguous CUDA tensors of m int32 / float32 entries")
+        fb = C.c_void_p(n_fallback.data_ptr()) if n_fallback is not None else C.c_void_p(0)
+        px, py, pz = _ptrs(p)
+        check(lib().vicp_nns_noalloc(self.handle, px, py, pz, m, rt.ctypes.data_as(C.POINTER(C.c_float)),
+                                     C.c_void_p(nn_idx.data_ptr()), C.c_void_p(nn_d2.data_ptr()), fb, _stream()),
+              "vicp_nns_noalloc")
+
     # -- the ICP loop
     def register(self, p: torch.Tensor, max_iter: int, rmse_eps: float = 1e-5, early_stop: bool = False,
                  use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False,

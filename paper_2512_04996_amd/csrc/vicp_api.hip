@@ -498,6 +498,29 @@ bool capturing(hipStream_t s)
     return cs == hipStreamCaptureStatusActive;
 }
 
+// The target and grid fields of one pair's device record.
+void fill_grid_fields(const PairHost& h, int32_t pad, PairDev& d)
+{
+    d.q_base = h.q_base;
+    d.n = h.n;
+    d.v_base = h.v_base;
+    d.V = h.V;
+    d.ox = h.origin[0];
+    d.oy = h.origin[1];
+    d.oz = h.origin[2];
+    d.inv = h.inv;
+    d.Dx = h.dims[0];
+    d.Dy = h.dims[1];
+    d.Dz = h.dims[2];
+    d.fDx = (float)h.dims[0];
+    d.fDy = (float)h.dims[1];
+    d.fDz = (float)h.dims[2];
+    d.cx = h.origin[0] + 0.5f * (float)h.dims[0] * h.voxel;
+    d.cy = h.origin[1] + 0.5f * (float)h.dims[1] * h.voxel;
+    d.cz = h.origin[2] + 0.5f * (float)h.dims[2] * h.voxel;
+    d.pad = pad;
+}
+
 void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
 {
     pd.assign(g->B, PairDev{});
@@ -505,24 +528,7 @@ void fill_pairdev(const vicp_grid* g, std::vector<PairDev>& pd)
     for (int p = 0; p < g->B; ++p) {
         const PairHost& h = g->pairs[p];
         PairDev& d = pd[p];
-        d.q_base = h.q_base;
-        d.n = h.n;
-        d.v_base = h.v_base;
-        d.V = h.V;
-        d.ox = h.origin[0];
-        d.oy = h.origin[1];
-        d.oz = h.origin[2];
-        d.inv = h.inv;
-        d.Dx = h.dims[0];
-        d.Dy = h.dims[1];
-        d.Dz = h.dims[2];
-        d.fDx = (float)h.dims[0];
-        d.fDy = (float)h.dims[1];
-        d.fDz = (float)h.dims[2];
-        d.cx = h.origin[0] + 0.5f * (float)h.dims[0] * h.voxel;
-        d.cy = h.origin[1] + 0.5f * (float)h.dims[1] * h.voxel;
-        d.cz = h.origin[2] + 0.5f * (float)h.dims[2] * h.voxel;
-        d.pad = g->pad;
+        fill_grid_fields(h, g->pad, d);
         if ((int)g->m.size() == g->B) {
             d.p_base = pb;
             d.m = g->m[p];
@@ -1263,6 +1269,154 @@ int vicp_nns(const vicp_grid* g, const float* px, const float* py, const float* 
     if (g->B != 1) return fail(VICP_ERR_INVALID_ARG, "vicp_nns needs a single-pair grid");
     if (m < 0) return fail(VICP_ERR_INVALID_ARG, "m < 0");
     return vicp_nns_batched(g, px, py, pz, &m, Rt, nn_idx, nn_d2, n_fallback, s);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- the allocation-free search
+//
+// vicp_nns_noalloc keeps every intermediate of one search in `scratch`, a
+// fixed device array of this translation unit.  In host code the array's
+// name only stands for the symbol: its device address on the current GPU is
+// found once per device with hipGetSymbolAddress and kept, and only that
+// address is ever handed to a kernel.
+namespace {
+
+constexpr int64_t kNaMaxQ = VICP_NOALLOC_MAX_QUERIES;
+constexpr int64_t kNaMinQpb = 16;                        // fewest queries per block of any schedule
+constexpr int64_t kNaMaxJobs = kNaMaxQ / kNaMinQpb;      // search blocks
+constexpr int64_t kNaMaxJobs256 = kNaMaxQ / 256;         // 256-point blocks of the result pass
+constexpr size_t kNaOffPd = 0;                           // PairDev
+constexpr size_t kNaOffSt = 256;                         // PairState
+constexpr size_t kNaOffCnt = 512;                        // global-search count, fault flags
+constexpr size_t kNaOffJobs = 768;
+constexpr size_t kNaOffJobs256 = kNaOffJobs + sizeof(BlockJob) * kNaMaxJobs;
+constexpr size_t kNaOffCtr = kNaOffJobs256 + sizeof(BlockJob) * kNaMaxJobs256;
+constexpr size_t kNaOffList = kNaOffCtr + sizeof(unsigned long long) * 3 * kNaMaxJobs;
+constexpr size_t kNaOffKey = kNaOffList + sizeof(uint32_t) * kNaMaxQ;
+constexpr size_t kNaBytes = kNaOffKey + sizeof(unsigned long long) * kNaMaxQ;
+static_assert(sizeof(PairDev) <= 256 && sizeof(PairState) <= 256, "scratch header slots");
+static_assert(kNaOffJobs256 % 256 == 0 && kNaOffCtr % 256 == 0 && kNaOffList % 256 == 0 && kNaOffKey % 256 == 0,
+              "scratch sections stay 256-byte aligned");
+static_assert(kNaBytes == 14713600, "the size the header states");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+std::mutex g_na_mu;
+std::map<int, unsigned char*> g_na_ptr;   // device ordinal -> address of `scratch` on that device
+
+// The address of `scratch` on the current device (located on first use).
+int noalloc_scratch(unsigned char** out)
+{
+    int devi = 0;
+    VICP_HIP(hipGetDevice(&devi));
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    auto it = g_na_ptr.find(devi);
+    if (it == g_na_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VICP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_na_ptr.emplace(devi, (unsigned char*)p).first;
+    }
+    *out = it->second;
+    return VICP_OK;
+}
+
+struct NaSetup {
+    PairDev pd;
+    float rt[12];
+};
+
+// One launch prepares the search: the pair record and pose, the global-search
+// count and fault flags at zero, and the two block tables (search blocks of
+// qpb queries, result blocks of 256 points).
+__global__ void k_noalloc_setup(NaSetup a, int32_t njobs, int32_t qpb, int32_t njobs256, unsigned char* base)
+{
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid == 0) {
+        *reinterpret_cast<PairDev*>(base + kNaOffPd) = a.pd;
+        PairState& S = *reinterpret_cast<PairState*>(base + kNaOffSt);
+        for (int j = 0; j < 12; ++j) {
+            S.Rt[j] = (double)a.rt[j];
+            S.Rtf[j] = a.rt[j];
+        }
+        S.prev_rmse = 0.0;
+        S.done = 0;
+        S.iters = 0;
+        S.degenerate = 0;
+        S.status = 0;
+        int32_t* cnt = reinterpret_cast<int32_t*>(base + kNaOffCnt);
+        cnt[0] = 0;   // global-search count
+        cnt[1] = 0;   // fault flags
+    }
+    BlockJob* jobs = reinterpret_cast<BlockJob*>(base + kNaOffJobs);
+    BlockJob* jobs256 = reinterpret_cast<BlockJob*>(base + kNaOffJobs256);
+    for (int64_t j = tid; j < njobs; j += (int64_t)gridDim.x * blockDim.x) jobs[j] = BlockJob{0, (int32_t)(j * qpb)};
+    for (int64_t j = tid; j < njobs256; j += (int64_t)gridDim.x * blockDim.x)
+        jobs256[j] = BlockJob{0, (int32_t)(j * 256)};
+}
+
+}  // namespace
+
+extern "C" {
+
+int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const float* pz, int64_t m,
+                     const float Rt[12], int32_t* nn_idx, float* nn_d2, int32_t* n_fallback, hipStream_t s)
+{
+    (void)hipGetLastError();   // an error left by other code is not ours to report
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (g->B != 1) return fail(VICP_ERR_INVALID_ARG, "vicp_nns_noalloc needs a single-pair grid");
+    if (m < 0) return fail(VICP_ERR_INVALID_ARG, "m < 0");
+    if (m > kNaMaxQ)
+        return fail(VICP_ERR_INVALID_ARG, "vicp_nns_noalloc takes at most " + std::to_string(kNaMaxQ) +
+                                              " source points (its fixed scratch array); use vicp_nns");
+    unsigned char* base = nullptr;
+    rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    int32_t* cnt = reinterpret_cast<int32_t*>(base + kNaOffCnt);
+    if (m == 0) {
+        if (n_fallback) launch_fill_u32((uint32_t*)n_fallback, 0u, 1, s);
+        return VICP_OK;
+    }
+    if (!px || !py || !pz || !nn_idx || !nn_d2 || !Rt) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    for (int i = 0; i < 12; ++i)
+        if (!isfinite(Rt[i])) return fail(VICP_ERR_INVALID_ARG, "non-finite pose");
+    // the grid's search schedule, over the source in index order (bucketing
+    // the source would need the grid's workspace)
+    const int qpb = g->nns_block / g->nns_lpq;
+    const int64_t njobs = (m + qpb - 1) / qpb, njobs256 = (m + 255) / 256;
+    NaSetup a{};
+    fill_grid_fields(g->pairs[0], g->pad, a.pd);
+    a.pd.p_base = 0;
+    a.pd.m = m;
+    a.pd.s_chunks = 1;
+    a.pd.s_shift = 62;
+    for (int i = 0; i < 12; ++i) a.rt[i] = Rt[i];
+    const PairDev* pd = reinterpret_cast<const PairDev*>(base + kNaOffPd);
+    PairState* st = reinterpret_cast<PairState*>(base + kNaOffSt);
+    const BlockJob* jobs = reinterpret_cast<const BlockJob*>(base + kNaOffJobs);
+    const BlockJob* jobs256 = reinterpret_cast<const BlockJob*>(base + kNaOffJobs256);
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(base + kNaOffCtr);
+    uint32_t* fb_list = reinterpret_cast<uint32_t*>(base + kNaOffList);
+    unsigned long long* fb_key = reinterpret_cast<unsigned long long*>(base + kNaOffKey);
+    const int setup_blocks = (int)std::min<int64_t>((njobs + 255) / 256, 256);
+    hipLaunchKernelGGL(k_noalloc_setup, dim3(setup_blocks), dim3(256), 0, s, a, (int32_t)njobs, (int32_t)qpb,
+                       (int32_t)njobs256, base);
+    launch_nns_local(pd, jobs, (int)njobs, g->nns_block, g->nns_lpq, false, false, px, py, pz, nullptr, st, g->dir,
+                     g->qs4, nn_idx, nn_d2, cnt, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, s);
+    launch_fallback(pd, 1, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, st, cnt, fb_list, fb_key, nullptr, 0,
+                    nullptr, nullptr, nullptr, nullptr, s);
+    launch_fb_finalize(pd, jobs256, (int)njobs256, fb_key, nn_idx, nn_d2, cnt + 1, s);
+    if (n_fallback) launch_copy_fb(cnt, n_fallback, 1, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("nns_noalloc: ") + hipGetErrorString(e));
+    return VICP_OK;
 }
 
 int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz,
