@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NNS queries/s + ICP iters/s at 226K pts; dilation buffer bytes; fwd+bwd pairs/s"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3        # published dense float32 vector peak
+# flops per byte of the search: one candidate is 16 bytes (x, y, z, index)
+# and 8 flops (3 subtractions, 1 multiply, 2 fused multiply-adds)
+SEARCH_FLOPS_PER_BYTE = 8.0 / 16.0
 PROFILE_PMC = os.path.join(ROOT, "profiles", "nns_local_room_226k_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_04996_amd", "csrc", "k_nns.hip")
 
@@ -101,6 +105,7 @@ def main():
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
                    f"{tf(schedule['sort_source'])}, true, false, {schedule['search_mode']}>")
     nns_blocks = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block'])
+    build_schedule = g.build_schedule
 
     def step():
         g.rebuild(q)
@@ -144,6 +149,7 @@ def main():
     queries_per_s = K * P.m / (ms * 1e-3)
     kernels = {}
     timing_pass = None
+    per_iter = None
     if not a.no_prof:
         prof_steps = min(a.steps, 5)
         api.prof_reset()
@@ -163,6 +169,13 @@ def main():
             if n_launch:
                 kernels[name] = {"launches_per_step": n_launch / prof_steps, "avg_us": 1e3 * tot / n_launch,
                                  "ms_per_step": tot / prof_steps}
+        # per-iteration search time (local search + global search), each
+        # iteration's mean over the timing pass's steps
+        ns, fs = api.prof_samples("nns_local"), api.prof_samples("fallback")
+        if len(ns) == len(fs) == prof_steps * P.iters:
+            it = (np.asarray(ns) + np.asarray(fs)).reshape(prof_steps, P.iters).mean(0) * 1e-3
+            per_iter = {"median_s": float(np.median(it)), "iter0_s": float(it[0]),
+                        "nns_local_median_us": float(np.median(np.asarray(ns).reshape(prof_steps, P.iters).mean(0))) * 1e3}
 
     F = np.asarray(res.fallbacks[0], np.int64)
     cand = np.asarray(res.candidates[0], np.int64)
@@ -180,8 +193,25 @@ def main():
             # counters of this very kernel variant, taken from the current source
             if pmc.get("kernel_source_sha256") == src_hash and pmc.get("kernel") == nns_variant:
                 traffic = pmc.get("hbm_bytes_per_launch")
-        roofline = {"kernel": nns_variant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        # the roofline that bounds the kernel, from its arithmetic intensity
+        # against the machine balance (peak flops / peak bytes)
+        balance = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+        bound = "hbm" if SEARCH_FLOPS_PER_BYTE < balance else "alu"
+        measured = None if traffic is None else traffic / dur_s / 1e9
+        if measured is None:
+            limiter = "unknown (no counter traffic for this kernel source)"
+        elif measured < 0.5 * HBM_PEAK_GBS:
+            limiter = (f"latency: the counters see {measured:.0f} GB/s of HBM traffic ({measured / HBM_PEAK_GBS:.2f} "
+                       f"of peak); the rest of the algorithmic bytes are served by the caches")
+        else:
+            limiter = "hbm bandwidth"
+        roofline = {"kernel": nns_variant, "bound": bound, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "hbm_measured_gbs": None if measured is None else round(measured, 1),
+                    "hbm_frac": None if measured is None else round(measured / HBM_PEAK_GBS, 4),
+                    "limiter": limiter,
+                    "flops_per_byte": SEARCH_FLOPS_PER_BYTE, "machine_balance_flops_per_byte": round(balance, 2),
+                    "timing": "mean of the per-launch start/stop HIP events of the eager timing pass",
                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
                     "mean_candidates_per_query": round(float(cand.mean()) / P.m, 3),
                     "dilated_lookup_fraction": round(float(dil.mean()) / P.m, 4)}
@@ -210,27 +240,46 @@ def main():
     vox = ijk[0] + dims[0] * (ijk[1] + dims[1] * ijk[2])
     blk = np.arange(P.n) // 256
     atomics = int(np.unique(blk * desc["V"] + vox).size)
-    # the dilation's compulsory bytes: all rings in one launch read each
-    # voxel's count once (4) and, per dilated voxel, read its offset (4) and
-    # write its count word (4) and directory entry (8); a ring-per-launch
-    # run also moves 8 per voxel per ring for the ring state
+    # the dilation's bytes, two ways.  This kernel's own compulsory bytes:
+    # all rings in one launch read each voxel's directory entry once (8;
+    # the halo re-reads hit the caches) and, per dilated voxel, write its
+    # count word (4) and its directory entry (8).  The ring model: every ring
+    # reads each voxel's offset and count word (8) and writes each newly
+    # dilated voxel's word (4), i.e. 8 L V + 4 (dilated) for L rings.
     dilation_roof = None
+    V, nd = desc["V"], desc["dilated"]
+    ring_model = 8 * P.rings * V + 4 * nd
+    tiles = ("8x8x4", "16x8x4", "8x8x8", "32x8x4", "16x16x4")
     if "dilate" in kernels:
-        dbytes = 4 * desc["V"] + 16 * desc["dilated"]
-        ach = dbytes / (kernels["dilate"]["avg_us"] * 1e-6) / 1e9
-        dilation_roof = {"kernel": f"k_dilate_fused<{P.rings}>", "bound": "hbm", "achieved": round(ach, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "compulsory_bytes_per_launch": int(dbytes)}
+        dur = kernels["dilate"]["avg_us"] * 1e-6
+        dbytes = 8 * V + 12 * nd
+        ach = dbytes / dur / 1e9
+        t = tiles[build_schedule["dilate_tile"]].split("x")
+        dilation_roof = {"kernel": f"k_dilate_fused<{P.rings}, {t[0]}, {t[1]}, {t[2]}>", "bound": "hbm",
+                         "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "compulsory_bytes_per_launch": int(dbytes),
+                         "ring_model_bytes": int(ring_model),
+                         "ring_model_frac": round(ring_model / dur / 1e9 / HBM_PEAK_GBS, 4),
+                         "avg_us": round(kernels["dilate"]["avg_us"], 3)}
     elif "dilate_ring" in kernels:
-        ring_bytes = 8 * desc["V"] + 4 * desc["dilated"] / max(P.rings, 1)
-        ach = ring_bytes / (kernels["dilate_ring"]["avg_us"] * 1e-6) / 1e9
-        dilation_roof = {"kernel": "k_dilate_ring<256>", "bound": "hbm", "achieved": round(ach, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "compulsory_bytes_per_ring": int(ring_bytes)}
+        dur = kernels["dilate_ring"]["avg_us"] * 1e-6 * P.rings
+        ach = ring_model / dur / 1e9
+        dilation_roof = {"kernel": f"k_dilate_ring<{build_schedule['ring_block']}> x {P.rings}", "bound": "hbm",
+                         "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "ring_model_bytes": int(ring_model),
+                         "avg_us_all_rings": round(dur * 1e6, 3)}
     search_qps = None
     if "nns_local" in kernels and "fallback" in kernels:
         it_us = kernels["nns_local"]["avg_us"] + kernels["fallback"]["avg_us"]
         search_qps = round(P.m / (it_us * 1e-6), 1)
+    nns_qps = None
+    if per_iter is not None:
+        nns_qps = {"median_over_iterations": round(P.m / per_iter["median_s"], 1),
+                   "iteration0": round(P.m / per_iter["iter0_s"], 1),
+                   "median_iteration_us": round(per_iter["median_s"] * 1e6, 3),
+                   "iteration0_us": round(per_iter["iter0_s"] * 1e6, 3),
+                   "what": "source points / (local search + global search time of one iteration), per-launch HIP "
+                           "events of the timing pass, each iteration averaged over its steps"}
     # attainable bandwidth: a plain device-to-device copy of 1 GiB (with the
     # timing pass only: profiler runs keep their copies to the calibration one)
     if roofline is not None:
@@ -253,6 +302,7 @@ def main():
         "config": {"workload": P.name, "n_target": P.n, "n_source": P.m, "voxel": P.voxel, "rings": P.rings,
                    "iters": P.iters, "step": "grid build + dilation + 30 ICP iterations",
                    "icp_mode": "graph" if a.graph else "eager", "schedule": schedule,
+                   "build_schedule": build_schedule,
                    "schedule_source": "autotuned" if a.schedule == "auto" else "given",
                    "kernel_timing": timing_pass},
         "icp_iters_per_s": round(K / (ms * 1e-3), 2),
@@ -263,6 +313,7 @@ def main():
         "register_ms_p90": round(float(np.percentile(reg_ms, 90)), 4),
         "icp_iters_per_s_registration": round(K / (float(np.median(reg_ms)) * 1e-3), 2),
         "search_queries_per_s": search_qps,
+        "nns_queries_per_s": nns_qps,
         "global_searches_per_iter": [int(x) for x in F],
         "count_global_atomics": {"with_lds_hash": atomics, "one_per_point": P.n},
         "roofline": roofline,
@@ -478,7 +529,7 @@ def extra_figures(api, synth, torch, dev, np):
         return Pg.grad, xg.grad
 
     for _ in range(3):
-        fwd_bwd()
+        gb_P, gb_x = fwd_bwd()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nrep = 20
@@ -486,9 +537,43 @@ def extra_figures(api, synth, torch, dev, np):
         fwd_bwd()
     torch.cuda.synchronize()
     td = (time.perf_counter() - t0) / nrep
+    # the same 16 forward + backward passes as single-pair calls, one grid
+    # per pair under the same schedule, at the same accuracy (compared)
+    singles = []
+    for b, x in enumerate(dpairs):
+        gs = api.build_grid(torch.from_numpy(x.q).to(dev), x.voxel, 2)
+        gs.dilate(2)
+        gs.set_schedule(**g.schedule)
+        singles.append(gs)
+
+    def single_fwd_bwd():
+        out = []
+        for b in range(B):
+            Pg = P3[b:b + 1].detach().requires_grad_(True)
+            xg = xit[b:b + 1].detach().requires_grad_(True)
+            L = p2p_loss(singles[b], Pg, xg).sum()
+            L.backward()
+            out.append((Pg.grad, xg.grad))
+        return out
+
+    for _ in range(3):
+        sl = single_fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nrep):
+        single_fwd_bwd()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / nrep
+    same = all(torch.equal(sl[b][0][0], gb_P[b]) and torch.equal(sl[b][1][0], gb_x[b]) for b in range(B))
+    for gs in singles:
+        gs.free()
     g.free()
     ex["diff_16x40k"] = {"pairs": B, "points_per_pair": dpairs[0].m, "ms_fwd_bwd": round(td * 1e3, 3),
-                         "fwd_bwd_pairs_per_s": round(B / td, 1)}
+                         "fwd_bwd_pairs_per_s": round(B / td, 1),
+                         "single_pair_calls_ms": round(ts * 1e3, 3),
+                         "single_pair_calls_pairs_per_s": round(B / ts, 1),
+                         "speedup_vs_single_pair_calls": round(ts / td, 3),
+                         "bit_identical_to_single_pair_calls": bool(same)}
     ex["dilation_buffer_other"] = sizes
     return ex
 
@@ -560,20 +645,24 @@ def vanicp_comparator(api, synth, torch, dev, np):
 
 
 def cpu_baseline(P):
-    """The CPU oracle as it stands, single-threaded, on the same workload:
-    whole registrations (grid, dilation, 30 iterations) repeated until about
-    10 s of CPU time have been spent."""
+    """The CPU oracle as it stands on this host's cores: whole registrations
+    (grid, dilation, every iteration) of the three single-pair workloads,
+    single-threaded and with Alg. 4's per-query loop on every core the
+    process may use (at most 16), median of 3 runs (1 for the room); then the
+    headline figure, the room workload on every core, repeated for about
+    10 s."""
+    import statistics
+
     import oracle
+    from paper_2512_04996_amd import synth
     log("[bench] cpu baseline (oracle)")
     oracle.lib()
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        r = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 40:
-            break
+    cores = min(16, len(os.sched_getaffinity(0)))
+    try:
+        cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    except ValueError:
+        pass
+    cores = max(cores, 1)
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -582,10 +671,37 @@ def cpu_baseline(P):
                 break
     except OSError:
         pass
-    return {"value": round(reps * r.iters * P.m / el, 1), "unit": "queries/s", "cores": 1, "kind": "oracle",
+    per = {}
+    for name, reps in (("sphere_2k", 3), ("bumpy_40k", 3), ("room_226k", 1)):
+        W = P if name == P.name else synth.config(name)
+        row = {}
+        for th in sorted({1, cores}):
+            used = oracle.set_threads(th)
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                r = oracle.register(W.q, W.p, W.voxel, W.rings, W.iters)
+                times.append(time.perf_counter() - t0)
+            t = statistics.median(times)
+            row[f"threads_{used}"] = {"queries_per_s": round(r.iters * W.m / t, 1),
+                                      "icp_iters_per_s": round(r.iters / t, 3), "s_per_registration": round(t, 4)}
+        per[name] = row
+    used = oracle.set_threads(cores)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.register(P.q, P.p, P.voxel, P.rings, P.iters)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or reps >= 200:
+            break
+    oracle.set_threads(1)
+    return {"value": round(reps * r.iters * P.m / el, 1), "unit": "queries/s", "cores": used, "kind": "oracle",
             "sample": f"{reps} full registrations of {P.name} (grid + dilation + {P.iters} iterations), "
-                      f"{el:.1f} s, single thread",
-            "icp_iters_per_s": round(reps * r.iters / el, 3), "cpu": cpu}
+                      f"{el:.1f} s, Alg. 4's per-query loop on {used} threads",
+            "icp_iters_per_s": round(reps * r.iters / el, 3), "cpu": cpu,
+            "per_workload": per,
+            "note": "median of 3 runs for sphere_2k and bumpy_40k, 1 for room_226k; threads_1 is single-threaded"}
 
 
 if __name__ == "__main__":

@@ -101,6 +101,11 @@ typedef struct vicp_icp_opts {
     int32_t layout;      /* 0: the segmented, offset-addressed layout (Alg. 2-4); 1: VANICP's
                             monolithic direct-addressed layout built by vicp_direct_build (the
                             comparator); excludes global_only */
+    int32_t* nn_idx;     /* optional (NULL: not written): device int32[m] (batched: all pairs'
+                            sources in pair order) receiving, for every source point, the target
+                            index of its Alg. 4 correspondence in the last iteration the pair ran,
+                            written by the registration's own search and solve kernels */
+    float* nn_d2;        /* with nn_idx: device float32[m], the squared distances (float32) */
 } vicp_icp_opts;
 
 /* Per-pair registration statistics.  The arrays are caller-owned HOST arrays
@@ -121,7 +126,10 @@ typedef struct vicp_icp_stats {
  * into their segments [lock = 0, count, indices ascending].  Synchronises the
  * stream once, to read the 24-byte bounding box that sizes the grid.
  * Errors: n <= 0, voxel <= 0 or non-finite, pad_rings < 0 -> INVALID_ARG;
- * non-finite target coordinates -> NONFINITE; grid too large -> GRID_TOO_LARGE. */
+ * non-finite target coordinates -> NONFINITE; grid too large -> GRID_TOO_LARGE;
+ * a padded grid reaching beyond +-VICP_COORD_LIMIT on any axis (float32
+ * squared distances inside it could overflow) -> INVALID_ARG. */
+#define VICP_COORD_LIMIT 1e18f
 int vicp_build_grid(const float* qx, const float* qy, const float* qz, int64_t n,
                     float voxel, int32_t pad_rings, const vicp_allocator* alloc,
                     hipStream_t stream, vicp_grid** out);
@@ -296,13 +304,26 @@ int vicp_grid_export(const vicp_grid* g, int32_t pair, uint32_t* hist, uint32_t*
 /* Releases the grid and everything it owns (after its queued work). */
 int vicp_grid_free(vicp_grid* g);
 
-/* Autotuning: times the schedules of the search (see vicp_get_schedule) on
- * this grid and source at the identity pose and keeps the fastest in the
- * grid.  The source-bucketing pass serves `searches_per_plan` searches (1 for
- * vicp_nns, the iteration count for vicp_register) and is charged at that
- * rate.  Correspondences and counts never depend on the schedule; a pose may
- * differ in its last bits (see vicp_get_schedule).  Synchronises the
- * stream. */
+/* Autotuning: times schedules on this grid and source and keeps the fastest
+ * in the grid:
+ *   - the count's block size (vicp_get_build_schedule), re-running the count
+ *     (the histogram it leaves is the same);
+ *   - on a dilated grid of 1 to 4 rings, the dilation's form and tile shape,
+ *     re-running the dilation (which leaves the same grid);
+ *   - the search (see vicp_get_schedule) in its registration form at the
+ *     identity pose; the source-bucketing pass serves `searches_per_plan`
+ *     searches (1 for vicp_nns, the iteration count for vicp_register) and is
+ *     charged at that rate;
+ *   - the global search's block count on a load of listed queries (the
+ *     first max(256, m/64) sources of each pair) charged once per
+ *     `searches_per_plan` searches, beside the fold it also runs.
+ * The chosen schedule is stored per shape (pairs' point counts, grid
+ * dimensions, rings, source sizes); a later call on the same shape in this
+ * process takes it without timing, and with the environment variable
+ * VICP_AUTOTUNE_CACHE naming a file, schedules are read from and appended to
+ * that file.  Correspondences, counts and grids never depend on the schedule;
+ * a pose may differ in its last bits (see vicp_get_schedule).  Synchronises
+ * the stream. */
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz,
                   const int64_t* m_per_pair, int32_t searches_per_plan, hipStream_t stream);
 
@@ -324,11 +345,32 @@ int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per
 int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, int32_t sort_source,
                       int32_t fallback_grid, int32_t search_mode);
 
+/* The build schedule of a grid: threads per block of the count (256, 512 or
+ * 1024 target points per block, which is also how many points share one LDS
+ * hash), and the dilation's form for 1 to 4 rings: dilate_fused = 1 runs every
+ * ring in one launch on LDS tiles of shape dilate_tile (0: 8x8x4 voxels,
+ * 1: 16x8x4, 2: 8x8x8, 3: 32x8x4, 4: 16x16x4, plus a halo of L voxels),
+ * 0 one launch per ring with ring_block threads per 256-voxel block (64, 128
+ * or 256; also the form for more than 4 rings).  No setting changes a result.
+ * INVALID_ARG for an unsupported value. */
+int vicp_get_build_schedule(const vicp_grid* g, int32_t* count_block, int32_t* dilate_fused, int32_t* dilate_tile,
+                            int32_t* ring_block);
+int vicp_set_build_schedule(vicp_grid* g, int32_t count_block, int32_t dilate_fused, int32_t dilate_tile,
+                            int32_t ring_block);
+
+/* Forgets every schedule vicp_autotune stored in this process (the file
+ * named by VICP_AUTOTUNE_CACHE is left as it is). */
+int vicp_autotune_cache_clear(void);
+
 /* Per-kernel timing with HIP events on the launch stream (0 = off).  While on,
  * every launch of a named kernel is bracketed by events; vicp_prof_read gives
- * the count and summed milliseconds (synchronises the events). */
+ * the count and summed milliseconds, vicp_prof_samples the duration of each
+ * launch in launch order (up to `cap` into the HOST array ms, the number
+ * recorded in *count); both synchronise the events.  vicp_prof_reset clears
+ * both. */
 int vicp_prof_enable(int32_t on);
 int vicp_prof_read(const char* kernel, int64_t* launches, double* total_ms);
+int vicp_prof_samples(const char* kernel, double* ms, int64_t cap, int64_t* count);
 int vicp_prof_reset(void);
 
 const char* vicp_status_str(int code);

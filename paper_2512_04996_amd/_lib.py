@@ -41,7 +41,8 @@ class GridDesc(C.Structure):
 
 class IcpOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("rmse_eps", C.c_double), ("early_stop", C.c_int32),
-                ("use_graph", C.c_int32), ("global_only", C.c_int32), ("layout", C.c_int32)]
+                ("use_graph", C.c_int32), ("global_only", C.c_int32), ("layout", C.c_int32),
+                ("nn_idx", C.c_void_p), ("nn_d2", C.c_void_p)]
 
 
 class IcpStats(C.Structure):
@@ -88,7 +89,12 @@ SYMBOLS = {
     "vicp_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "vicp_set_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "vicp_get_build_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vicp_set_build_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "vicp_autotune_cache_clear": (C.c_int, []),
     "vicp_prof_enable": (C.c_int, [C.c_int32]),
+    "vicp_prof_samples": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]),
     "vicp_prof_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "vicp_prof_reset": (C.c_int, []),
     "vicp_status_str": (C.c_char_p, [C.c_int]),

@@ -16,7 +16,8 @@ import torch
 from . import _lib
 from ._lib import GridDesc, IcpOpts, IcpStats, VicpError, check, lib
 
-__all__ = ["Grid", "build_grid", "build_grid_batched", "IcpResult", "prof_enable", "prof_read", "prof_reset"]
+__all__ = ["Grid", "build_grid", "build_grid_batched", "IcpResult", "prof_enable", "prof_read", "prof_samples",
+           "prof_reset", "autotune_cache_clear"]
 
 
 def _stream():
@@ -56,6 +57,8 @@ class IcpResult:
     candidates: list          # per pair, int64[iters]: target points scanned by local searches
     dilated_lookups: list     # per pair, int64[iters]: local searches sent to a root voxel
     status: int
+    nn_idx: object = None     # with correspondences=True: int32[m] CUDA tensor, the last iteration's targets
+    nn_d2: object = None      # ... and their float32 squared distances
 
 
 class Grid:
@@ -131,6 +134,20 @@ class Grid:
                                       int(fallback_grid), int(search_mode)), "vicp_set_schedule")
         return self
 
+    @property
+    def build_schedule(self) -> dict:
+        a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().vicp_get_build_schedule(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
+              "vicp_get_build_schedule")
+        return {"count_block": a.value, "dilate_fused": bool(b.value), "dilate_tile": c.value,
+                "ring_block": d.value}
+
+    def set_build_schedule(self, count_block: int = 256, dilate_fused: bool = True, dilate_tile: int = 0,
+                           ring_block: int = 256):
+        check(lib().vicp_set_build_schedule(self.handle, int(count_block), int(bool(dilate_fused)), int(dilate_tile),
+                                            int(ring_block)), "vicp_set_build_schedule")
+        return self
+
     # -- Alg. 3
     def dilate(self, rings: int):
         check(lib().vicp_dilate(self.handle, int(rings), _stream()), "vicp_dilate")
@@ -182,7 +199,10 @@ class Grid:
     # -- the ICP loop
     def register(self, p: torch.Tensor, max_iter: int, rmse_eps: float = 1e-5, early_stop: bool = False,
                  use_graph: bool = True, Rt0=None, m_per_pair=None, raise_degenerate: bool = False,
-                 global_only: bool = False, layout: str = "segmented") -> IcpResult:
+                 global_only: bool = False, layout: str = "segmented", correspondences: bool = False) -> IcpResult:
+        """The ICP loop (Sec. II.A); with correspondences=True the result also
+        carries the last iteration's correspondences, written by the
+        registration's own kernels."""
         p = _soa(p, "p")
         m = p.shape[1]
         B = self.npairs
@@ -208,8 +228,13 @@ class Grid:
             stats[b].dilated_lookups = dil[b].ctypes.data_as(C.POINTER(C.c_int64))
         if layout not in ("segmented", "direct"):
             raise ValueError("layout must be 'segmented' or 'direct'")
+        out_idx = out_d2 = None
+        if correspondences:
+            out_idx = torch.full((max(m, 1),), -1, dtype=torch.int32, device=p.device)
+            out_d2 = torch.full((max(m, 1),), float("nan"), dtype=torch.float32, device=p.device)
         opts = IcpOpts(K, float(rmse_eps), int(bool(early_stop)), int(bool(use_graph)), int(bool(global_only)),
-                       int(layout == "direct"))
+                       int(layout == "direct"), out_idx.data_ptr() if correspondences else None,
+                       out_d2.data_ptr() if correspondences else None)
         px, py, pz = _ptrs(p)
         rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
                                          rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())
@@ -221,7 +246,8 @@ class Grid:
                          [rm[b, :iters[b]].copy() for b in range(B)],
                          [fbk[b, :iters[b]].copy() for b in range(B)],
                          [cnd[b, :iters[b]].copy() for b in range(B)],
-                         [dil[b, :iters[b]].copy() for b in range(B)], rc)
+                         [dil[b, :iters[b]].copy() for b in range(B)], rc,
+                         out_idx[:m] if correspondences else None, out_d2[:m] if correspondences else None)
 
     # -- helpers
     def describe(self, pair: int = 0) -> dict:
@@ -307,6 +333,20 @@ def prof_read(kernel: str):
     ms = C.c_double()
     check(lib().vicp_prof_read(kernel.encode(), C.byref(n), C.byref(ms)), "vicp_prof_read")
     return n.value, ms.value
+
+
+def prof_samples(kernel: str):
+    """Each launch's milliseconds, in launch order, since the last reset."""
+    n = C.c_int64()
+    check(lib().vicp_prof_samples(kernel.encode(), None, 0, C.byref(n)), "vicp_prof_samples")
+    out = (C.c_double * max(n.value, 1))()
+    check(lib().vicp_prof_samples(kernel.encode(), out, n.value, C.byref(n)), "vicp_prof_samples")
+    return [out[i] for i in range(n.value)]
+
+
+def autotune_cache_clear():
+    """Forget the schedules the autotuner stored in this process."""
+    check(lib().vicp_autotune_cache_clear(), "vicp_autotune_cache_clear")
 
 
 def prof_reset():

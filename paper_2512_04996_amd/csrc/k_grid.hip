@@ -113,9 +113,12 @@ __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx,
 // --------------------------------------------------------------------------
 // voxelise + count with a per-block LDS hash (32-bit key, 32-bit count):
 // one global atomic per distinct (block, voxel), which also hands each point
-// its slot inside the voxel's segment.
+// its slot inside the voxel's segment.  BS points per block share one hash
+// of 2 BS slots.
 // --------------------------------------------------------------------------
 constexpr int kSlots = 2 * kThreads;
+
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 
 //
 // kDirect: VANICP's monolithic layout instead.  The point's slot is its
@@ -123,17 +126,19 @@ constexpr int kSlots = 2 * kThreads;
 // copied there as (x, y, z, index) when the block has room; `hist` then
 // counts every point of the voxel, so a count above `cap` marks a block that
 // overflowed.
-template <bool kDirect>
-__global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
-                                                    const float* __restrict__ qz, const PairDev* __restrict__ pd,
-                                                    const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
-                                                    uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
-                                                    uint32_t* err, float4* __restrict__ blk, uint32_t cap)
+template <bool kDirect, int BS>
+__global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
+                                              const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                              const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
+                                              uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
+                                              uint32_t* err, float4* __restrict__ blk, uint32_t cap)
 {
-    __shared__ uint32_t skey[kSlots];
-    __shared__ uint32_t scnt[kSlots];
-    __shared__ uint32_t sbase[kSlots];
-    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+    constexpr int kS = 2 * BS;
+    constexpr int kShift = 32 - log2i(kS);
+    __shared__ uint32_t skey[kS];
+    __shared__ uint32_t scnt[kS];
+    __shared__ uint32_t sbase[kS];
+    for (int s = threadIdx.x; s < kS; s += BS) {
         skey[s] = kNone;
         scnt[s] = 0;
     }
@@ -156,16 +161,16 @@ __global__ __launch_bounds__(kThreads) void k_count(const float* __restrict__ qx
         }
     }
     if (valid) {
-        slot = (v * 2654435761u) >> 23;   // 9 bits
+        slot = (v * 2654435761u) >> kShift;
         while (true) {
             uint32_t prev = atomicCAS(&skey[slot], kNone, v);
             if (prev == kNone || prev == v) break;
-            slot = (slot + 1) & (kSlots - 1);
+            slot = (slot + 1) & (kS - 1);
         }
         lr = atomicAdd(&scnt[slot], 1u);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+    for (int s = threadIdx.x; s < kS; s += BS) {
         const uint32_t k = skey[s];
         if (k != kNone) sbase[s] = atomicAdd(&hist[P.v_base + k], scnt[s]);
     }
@@ -491,22 +496,29 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
 }
 
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
-                  int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, bool packed, hipStream_t s)
+                  int njobs, int block, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, bool packed,
+                  hipStream_t s)
 {
     if (njobs <= 0) return;
     if (packed)
         hipLaunchKernelGGL(k_count_packed, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
                            err);
-    else
-        hipLaunchKernelGGL(k_count<false>, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
+    else if (block == 1024)
+        hipLaunchKernelGGL((k_count<false, 1024>), dim3(njobs), dim3(1024), 0, s, qx, qy, qz, pd, jobs, hist, vox,
+                           rank, err, (float4*)nullptr, 0u);
+    else if (block == 512)
+        hipLaunchKernelGGL((k_count<false, 512>), dim3(njobs), dim3(512), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
                            err, (float4*)nullptr, 0u);
+    else
+        hipLaunchKernelGGL((k_count<false, kThreads>), dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist,
+                           vox, rank, err, (float4*)nullptr, 0u);
 }
 
 void launch_count_direct(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
                          int njobs, uint32_t* cnt, uint32_t* err, float4* blk, uint32_t cap, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_count<true>, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, cnt,
+    hipLaunchKernelGGL((k_count<true, kThreads>), dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, cnt,
                        (uint32_t*)nullptr, (uint32_t*)nullptr, err, blk, cap);
 }
 

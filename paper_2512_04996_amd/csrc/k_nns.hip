@@ -140,6 +140,10 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // lane keeps the best distance and segment position only, and the winner's
 // record is read once after the lanes combine (one more dependent load per
 // query, three fewer selects per candidate).
+//
+// In registration nn_idx / nn_d2 are optional (null when not asked for): the
+// correspondence and squared distance of each locally resolved query are
+// written there too; the solve writes those of the globally searched ones.
 template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, int kMode>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
@@ -272,15 +276,17 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             }
         }
     }
+    uint32_t bidx = bj;   // the winner's target index
     if (kReload && active && c > 0 && sub == 0) {
-        const float4 wv = qs4[cs + bj];
+        const float4 wv = qs4[cs + min(bj, c - 1u)];   // bj < c: every distance is finite inside a grid
         bx = wv.x;
         by = wv.y;
         bz = wv.z;
+        bidx = __float_as_uint(wv.w);
     }
     const bool found = active && c > 0 && sub == 0;
-    if (!kMom && found) {
-        nn_idx[gp] = (int32_t)bj;
+    if (found && (!kMom || nn_idx)) {
+        nn_idx[gp] = (int32_t)bidx;
         nn_d2[gp] = bd;
     }
     // Reductions over the block in a fixed order.  Counters are exact
@@ -476,10 +482,10 @@ __global__ __launch_bounds__(256) void k_src_rank(const PairDev* __restrict__ pd
 // Global search.  Work item = (pair, chunk of kFbQ listed queries, tile of
 // kFbT targets); items are enumerated from the device-side list lengths, so
 // the launch shape is fixed (graph-capturable) whatever the number of misses.
-constexpr int kFbThreads = 256;
-constexpr int kFbQ = kFbThreads;
-constexpr int kFbT = 1024;
-constexpr int kMaxPairs = 4096;
+constexpr int kFbThreads = kFbQueries;
+constexpr int kFbQ = kFbQueries;
+constexpr int kFbT = kFbTargets;
+constexpr int kMaxPairs = kFbMaxPairs;
 
 __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restrict__ pd, int npairs,
                                                          const float* __restrict__ qx, const float* __restrict__ qy,
@@ -495,7 +501,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
                                                          double* __restrict__ fpart,
                                                          unsigned long long* __restrict__ fctr)
 {
-    __shared__ int32_t s_pref[kMaxPairs + 1];
+    __shared__ int64_t s_pref[kMaxPairs + 1];
     __shared__ float tx[kFbT], ty[kFbT], tz[kFbT];
     // the first kFbThreads pairs' list lengths and target counts do not
     // depend on the fold: loaded before it, used after it
@@ -554,16 +560,16 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
             __syncthreads();
         }
     }
-    // items per pair, loaded in parallel, then an in-LDS running sum
+    // items per pair (64-bit), loaded in parallel, then an in-LDS running sum
     for (int p = threadIdx.x; p < npairs; p += kFbThreads) {
         const bool first = p == (int)threadIdx.x;
         const int64_t F = first ? F0 : fb_count[p];
         const int64_t n = first ? n0 : pd[p].n;
-        s_pref[p + 1] = F > 0 ? (int32_t)(((F + kFbQ - 1) / kFbQ) * ((n + kFbT - 1) / kFbT)) : 0;
+        s_pref[p + 1] = fallback_items(F, n);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t acc = 0;
+        int64_t acc = 0;
         s_pref[0] = 0;
         for (int p = 1; p <= npairs; ++p) {
             acc += s_pref[p];
@@ -571,8 +577,8 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
         }
     }
     __syncthreads();
-    const int32_t total = s_pref[npairs];
-    for (int32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int64_t total = s_pref[npairs];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
         int lo = 0, hi = npairs;   // last p with s_pref[p] <= item
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -581,9 +587,9 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
         }
         const int p = lo;
         const PairDev& P = pd[p];
-        const int32_t local = item - s_pref[p];
-        const int32_t ntile = (int32_t)((P.n + kFbT - 1) / kFbT);
-        const int32_t qc = local / ntile, tile = local % ntile;
+        const int64_t local = item - s_pref[p];
+        const int64_t ntile = (P.n + kFbT - 1) / kFbT;
+        const int64_t qc = local / ntile, tile = local % ntile;
         const int64_t t0 = (int64_t)tile * kFbT;
         const int tn = (int)min((int64_t)kFbT, P.n - t0);
         __syncthreads();
@@ -594,7 +600,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
             tz[j] = qz[g];
         }
         __syncthreads();
-        const int32_t slot = qc * kFbQ + threadIdx.x;
+        const int64_t slot = qc * kFbQ + threadIdx.x;
         if (slot < fb_count[p]) {
             const uint32_t i = fb_list[P.p_base + slot];
             const int64_t gp = P.p_base + i;
@@ -740,15 +746,16 @@ void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const f
     hipLaunchKernelGGL(k_src_rank, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, soff, sidx, sbig, ps4);
 }
 
-void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
+bool launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
                      const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
                      const double* part, const unsigned long long* ctr, double* fpart,
                      unsigned long long* fctr, hipStream_t s)
 {
-    if (npairs <= 0 || npairs > kMaxPairs) return;
+    if (npairs <= 0 || npairs > kMaxPairs || grid <= 0) return false;
     launch_timed(k_fallback, dim3(grid), dim3(kFbThreads), s, pd, npairs, qx, qy, qz, px, py, pz, st, fb_count,
                  fb_list, fb_key, fjobs, nunits, part, ctr, fpart, fctr);
+    return true;
 }
 
 void launch_fb_finalize(const PairDev* pd, const BlockJob* jobs, int njobs, const unsigned long long* fb_key,

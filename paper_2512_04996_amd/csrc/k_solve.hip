@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
     int32_t* __restrict__ flags, double* __restrict__ rmse_hist, int32_t* __restrict__ fb_hist,
     int32_t* __restrict__ deg_hist, unsigned long long* __restrict__ ctr_hist, int k, int K, int early_stop,
-    double eps)
+    double eps, int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2)
 {
     __shared__ double tot[kMoments];
     __shared__ unsigned long long ctot[2];
@@ -400,8 +400,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
                     continue;
                 }
                 const int64_t gp = P.p_base + w0 + r, gq = P.q_base + j;
-                add_moments(acc, px[gp], py[gp], pz[gp], qx[gq], qy[gq], qz[gq],
-                            __uint_as_float((uint32_t)(key >> 32)), cen[0], cen[1], cen[2]);
+                const float d = __uint_as_float((uint32_t)(key >> 32));
+                add_moments(acc, px[gp], py[gp], pz[gp], qx[gq], qy[gq], qz[gq], d, cen[0], cen[1], cen[2]);
+                if (nn_idx) {   // the correspondences, when asked for
+                    nn_idx[gp] = (int32_t)j;
+                    nn_d2[gp] = d;
+                }
             }
             __syncthreads();
         }
@@ -492,12 +496,12 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                   const unsigned long long* fb_key, const float* px, const float* py, const float* pz,
                   const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
-                  double eps, hipStream_t s)
+                  double eps, int32_t* nn_idx, float* nn_d2, hipStream_t s)
 {
     if (npairs <= 0) return;
     launch_timed(k_solve, dim3(npairs), dim3(kSolveThreads), s, pd, fold_begin, nunits, fpart, fctr, st, fb_count,
                  fb_list, fb_key, px, py, pz, qx, qy, qz, flags, rmse_hist, fb_hist, deg_hist, ctr_hist, k, K,
-                 early_stop, eps);
+                 early_stop, eps, nn_idx, nn_d2);
 }
 
 void launch_set_state_inline(const PairDev* pd, PairState* st, const double* host_rt, int npairs,

@@ -6,6 +6,8 @@
 // arithmetic of the method runs on the host except the grid specification
 // (float32 scalar code, identical rounding to the device's).
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -112,6 +114,7 @@ struct Prof {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<int64_t, double>> acc;
+    std::map<std::string, std::vector<double>> samples;   // each launch's milliseconds, in launch order
 } g_prof;
 
 // Host-side work timed on the host clock (e.g. the host offset scan).
@@ -145,6 +148,7 @@ void prof_flush_locked()
             auto& x = g_prof.acc[r.name];
             x.first += 1;
             x.second += ms;
+            g_prof.samples[r.name].push_back(ms);
         }
         g_prof.pool.push_back(r.a);
         g_prof.pool.push_back(r.b);
@@ -263,6 +267,7 @@ void prof_add_graph(const std::vector<ProfRec>& evs)
             auto& x = g_prof.acc[r.name];
             x.first += 1;
             x.second += ms;
+            g_prof.samples[r.name].push_back(ms);
         } else {
             (void)hipGetLastError();
             g_prof.acc["graph_untimed"].first += 1;
@@ -366,6 +371,10 @@ struct vicp_grid {
     uint32_t* err = nullptr;
     BlockJob* jobs_q = nullptr;      // 256 target points per block
     int njobs_q = 0;
+    BlockJob* jobs_q512 = nullptr;   // 512 and 1024 target points per block (count schedules)
+    int njobs_q512 = 0;
+    BlockJob* jobs_q1024 = nullptr;
+    int njobs_q1024 = 0;
     BlockJob* jobs_q8 = nullptr;     // 2048 target points per block (bounding box)
     int njobs_q8 = 0;
     uint32_t *vox = nullptr, *rank = nullptr, *slots = nullptr;
@@ -374,13 +383,17 @@ struct vicp_grid {
     uint2* dir = nullptr;   // per voxel: (start in qs4, count | mask), root's entry for a dilated voxel
     BlockJob* jobs_v = nullptr;
     int njobs_v = 0;
-    BlockJob* jobs_t = nullptr;   // voxel tiles of the one-launch dilation
-    int njobs_t = 0;
+    BlockJob* jobs_t[kDilateShapes] = {};   // voxel tiles of the one-launch dilation, per tile shape
+    int njobs_t[kDilateShapes] = {};
     unsigned long long* scan_status = nullptr;
     uint32_t* scan_ticket = nullptr;
     uint32_t *dil_a = nullptr, *dil_b = nullptr;
 
     // schedule choices (never change a result)
+    int count_block = 256;   // target points per count block
+    bool dil_fused = true;   // 1-4 rings in one launch (else one launch per ring)
+    int dil_shape = 0;       // tile shape of the one-launch dilation
+    int ring_block = 256;    // threads per block of the ring-by-ring dilation
     int nns_block = 256;
     int nns_lpq = 4;
     int fb_grid = 128;
@@ -720,10 +733,12 @@ void queue_start(vicp_grid* g, const double* rt_host, const float* px, const flo
 }
 
 // Correspondence search for every pair at the poses in g->st (Alg. 4).
-// mom: registration form (per-block moment partials instead of per-query
-// results).  all_global: every query takes the exact global search.
-// direct: search VANICP's monolithic layout instead (registration form).
-void queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
+// mom: registration form (per-block moment partials; the per-query results
+// only when nn_idx is not null).  all_global: every query takes the exact
+// global search.  direct: search VANICP's monolithic layout instead
+// (registration form).  False when the batch is too large for the global
+// search (nothing of it queued).
+bool queue_search(vicp_grid* g, const float* px, const float* py, const float* pz, int32_t* nn_idx, float* nn_d2,
                   hipStream_t s, bool cap, bool mom, bool all_global = false, bool direct = false)
 {
     const int tab = table_of(g->nns_block / g->nns_lpq);
@@ -734,23 +749,35 @@ void queue_search(vicp_grid* g, const float* px, const float* py, const float* p
                          g->fb_key, g->ctr, g->npart, all_global ? 1 : 0, direct ? g->dcnt : nullptr, g->dcap,
                          g->search_mode, s);
     }
-    {
-        ProfScope ps("fallback", s, cap, true);
-        launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count, g->fb_list,
-                        g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->npart, g->ctr,
-                        g->fpart, g->fctr, s);
-    }
+    ProfScope ps("fallback", s, cap, true);
+    return launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count,
+                           g->fb_list, g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->npart, g->ctr,
+                           g->fpart, g->fctr, s);
 }
 
-void queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
-                     double eps, hipStream_t s, bool cap, bool all_global, bool direct)
+// One ICP iteration (search, global search with the fold, solve); nn_idx /
+// nn_d2 (optional) receive the iteration's correspondences.
+bool queue_iteration(vicp_grid* g, const float* px, const float* py, const float* pz, int k, int K, int early,
+                     double eps, hipStream_t s, bool cap, bool all_global, bool direct, int32_t* nn_idx, float* nn_d2)
 {
-    queue_search(g, px, py, pz, nullptr, nullptr, s, cap, true, all_global, direct);
+    if (!queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, true, all_global, direct)) return false;
     ProfScope ps("solve", s, cap, true);
     const int tab = table_of(g->nns_block / g->nns_lpq);
     launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
                  g->fb_count, g->fb_list, g->fb_key, px, py, pz, g->qx, g->qy, g->qz, g->flags, g->rmse_hist,
-                 g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, s);
+                 g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, nn_idx, nn_d2, s);
+    return true;
+}
+
+// The grid box [origin, origin + dims * voxel] within the coordinate limit.
+bool box_fits(const float origin[3], const int32_t dims[3], float voxel)
+{
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = origin[a];
+        hi[a] = (float)((double)origin[a] + (double)dims[a] * (double)voxel);
+    }
+    return grid_box_fits(lo, hi);
 }
 
 // float32 grid specification of one pair from its bounding box (host code,
@@ -771,6 +798,8 @@ int grid_spec(PairHost& h, const float lo[3], const float hi[3], float voxel, in
         if (V >= (int64_t)1 << 31) return fail(VICP_ERR_GRID_TOO_LARGE, "grid has 2^31 voxels or more");
     }
     if (h.n + 2 * V >= (int64_t)1 << 32) return fail(VICP_ERR_GRID_TOO_LARGE, "n + 2V does not fit 32-bit offsets");
+    if (!box_fits(h.origin, h.dims, voxel))
+        return fail(VICP_ERR_INVALID_ARG, "the grid reaches beyond +-1e18: float32 squared distances could overflow");
     h.inv = inv;
     h.voxel = voxel;
     h.V = V;
@@ -788,6 +817,8 @@ int fixed_grid_spec(PairHost& h, const float origin[3], const int32_t dims[3], f
     }
     if (V >= (int64_t)1 << 31) return fail(VICP_ERR_GRID_TOO_LARGE, "grid has 2^31 voxels or more");
     if (h.n + 2 * V >= (int64_t)1 << 32) return fail(VICP_ERR_GRID_TOO_LARGE, "n + 2V does not fit 32-bit offsets");
+    if (!box_fits(origin, dims, voxel))
+        return fail(VICP_ERR_INVALID_ARG, "the grid reaches beyond +-1e18: float32 squared distances could overflow");
     h.inv = 1.0f / voxel;
     h.voxel = voxel;
     h.V = V;
@@ -800,6 +831,47 @@ float unordered(uint32_t k)
     float f;
     memcpy(&f, &u, 4);
     return f;
+}
+
+// The count (Alg. 1 GPU part) under the grid's count schedule (the
+// packed-hash ablation always runs 256 points per block).
+void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz, bool packed, hipStream_t s)
+{
+    ProfScope ps("count", s, false);
+    const BlockJob* jobs = g->jobs_q;
+    int nj = g->njobs_q, bs = 256;
+    if (!packed && g->count_block == 512) {
+        jobs = g->jobs_q512;
+        nj = g->njobs_q512;
+        bs = 512;
+    } else if (!packed && g->count_block == 1024) {
+        jobs = g->jobs_q1024;
+        nj = g->njobs_q1024;
+        bs = 1024;
+    }
+    launch_count(qx, qy, qz, g->d_pd, jobs, nj, bs, g->hist, g->vox, g->rank, g->err, packed, s);
+}
+
+// `rings` dilation rings (Alg. 3) under the grid's dilation schedule: all in
+// one launch on LDS tiles (1 to 4 rings), or one launch per ring.  Running it
+// again on the same grid rewrites the same words.
+void queue_dilate(vicp_grid* g, int rings, hipStream_t s, bool cap)
+{
+    if (rings < 1) return;
+    if (rings <= kFusedRings && g->dil_fused) {
+        ProfScope ps("dilate", s, cap);
+        launch_dilate_fused(g->d_pd, g->jobs_t[g->dil_shape], g->njobs_t[g->dil_shape], rings, g->dil_shape, g->vm,
+                            g->dir, s);
+        return;
+    }
+    uint32_t* a = g->dil_a;
+    uint32_t* b = g->dil_b;
+    for (int r = 1; r <= rings; ++r) {
+        ProfScope ps("dilate_ring", s, cap);
+        launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, g->ring_block, g->hist, g->off, g->vm, g->dir,
+                           r == 1 ? nullptr : a, r == rings ? nullptr : b, r == 1, r == rings, s);
+        std::swap(a, b);
+    }
 }
 
 // Fills (or refills) a grid from target coordinates: bounding box (the one
@@ -878,11 +950,14 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         g->vm_words = words;
         std::vector<int64_t> vcount(B);
         for (int p = 0; p < B; ++p) vcount[p] = pairs[p].V;
-        std::vector<BlockJob> jv, jt;
+        std::vector<BlockJob> jv, jt[kDilateShapes];
         make_jobs(vcount, 256, jv, nullptr);
-        std::vector<int64_t> tcount(B);
-        for (int p = 0; p < B; ++p) tcount[p] = dilate_tiles(pairs[p].dims[0], pairs[p].dims[1], pairs[p].dims[2]);
-        make_jobs(tcount, 1, jt, nullptr);
+        for (int sh = 0; sh < kDilateShapes; ++sh) {
+            std::vector<int64_t> tcount(B);
+            for (int p = 0; p < B; ++p)
+                tcount[p] = dilate_tiles(sh, pairs[p].dims[0], pairs[p].dims[1], pairs[p].dims[2]);
+            make_jobs(tcount, 1, jt[sh], nullptr);
+        }
         const int tiles = scan_tiles(Vt);
         bool ok = true;
         g->hist = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
@@ -890,7 +965,8 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         g->vm = (uint32_t*)g->take(sizeof(uint32_t) * words, s, g->vbufs, ok);
         g->dir = (uint2*)g->take(sizeof(uint2) * Vt, s, g->vbufs, ok);
         g->jobs_v = (BlockJob*)g->take(sizeof(BlockJob) * jv.size(), s, g->vbufs, ok);
-        g->jobs_t = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jt.size(), 1), s, g->vbufs, ok);
+        for (int sh = 0; sh < kDilateShapes; ++sh)
+            g->jobs_t[sh] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jt[sh].size(), 1), s, g->vbufs, ok);
         g->scan_status = (unsigned long long*)g->take(sizeof(unsigned long long) * tiles, s, g->vbufs, ok);
         g->scan_ticket = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->vbufs, ok);
         g->dil_a = (uint32_t*)g->take(sizeof(uint32_t) * Vt, s, g->vbufs, ok);
@@ -902,9 +978,12 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         }
         g->njobs_v = (int)jv.size();
         VICP_HIP(hipMemcpyAsync(g->jobs_v, jv.data(), sizeof(BlockJob) * jv.size(), hipMemcpyHostToDevice, s));
-        g->njobs_t = (int)jt.size();
-        if (!jt.empty())
-            VICP_HIP(hipMemcpyAsync(g->jobs_t, jt.data(), sizeof(BlockJob) * jt.size(), hipMemcpyHostToDevice, s));
+        for (int sh = 0; sh < kDilateShapes; ++sh) {
+            g->njobs_t[sh] = (int)jt[sh].size();
+            if (!jt[sh].empty())
+                VICP_HIP(hipMemcpyAsync(g->jobs_t[sh], jt[sh].data(), sizeof(BlockJob) * jt[sh].size(),
+                                        hipMemcpyHostToDevice, s));
+        }
     }
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
@@ -912,10 +991,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
     bool packed = g->packed_hash;
     for (int p = 0; p < B && packed; ++p) packed = count_packed_fits(pairs[p].V);
-    {
-        ProfScope ps("count", s, false);
-        launch_count(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err, packed, s);
-    }
+    queue_count(g, qx, qy, qz, packed, s);
     if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
         uint32_t herr = 0;
         VICP_HIP(hipMemcpyAsync(&herr, g->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1044,15 +1120,19 @@ int build_grid_impl(const float* qx, const float* qy, const float* qz, const int
     };
     std::vector<int64_t> ncount(npairs);
     for (int p = 0; p < npairs; ++p) ncount[p] = pairs[p].n;
-    std::vector<BlockJob> jq, jq8;
+    std::vector<BlockJob> jq, jq8, jq512, jq1024;
     make_jobs(ncount, 256, jq, nullptr);
     make_jobs(ncount, 2048, jq8, nullptr);
+    make_jobs(ncount, 512, jq512, nullptr);
+    make_jobs(ncount, 1024, jq1024, nullptr);
     bool ok = true;
     g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned, ok);
     g->box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * std::max<size_t>(jq8.size(), 1), s, g->owned, ok);
     g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned, ok);
     g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned, ok);
     g->jobs_q8 = (BlockJob*)g->take(sizeof(BlockJob) * jq8.size(), s, g->owned, ok);
+    g->jobs_q512 = (BlockJob*)g->take(sizeof(BlockJob) * jq512.size(), s, g->owned, ok);
+    g->jobs_q1024 = (BlockJob*)g->take(sizeof(BlockJob) * jq1024.size(), s, g->owned, ok);
     g->vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
     g->rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
     g->slots = (uint32_t*)g->take(sizeof(uint32_t) * (nt + 4), s, g->owned, ok);   // +4: rank_in reads 16-byte chunks
@@ -1060,12 +1140,18 @@ int build_grid_impl(const float* qx, const float* qy, const float* qz, const int
     if (!ok) return bail(fail(VICP_ERR_OOM, "allocation failed"));
     g->njobs_q = (int)jq.size();
     g->njobs_q8 = (int)jq8.size();
+    g->njobs_q512 = (int)jq512.size();
+    g->njobs_q1024 = (int)jq1024.size();
     g->h_jobs_q8 = jq8;
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);   // target fields only; the grid fields follow the bounding box
     if (hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(g->jobs_q, jq.data(), sizeof(BlockJob) * jq.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(g->jobs_q8, jq8.data(), sizeof(BlockJob) * jq8.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(g->jobs_q8, jq8.data(), sizeof(BlockJob) * jq8.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(g->jobs_q512, jq512.data(), sizeof(BlockJob) * jq512.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(g->jobs_q1024, jq1024.data(), sizeof(BlockJob) * jq1024.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
         return bail(fail(VICP_ERR_HIP, "upload failed"));
     int rc = grid_fill(g, qx, qy, qz, s);
     if (rc) return bail(rc);
@@ -1207,21 +1293,7 @@ int vicp_dilate(vicp_grid* g, int32_t rings, hipStream_t s)
     if (rings < 0 || rings > g->pad) return fail(VICP_ERR_INVALID_ARG, "rings must be in [0, pad_rings]");
     g->dilated = true;
     g->rings_applied = rings;
-    uint32_t* a = g->dil_a;
-    uint32_t* b = g->dil_b;
-    const bool cap = capturing(s);
-    if (rings >= 1 && rings <= kFusedRings) {
-        // every ring in one launch, on LDS tiles with an L-voxel halo
-        ProfScope ps("dilate", s, cap);
-        launch_dilate_fused(g->d_pd, g->jobs_t, g->njobs_t, rings, g->hist, g->off, g->vm, g->dir, s);
-    } else {
-        for (int r = 1; r <= rings; ++r) {
-            ProfScope ps("dilate_ring", s, cap);
-            launch_dilate_ring(g->d_pd, g->jobs_v, g->njobs_v, 256, g->hist, g->off, g->vm, g->dir,
-                               r == 1 ? nullptr : a, r == rings ? nullptr : b, r == 1, r == rings, s);
-            std::swap(a, b);
-        }
-    }
+    queue_dilate(g, rings, s, capturing(s));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("dilate: ") + hipGetErrorString(e));
     return VICP_OK;
@@ -1251,7 +1323,8 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
     for (int i = 0; i < 12 * g->B; ++i) rt64[i] = (double)Rt[i];
     queue_start(g, rt64.data(), px, py, pz, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-    queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, false);
+    if (!queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, false))
+        return fail(VICP_ERR_INVALID_ARG, "too many pairs for the global search");
     {
         ProfScope ps("fb_finalize", s, cap);
         launch_fb_finalize(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->fb_key, nn_idx, nn_d2, g->flags, s);
@@ -1410,8 +1483,9 @@ int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const
                        (int32_t)njobs256, base);
     launch_nns_local(pd, jobs, (int)njobs, g->nns_block, g->nns_lpq, false, false, px, py, pz, nullptr, st, g->dir,
                      g->qs4, nn_idx, nn_d2, cnt, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, s);
-    launch_fallback(pd, 1, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, st, cnt, fb_list, fb_key, nullptr, 0,
-                    nullptr, nullptr, nullptr, nullptr, s);
+    if (!launch_fallback(pd, 1, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, st, cnt, fb_list, fb_key, nullptr, 0,
+                         nullptr, nullptr, nullptr, nullptr, s))
+        return fail(VICP_ERR_INVALID_ARG, "global-search grid out of range");
     launch_fb_finalize(pd, jobs256, (int)njobs256, fb_key, nn_idx, nn_d2, cnt + 1, s);
     if (n_fallback) launch_copy_fb(cnt, n_fallback, 1, s);
     hipError_t e = hipGetLastError();
@@ -1451,6 +1525,11 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     const bool direct = o->layout != 0;
     if (direct && all_global) return fail(VICP_ERR_INVALID_ARG, "global_only and the direct layout exclude each other");
     if (direct && !g->direct_ready) return fail(VICP_ERR_STATE, "no direct layout: call vicp_direct_build first");
+    if ((o->nn_idx == nullptr) != (o->nn_d2 == nullptr))
+        return fail(VICP_ERR_INVALID_ARG, "nn_idx and nn_d2 are given together or not at all");
+    int32_t* out_idx = o->nn_idx;
+    float* out_d2 = o->nn_d2;
+    constexpr const char* kTooMany = "too many pairs for the global search";
     queue_start(g, Rt_io, px, py, pz, s);
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
@@ -1458,7 +1537,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                                       (uintptr_t)g->search_mode,
                                       (uintptr_t)g->sort_src, (uintptr_t)all_global, (uintptr_t)direct,
                                       (uintptr_t)g->dblk,
-                                      (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz};
+                                      (uintptr_t)g->qx, (uintptr_t)g->qy, (uintptr_t)g->qz,
+                                      (uintptr_t)out_idx, (uintptr_t)out_d2};
         uint64_t eb;
         memcpy(&eb, &eps, 8);
         key.push_back((uintptr_t)eb);
@@ -1474,8 +1554,10 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                 VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
                 t_capture_events = attempt == 0 ? &g->gevents : nullptr;
                 if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
-                for (int k = 0; k < K; ++k)
-                    queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global, direct);
+                bool queued = true;
+                for (int k = 0; k < K && queued; ++k)
+                    queued = queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global, direct,
+                                             out_idx, out_d2);
                 t_capture_events = nullptr;
                 hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
                 hipError_t e = ec;
@@ -1483,10 +1565,12 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
                     e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
                     (void)hipGraphDestroy(graph);
                 }
-                if (e != hipSuccess) {
+                if (e != hipSuccess || !queued) {
                     (void)hipGetLastError();
+                    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
                     g->gexec = nullptr;
                     prof_return(g->gevents);
+                    if (!queued) return fail(VICP_ERR_INVALID_ARG, kTooMany);
                     why = hipGetErrorString(e);
                 }
             }
@@ -1499,7 +1583,8 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
         const bool cap = capturing(s);
         if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
         for (int k = 0; k < K; ++k)
-            queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global, direct);
+            if (!queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global, direct, out_idx, out_d2))
+                return fail(VICP_ERR_INVALID_ARG, kTooMany);
     }
     VICP_HIP(hipMemcpyAsync(g->h_res, g->res, g->res_bytes, hipMemcpyDeviceToHost, s));
     VICP_HIP(hipStreamSynchronize(s));
@@ -1558,7 +1643,8 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
-    queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap, false);
+    if (!queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap, false))
+        return fail(VICP_ERR_INVALID_ARG, "too many pairs for the global search");
     return VICP_OK;
 }
 
@@ -1680,12 +1766,155 @@ int vicp_grid_free(vicp_grid* g)
     return VICP_OK;
 }
 
-// The search schedule (threads per block, lanes per query, source bucketing
-// on or off, blocks of the global search) never changes a result; this times
-// the candidates on the caller's data at the identity pose and keeps the
-// fastest.  The bucketing pass serves `searches_per_plan` searches (1 for a
-// single search, the iteration count for a registration), so its time is
-// charged at that rate.
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuning
+namespace {
+
+// Every schedule choice of a grid (none changes a correspondence, a count or
+// a grid word).
+struct Sched {
+    int count_block, dil_fused, dil_shape, ring_block, nns_block, nns_lpq, sort_src, fb_grid, search_mode;
+};
+
+Sched sched_of(const vicp_grid* g)
+{
+    return Sched{g->count_block, g->dil_fused ? 1 : 0, g->dil_shape, g->ring_block, g->nns_block, g->nns_lpq,
+                 g->sort_src ? 1 : 0, g->fb_grid, g->search_mode};
+}
+
+void apply_sched(vicp_grid* g, const Sched& c)
+{
+    g->count_block = c.count_block;
+    g->dil_fused = c.dil_fused != 0;
+    g->dil_shape = c.dil_shape;
+    g->ring_block = c.ring_block;
+    g->nns_block = c.nns_block;
+    g->nns_lpq = c.nns_lpq;
+    g->sort_src = c.sort_src != 0;
+    g->fb_grid = c.fb_grid;
+    g->search_mode = c.search_mode;
+    g->drop_graph();
+}
+
+bool sched_valid(const Sched& c)
+{
+    auto in = [](int v, std::initializer_list<int> ok) { return std::find(ok.begin(), ok.end(), v) != ok.end(); };
+    return in(c.count_block, {256, 512, 1024}) && in(c.dil_fused, {0, 1}) && c.dil_shape >= 0 &&
+           c.dil_shape < kDilateShapes && in(c.ring_block, {64, 128, 256}) && in(c.nns_block, {128, 256, 512}) &&
+           in(c.nns_lpq, {1, 2, 4, 8}) && in(c.sort_src, {0, 1}) && c.fb_grid >= 1 && c.fb_grid <= 65536 &&
+           in(c.search_mode, {0, 1}) && (c.search_mode == 0 || c.nns_lpq >= 4);
+}
+
+// Stored schedules by shape: in this process, and in the file named by
+// VICP_AUTOTUNE_CACHE when set (one line per shape: key, tab, nine numbers).
+std::mutex g_tune_mu;
+std::map<std::string, Sched> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("VICP_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    std::string line;
+    char buf[4096];
+    while (fgets(buf, sizeof buf, f)) {
+        line += buf;
+        if (line.empty() || line.back() != '\n') continue;   // a key longer than the buffer
+        const size_t tab = line.find('\t');
+        Sched c{};
+        if (tab != std::string::npos &&
+            sscanf(line.c_str() + tab + 1, "%d %d %d %d %d %d %d %d %d", &c.count_block, &c.dil_fused, &c.dil_shape,
+                   &c.ring_block, &c.nns_block, &c.nns_lpq, &c.sort_src, &c.fb_grid, &c.search_mode) == 9 &&
+            sched_valid(c))
+            g_tune[line.substr(0, tab)] = c;
+        line.clear();
+    }
+    fclose(f);
+}
+
+void tune_store(const std::string& key, const Sched& c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = c;
+    const char* path = getenv("VICP_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE* f = fopen(path, "a")) {
+        fprintf(f, "%s\t%d %d %d %d %d %d %d %d %d\n", key.c_str(), c.count_block, c.dil_fused, c.dil_shape,
+                c.ring_block, c.nns_block, c.nns_lpq, c.sort_src, c.fb_grid, c.search_mode);
+        fclose(f);
+    }
+}
+
+bool tune_find(const std::string& key, Sched* out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+// The shape a schedule is stored under: the device's architecture and CU
+// count, and per pair the point counts and grid dimensions; the rings, the
+// padding, the grid kind and the searches per bucketing pass.
+std::string tune_key(const vicp_grid* g, const int64_t* m, int32_t spp)
+{
+    std::string k;
+    int devi = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&devi) == hipSuccess && hipGetDeviceProperties(&prop, devi) == hipSuccess)
+        k += std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    else
+        (void)hipGetLastError();
+    k += " L" + std::to_string(g->rings_applied) + " P" + std::to_string(g->pad) + (g->fixed ? " F" : " B") + " S" +
+         std::to_string(spp);
+    for (int p = 0; p < g->B; ++p) {
+        const PairHost& h = g->pairs[p];
+        k += " " + std::to_string(h.n) + "," + std::to_string(m[p]) + "," + std::to_string(h.dims[0]) + "x" +
+             std::to_string(h.dims[1]) + "x" + std::to_string(h.dims[2]);
+    }
+    return k;
+}
+
+// A global-search load for timing: the first max(256, m/64) source points of
+// each pair listed as unresolved queries.
+__global__ void k_synthetic_misses(const PairDev* __restrict__ pd, int npairs, int32_t* __restrict__ fb_count,
+                                   uint32_t* __restrict__ fb_list, unsigned long long* __restrict__ fb_key)
+{
+    const int p = blockIdx.x;
+    if (p >= npairs) return;
+    const PairDev& P = pd[p];
+    const int64_t F = min(P.m, max((int64_t)256, P.m / 64));
+    if (threadIdx.x == 0) fb_count[p] = (int32_t)F;
+    for (int64_t i = threadIdx.x; i < F; i += blockDim.x) {
+        fb_list[P.p_base + i] = (uint32_t)i;
+        fb_key[P.p_base + i] = ~0ull;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vicp_autotune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = true;   // the file is not read again in this process
+    return VICP_OK;
+}
+
+// Times the schedule choices on the caller's data and keeps the fastest; see
+// the header for what is timed and how.  None of them changes a result, so
+// the grid is left as it was (re-running the count or the dilation rewrites
+// the same words).
 int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
                   int32_t searches_per_plan, hipStream_t s)
 {
@@ -1698,6 +1927,12 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     if (rc) return rc;
     if (g->m_total == 0) return VICP_OK;
     if (!px || !py || !pz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    const std::string key = tune_key(g, m_per_pair, searches_per_plan);
+    Sched cached{};
+    if (tune_find(key, &cached)) {
+        apply_sched(g, cached);
+        return VICP_OK;
+    }
     std::vector<double> rt(12 * g->B, 0.0);
     for (int p = 0; p < g->B; ++p) rt[12 * p] = rt[12 * p + 4] = rt[12 * p + 8] = 1.0;
     queue_start(g, rt.data(), px, py, pz, s);
@@ -1707,14 +1942,11 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     // one sample is kBurst back-to-back runs (launch jitter averages out);
     // the figure is the best of three samples after one untimed
     constexpr int kBurst = 8;
-    auto timed = [&](auto&& work) -> float {
+    auto timed_raw = [&](auto&& work) -> float {
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             (void)hipEventRecord(a, s);
-            for (int r = 0; r < kBurst; ++r) {
-                launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
-                work();
-            }
+            for (int r = 0; r < kBurst; ++r) work();
             (void)hipEventRecord(b, s);
             (void)hipEventSynchronize(b);
             float ms = 0.0f;
@@ -1723,9 +1955,58 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
         }
         return best;
     };
+    auto timed = [&](auto&& work) -> float {
+        return timed_raw([&] {
+            launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+            work();
+        });
+    };
     // a later candidate replaces the best only when it is clearly faster, so
     // that near-ties resolve the same way from run to run
     constexpr float kMargin = 0.99f;
+    // (1) the count's block size: the histogram is cleared and recounted (the
+    // counts come out the same; the slots it hands out are only used by a
+    // build, which recounts)
+    if (!g->packed_hash) {
+        float best = 1e30f;
+        int best_cb = g->count_block;
+        for (int cb : {256, 512, 1024}) {
+            g->count_block = cb;
+            const float t = timed_raw([&] {
+                launch_fill_u32(g->hist, 0u, g->V_total, s);
+                queue_count(g, g->qx, g->qy, g->qz, false, s);
+            });
+            if (t < kMargin * best) {
+                best = t;
+                best_cb = cb;
+            }
+        }
+        g->count_block = best_cb;
+    }
+    // (2) the dilation, on a grid dilated with 1 to 4 rings (re-running it
+    // rewrites the same words)
+    const int L = g->rings_applied;
+    if (g->dilated && L >= 1 && L <= kFusedRings) {
+        float best = 1e30f;
+        Sched bs = sched_of(g);
+        for (int fused = 1; fused >= 0; --fused)
+            for (int v = 0; v < (fused ? kDilateShapes : 3); ++v) {
+                g->dil_fused = fused != 0;
+                if (fused)
+                    g->dil_shape = v;
+                else
+                    g->ring_block = 64 << v;
+                const float t = timed_raw([&] { queue_dilate(g, L, s, true); });
+                if (t < kMargin * best) {
+                    best = t;
+                    bs = sched_of(g);
+                }
+            }
+        g->dil_fused = bs.dil_fused != 0;
+        g->dil_shape = bs.dil_shape;
+        g->ring_block = bs.ring_block;
+    }
+    // (3) the search in its registration form at the identity pose
     const float plan_ms = timed([&] { queue_plan(g, px, py, pz, s, true); });
     int best_bs = 256, best_lpq = 4, best_fg = g->fb_grid;
     bool best_sorted = true;
@@ -1736,6 +2017,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
                 g->nns_block = bs;
                 g->nns_lpq = lpq;
                 g->sort_src = sorted != 0;
+                g->search_mode = 0;
                 const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
                                 (sorted ? plan_ms / (float)searches_per_plan : 0.0f);
                 if (t < kMargin * best) {
@@ -1759,13 +2041,26 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
         else
             g->search_mode = 0;
     }
-    best = 1e30f;
-    for (int fg : {64, 128, 256, 512, 1024}) {
-        g->fb_grid = fg;
-        const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); });
-        if (t < kMargin * best) {
-            best = t;
-            best_fg = fg;
+    // (4) the global search's blocks: the fold every iteration runs, plus a
+    // listed-query load once per bucketing pass
+    {
+        const int tab = table_of(g->nns_block / g->nns_lpq);
+        best = 1e30f;
+        for (int fg : {64, 128, 256, 512, 1024}) {
+            g->fb_grid = fg;
+            const float t0 = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); });
+            const float t1 = timed_raw([&] {
+                hipLaunchKernelGGL(k_synthetic_misses, dim3(g->B), dim3(256), 0, s, g->d_pd, g->B, g->fb_count,
+                                   g->fb_list, g->fb_key);
+                (void)launch_fallback(g->d_pd, g->B, fg, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count,
+                                      g->fb_list, g->fb_key, g->fjobs[tab], g->nfjobs[tab], g->npart, g->ctr,
+                                      g->fpart, g->fctr, s);
+            });
+            const float t = t0 + t1 / (float)searches_per_plan;
+            if (t < kMargin * best) {
+                best = t;
+                best_fg = fg;
+            }
         }
     }
     g->fb_grid = best_fg;
@@ -1775,6 +2070,35 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+    VICP_HIP(hipStreamSynchronize(s));
+    tune_store(key, sched_of(g));
+    return VICP_OK;
+}
+
+int vicp_get_build_schedule(const vicp_grid* g, int32_t* count_block, int32_t* dilate_fused, int32_t* dilate_tile,
+                            int32_t* ring_block)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (count_block) *count_block = g->count_block;
+    if (dilate_fused) *dilate_fused = g->dil_fused ? 1 : 0;
+    if (dilate_tile) *dilate_tile = g->dil_shape;
+    if (ring_block) *ring_block = g->ring_block;
+    return VICP_OK;
+}
+
+int vicp_set_build_schedule(vicp_grid* g, int32_t count_block, int32_t dilate_fused, int32_t dilate_tile,
+                            int32_t ring_block)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    Sched c = sched_of(g);
+    c.count_block = count_block;
+    c.dil_fused = dilate_fused;
+    c.dil_shape = dilate_tile;
+    c.ring_block = ring_block;
+    if (!sched_valid(c))
+        return fail(VICP_ERR_INVALID_ARG, "count_block must be 256, 512 or 1024, dilate_fused 0 or 1, dilate_tile "
+                                          "0-4, ring_block 64, 128 or 256");
+    apply_sched(g, c);
     return VICP_OK;
 }
 
@@ -1829,11 +2153,24 @@ int vicp_prof_read(const char* kernel, int64_t* launches, double* total_ms)
     return VICP_OK;
 }
 
+int vicp_prof_samples(const char* kernel, double* ms, int64_t cap, int64_t* count)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    prof_flush_locked();
+    if (!kernel || cap < 0 || (cap > 0 && !ms)) return fail(VICP_ERR_INVALID_ARG, "null kernel name or output");
+    auto it = g_prof.samples.find(kernel);
+    const int64_t n = it == g_prof.samples.end() ? 0 : (int64_t)it->second.size();
+    for (int64_t i = 0; i < std::min(n, cap); ++i) ms[i] = it->second[(size_t)i];
+    if (count) *count = n;
+    return VICP_OK;
+}
+
 int vicp_prof_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     prof_flush_locked();
     g_prof.acc.clear();
+    g_prof.samples.clear();
     return VICP_OK;
 }
 

@@ -78,6 +78,30 @@ struct PairDev {
     int32_t s_pad;
 };
 
+// A padded grid box whose coordinates all lie within +-kCoordLimit keeps
+// every float32 difference and squared distance between two points inside it
+// finite (|a - b| <= 2e18 per axis, 3 (2e18)^2 = 1.2e37 < FLT_MAX), so every
+// local search has a finite best distance.
+constexpr float kCoordLimit = 1e18f;
+inline bool grid_box_fits(const float lo[3], const float hi[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(lo[a] >= -kCoordLimit && lo[a] <= kCoordLimit && hi[a] >= -kCoordLimit && hi[a] <= kCoordLimit))
+            return false;
+    return true;
+}
+
+// Work items of the global search for F listed queries of a pair over its n
+// targets: chunks of kFbQueries queries times tiles of kFbTargets targets.
+// 64-bit: F n / 2^18 passes 2^31 at about 24M points per pair.
+constexpr int kFbQueries = 256;
+constexpr int kFbTargets = 1024;
+constexpr int kFbMaxPairs = 4096;
+__host__ __device__ inline int64_t fallback_items(int64_t F, int64_t n)
+{
+    return F > 0 ? ((F + kFbQueries - 1) / kFbQueries) * ((n + kFbTargets - 1) / kFbTargets) : 0;
+}
+
 // A block's work: the pair it serves and its first item within the pair.
 struct BlockJob {
     int32_t pair;
@@ -230,8 +254,10 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, Args...
 // grid build
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd,
                  const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
+// block: target points per block (256, 512 or 1024; the packed-hash
+// ablation always takes 256); jobs must hold `block` points per entry
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd,
-                  const BlockJob* jobs, int njobs, uint32_t* hist, uint32_t* vox, uint32_t* rank,
+                  const BlockJob* jobs, int njobs, int block, uint32_t* hist, uint32_t* vox, uint32_t* rank,
                   uint32_t* err, bool packed, hipStream_t s);
 bool count_packed_fits(int64_t voxels);
 // VANICP's layout: counts every point of a voxel into cnt and copies it into
@@ -255,16 +281,20 @@ void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, u
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count, hipStream_t s);
 
-// dilation
+// dilation: one ring over jobs of 256 consecutive voxels, block = 64, 128
+// or 256 threads per job
 void launch_dilate_ring(const PairDev* pd, const BlockJob* jobs, int njobs, int block,
                         const uint32_t* hist, const uint32_t* off, uint32_t* vm, uint2* dir,
                         const uint32_t* src, uint32_t* dst, int first, int last, hipStream_t s);
 // all rings in one launch for rings <= kFusedRings, over a table of voxel
-// tiles (dilate_tiles per pair); returns false (nothing launched) otherwise
+// tiles of one of kDilateShapes shapes (dilate_tiles per pair); returns false
+// (nothing launched) otherwise.  Reads the search directory the offset scan
+// wrote, writes Mask(root) count words and the dilated voxels' entries.
 constexpr int kFusedRings = 4;
-int64_t dilate_tiles(int Dx, int Dy, int Dz);
-bool launch_dilate_fused(const PairDev* pd, const BlockJob* jobs, int njobs, int rings, const uint32_t* hist,
-                         const uint32_t* off, uint32_t* vm, uint2* dir, hipStream_t s);
+constexpr int kDilateShapes = 5;
+int64_t dilate_tiles(int shape, int Dx, int Dy, int Dz);
+bool launch_dilate_fused(const PairDev* pd, const BlockJob* jobs, int njobs, int rings, int shape, uint32_t* vm,
+                         uint2* dir, hipStream_t s);
 // VANICP's layout (single pair): copies each dilated voxel's root records
 // into its block, from the ring state (own id, root id or none per voxel)
 void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint32_t* cnt, float4* blk,
@@ -285,7 +315,8 @@ void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const 
 void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                      const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
                      const int32_t* sbig, float4* ps4, hipStream_t s);
-void launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
+// false (nothing launched) for npairs outside [1, kFbMaxPairs]
+bool launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
                      const uint32_t* fb_list, unsigned long long* fb_key, const FoldJob* fjobs, int nunits,
                      const double* part, const unsigned long long* ctr, double* fpart,
@@ -298,7 +329,7 @@ void launch_solve(const PairDev* pd, int npairs, const int32_t* fold_begin, int3
                   const unsigned long long* fb_key, const float* px, const float* py, const float* pz,
                   const float* qx, const float* qy, const float* qz, int32_t* flags, double* rmse_hist,
                   int32_t* fb_hist, int32_t* deg_hist, unsigned long long* ctr_hist, int k, int K, int early_stop,
-                  double eps, hipStream_t s);
+                  double eps, int32_t* nn_idx, float* nn_d2, hipStream_t s);
 // the same with the poses of up to kInlinePairs pairs passed in the launch
 // itself (host array), so no upload precedes it
 constexpr int kInlinePairs = 8;

@@ -1,13 +1,17 @@
 """GPU parity of the differentiable loss and of the batched workload.
 
 Differentiable: per-pair loss, dL/dP and dL/dxi of the HIP path against the
-float64 CPU oracle on the same correspondences, and against float64 central
-finite differences (h = 1e-6, 8 random directions in the joint (P, xi) space,
-correspondences frozen).  Batched: pairs of the 64-pair workload (uneven
-sizes, both surfaces) registered in one launch sequence, each against the
-oracle run on that pair alone.
+float64 CPU oracle on the same correspondences (every pair of the 16 x 40k
+workload, dL/dP element by element), and against float64 central finite
+differences (h = 1e-6, 8 random directions in the joint (P, xi) space,
+correspondences frozen; on small pairs and on a full 40k pair).  Batched:
+all 64 pairs of the 64-pair workload (uneven sizes, both surfaces) registered
+in one launch sequence under the autotuned schedule, each against the oracle
+run on that pair alone, with the last iteration's correspondences compared
+index for index.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -21,8 +25,10 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2512_04996_amd.api import build_grid, build_grid_batched  # noqa: E402
+from paper_2512_04996_amd.api import autotune_cache_clear, build_grid, build_grid_batched  # noqa: E402
 from paper_2512_04996_amd.autograd import p2p_loss  # noqa: E402
+
+oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
 
 
 def dev(a):
@@ -119,31 +125,74 @@ def test_p2p_zero_at_alignment_and_backward_scale():
     assert torch.allclose(gx, 2.5 * x1.grad, rtol=1e-12, atol=0)
 
 
-def test_diff_workload_full_size_sampled():
+def test_diff_workload_every_pair():
+    # every pair of the 16 x 40k workload: loss, dL/dxi, and dL/dP element by
+    # element.  dL/dP is a float64 value rounded to float32: within one
+    # float32 ulp of the oracle's float64 value, plus 1e-12 of the largest
+    # entry for the float64 rounding of residuals that cancel (both sides sum
+    # in float64, in different orders); and max |delta| / max |dP| <= 1e-7
     dpairs, xi = synth.config("diff_16x40k")
     L, dP, dxi = _gpu_loss_grad(dpairs, xi)
-    for b in (0, 7, 15):
-        P = dpairs[b]
+    for b, P in enumerate(dpairs):
         og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
         loss, dPo, dxio, _ = oracle.p2p(og, P.q, P.p, xi[b])
-        assert abs(L[b] - loss) <= 1e-12 * loss
-        assert np.linalg.norm(dP[b] - dPo) <= 1e-7 * np.linalg.norm(dPo)
-        assert np.abs(dxi[b] - dxio).max() <= 1e-10 * np.abs(dxio).max()
+        assert abs(L[b] - loss) <= 1e-12 * loss, b
+        delta = np.abs(dP[b].astype(np.float64) - dPo)
+        assert (delta <= 2.0 ** -23 * np.abs(dPo) + 1e-12 * np.abs(dPo).max()).all(), (b, float(delta.max()))
+        assert delta.max() <= 1e-7 * np.abs(dPo).max(), b
+        assert np.abs(dxi[b] - dxio).max() <= 1e-10 * np.abs(dxio).max(), b
 
 
-def test_batched_workload_sampled_pairs():
+def test_diff_workload_full_pair_by_finite_differences():
+    # 8 random directions in the joint (P, xi) space of one full 40k pair
+    dpairs, xi = synth.config("diff_16x40k")
+    sel = [3]
+    L, dP, dxi = _gpu_loss_grad([dpairs[b] for b in sel], xi[sel])
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    P = dpairs[sel[0]]
+    og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 2), 2)
+    _, _, _, idx = oracle.p2p(og, P.q, P.p, xi[sel[0]])        # correspondences, frozen
+    p64 = P.p.astype(np.float64)
+    scale = math.sqrt((dP[0].astype(np.float64) ** 2).sum() + (dxi[0] ** 2).sum())
+    for _ in range(8):
+        u = rng.standard_normal(p64.shape)
+        w = rng.standard_normal(6)
+        nrm = math.sqrt((u * u).sum() + (w * w).sum())
+        u, w = u / nrm, w / nrm
+        fp = oracle.p2p_loss_fixed(P.q, p64 + h * u, idx, xi[sel[0]] + h * w)
+        fm = oracle.p2p_loss_fixed(P.q, p64 - h * u, idx, xi[sel[0]] - h * w)
+        fd = (fp - fm) / (2 * h)
+        an = float((dP[0].astype(np.float64) * u).sum() + (dxi[0] * w).sum())
+        assert abs(fd - an) <= 1e-6 * scale, (fd, an)
+
+
+def test_batched_workload_every_pair():
     pairs = synth.config("batched_64")
-    sel = list(range(0, 64, 9))
     qc = dev(np.concatenate([x.q for x in pairs], 1))
     pc = dev(np.concatenate([x.p for x in pairs], 1))
+    ms = [x.m for x in pairs]
     gb = build_grid_batched(qc, [x.n for x in pairs], [x.voxel for x in pairs], 3).dilate(3)
-    res = gb.register(pc, 30, m_per_pair=[x.m for x in pairs], use_graph=True)
-    for b in sel:
-        P = pairs[b]
+    autotune_cache_clear()
+    gb.autotune(pc, m_per_pair=ms, searches_per_plan=30)   # the workload's autotuned schedule
+    res = gb.register(pc, 30, m_per_pair=ms, use_graph=True, correspondences=True)
+    idx_all = res.nn_idx.cpu().numpy()
+    d2_all = res.nn_d2.cpu().numpy()
+    start = 0
+    fallbacks = 0
+    for b, P in enumerate(pairs):
         hist, off, vm = gb.export(b)
         og = oracle.dilate(oracle.build_grid(P.q, P.voxel, 3), 3)
         assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm), b
         ref = oracle.register(P.q, P.p, P.voxel, 3, 30)
+        assert int(res.iters[b]) == ref.iters == 30, b
         assert list(res.fallbacks[b]) == list(ref.fallbacks), b
+        np.testing.assert_allclose(res.rmse[b], ref.rmse, rtol=1e-9, atol=0)
         assert rot_angle(res.Rt[b][:9], ref.Rt[:9]) <= 1e-5, b
         assert np.linalg.norm(res.Rt[b][9:] - ref.Rt[9:]) <= 1e-6 * P.extent, b
+        sl = slice(start, start + P.m)
+        assert np.array_equal(idx_all[sl], ref.nn_idx), b
+        assert np.array_equal(d2_all[sl].view(np.uint32), ref.nn_d2.view(np.uint32)), b
+        start += P.m
+        fallbacks += int(ref.fallbacks[0])
+    assert fallbacks > 0                       # some pairs start with global searches

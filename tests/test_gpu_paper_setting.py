@@ -24,6 +24,7 @@ from paper_2512_04996_amd._lib import ERR_INVALID_ARG, VicpError  # noqa: E402
 from paper_2512_04996_amd.api import build_grid_fixed  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
 ROT_TOL = 1e-5
 T_TOL = 1e-6
 
@@ -43,7 +44,8 @@ def small_room():
                                        "paper_room_30k")
 
 
-CASES = {"paper_bunny_40k": lambda: synth.config("paper_bunny_40k"), "paper_room_30k": small_room}
+CASES = {"paper_bunny_40k": lambda: synth.config("paper_bunny_40k"), "paper_room_30k": small_room,
+         "paper_room_226k": lambda: synth.config("paper_room_226k")}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -64,15 +66,28 @@ def test_fixed_grid_and_dilation_bit_exact(name):
     assert desc["static_bytes"] / 2 ** 20 == t["static_mb"]          # Table 1 note 1: 0.03125 MB
 
 
+_REFS = {}
+
+
+def _paper_ref(name, P):
+    if name not in _REFS:
+        o, d = P.meta["grid_origin"], P.meta["grid_dims"]
+        _REFS[name] = oracle.register_fixed(P.q, P.p, o, P.voxel, d, P.rings, P.iters, P.meta["rmse_eps"], True)
+    return _REFS[name]
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_paper_setting_registration_matches_oracle(name, use_graph):
     P = CASES[name]()
     o, d = P.meta["grid_origin"], P.meta["grid_dims"]
     g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings).dilate(P.rings)
-    res = g.register(dev(P.p), P.iters, rmse_eps=P.meta["rmse_eps"], early_stop=True, use_graph=use_graph)
-    ref = oracle.register_fixed(P.q, P.p, o, P.voxel, d, P.rings, P.iters, P.meta["rmse_eps"], True)
+    res = g.register(dev(P.p), P.iters, rmse_eps=P.meta["rmse_eps"], early_stop=True, use_graph=use_graph,
+                     correspondences=True)
+    ref = _paper_ref(name, P)
     assert int(res.iters[0]) == ref.iters and ref.iters < P.iters
+    assert np.array_equal(res.nn_idx.cpu().numpy(), ref.nn_idx)
+    assert np.array_equal(res.nn_d2.cpu().numpy().view(np.uint32), ref.nn_d2.view(np.uint32))
     assert list(res.fallbacks[0]) == list(ref.fallbacks)
     np.testing.assert_allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
     assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
