@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--schedule", default="auto",
                     help="search schedule: 'auto' (tuned on this workload first) or "
                          "'BLOCK,LANES,SORT,FALLBACK_GRID[,SEARCH_MODE]', e.g. 128,2,0,64")
+    ap.add_argument("--build-schedule", default=None,
+                    help="with a given --schedule: 'COUNT_BLOCK,DILATE_FUSED,DILATE_TILE,RING_BLOCK', e.g. 256,1,0,256")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
@@ -100,6 +102,9 @@ def main():
         vals = [int(x) for x in a.schedule.split(",")]
         bs, lpq, srt, fg = vals[:4]
         g.set_schedule(bs, lpq, bool(srt), fg, vals[4] if len(vals) > 4 else 0)
+        if a.build_schedule:
+            cb, fu, ti, rb = (int(x) for x in a.build_schedule.split(","))
+            g.set_build_schedule(cb, bool(fu), ti, rb)
     schedule = g.schedule
     tf = lambda b: "true" if b else "false"
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "

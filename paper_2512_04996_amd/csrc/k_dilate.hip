@@ -62,108 +62,146 @@ __global__ __launch_bounds__(BS) void k_dilate_ring(const PairDev* __restrict__ 
 }
 
 // All L rings in one launch (L <= kFusedRings): each block takes a tile of
-// TX x TY x TZ voxels plus an L-voxel halo into LDS, runs the L synchronous
-// rings there (ring r is exact on the region shrunk by r, which contains every
-// voxel it needs from ring r - 1), and writes the last ring's result for its
-// tile.  Voxels outside the grid stay "none" and are never dilated, as in the
-// per-ring form (only in-bounds neighbours count).
+// TX x TY x TZ voxels plus an L-voxel halo (the loaded region, EX x EY x EZ),
+// runs the L synchronous rings there (ring r is exact on the region shrunk by
+// r, which contains every voxel it needs from ring r - 1), and writes the
+// last ring's result for its tile.  Voxels outside the grid stay "none" and
+// are never dilated, as in the per-ring form (only in-bounds neighbours
+// count).
 //
 // The halo is loaded as search-directory entries (start of the voxel's points,
 // count), which the offset scan wrote for every voxel: the count tells an
 // occupied voxel, the start gives a voxel's segment offset back
 // (off[g] = start + 2g), and a root, which always lies inside the loaded
 // region, has its entry in LDS already, so no load waits on the rings.  The
-// ring state is the root's position in the loaded region (LDS element
-// index), whose order is the order of the voxel ids inside the grid (both
-// are z-major, then y, then x), so the lowest-id rule is unchanged.  Entries
-// of voxels that another block dilates while this one loads them carry the
-// mask bit and read as empty, as the count word 0 they replace does.
+// ring state is the root's position in the loaded region (element index
+// e = (ez EY + ey) EX + ex), whose order is the order of the voxel ids inside
+// the grid (both are z-major, then y, then x), so the lowest-id rule is
+// unchanged.  Entries of voxels that another block dilates while this one
+// loads them carry the mask bit and read as empty, as the count word 0 they
+// replace does.
+//
+// Each thread owns whole columns (all EZ elements of one (ex, ey)): the
+// column's coordinates and bounds are worked out once, its states live in
+// registers (its z neighbours are its own previous values), and only the
+// four x / y neighbours of each element come from LDS.
 template <int R, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_dilate_fused(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                       uint32_t* __restrict__ vm, uint2* __restrict__ dir)
 {
     constexpr int BS = 256;
-    constexpr int EX = TX + 2 * R, EY = TY + 2 * R, EZ = TZ + 2 * R, NE = EX * EY * EZ;
+    constexpr int EX = TX + 2 * R, EY = TY + 2 * R, EZ = TZ + 2 * R;
+    constexpr int NC = EX * EY, NE = NC * EZ;
+    constexpr int CPT = (NC + BS - 1) / BS;   // columns per thread
     static_assert(NE < 0xFFFF, "element indices fit 16 bits");
-    constexpr uint16_t kNone16 = 0xFFFF;
+    constexpr uint32_t kNone32 = 0xFFFFu;
     __shared__ uint2 dl[NE];
-    __shared__ uint16_t s0[NE], s1[NE];
-    const BlockJob job = jobs[blockIdx.x];
+    __shared__ uint16_t sb[2][NE];
+    // tiles of one slab of the grid per XCD: the halos neighbouring tiles
+    // share then sit in the same L2
+    const BlockJob job = jobs[xcd_slab((int)blockIdx.x, (int)gridDim.x)];
     const PairDev& P = pd[job.pair];
     const int Dx = P.Dx, Dy = P.Dy, Dz = P.Dz;
     const int ntx = (Dx + TX - 1) / TX, nty = (Dy + TY - 1) / TY;
     const int tile = job.start;
     const int bx = (tile % ntx) * TX, by = ((tile / ntx) % nty) * TY, bz = (tile / (ntx * nty)) * TZ;
     const int64_t vb = P.v_base;
-    auto inside = [&](int x, int y, int z) { return x >= 0 && x < Dx && y >= 0 && y < Dy && z >= 0 && z < Dz; };
-    // every entry load in flight before the first LDS store (a load-store
-    // loop waits for each load in turn); each element also keeps its depth
-    // inside the loaded region (-1 outside the grid), so that a ring's test
-    // is one compare: ring r updates the elements of depth >= r
-    constexpr int kLoads = (NE + BS - 1) / BS;
-    uint2 ev[kLoads];
-    int lv[kLoads];
+    const uint32_t plane = (uint32_t)Dx * (uint32_t)Dy;
+    int col[CPT], dxy[CPT];
+    uint32_t st[CPT][EZ];
+    // every entry load of the thread's columns in flight before the first
+    // LDS store (a load-store loop waits for each load in turn)
+    {
+        uint2 ev[CPT][EZ];
 #pragma unroll
-    for (int l = 0; l < kLoads; ++l) {
-        const int e = threadIdx.x + BS * l;
-        const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
-        const int x = bx - R + ex, y = by - R + ey, z = bz - R + ez;
-        const bool ok = e < NE && inside(x, y, z);
-        const uint32_t u = ok ? (uint32_t)x + (uint32_t)Dx * ((uint32_t)y + (uint32_t)Dy * (uint32_t)z) : 0u;
-        ev[l] = dir[vb + u];   // unconditional (voxel 0 exists): no branch to wait at
-        lv[l] = ok ? min(min(min(ex, EX - 1 - ex), min(ey, EY - 1 - ey)), min(ez, EZ - 1 - ez)) : -1;
-    }
+        for (int k = 0; k < CPT; ++k) {
+            const int c = threadIdx.x + BS * k;
+            col[k] = c;
+            const int ex = c % EX, ey = c / EX;
+            const int x = bx - R + ex, y = by - R + ey;
+            const bool inxy = c < NC && x >= 0 && x < Dx && y >= 0 && y < Dy;
+            // depth of the column inside the loaded region (-1: no column)
+            dxy[k] = inxy ? min(min(ex, EX - 1 - ex), min(ey, EY - 1 - ey)) : -1;
+            const uint32_t uxy = inxy ? (uint32_t)x + (uint32_t)Dx * (uint32_t)y : 0u;
 #pragma unroll
-    for (int l = 0; l < kLoads; ++l) {
-        const int e = threadIdx.x + BS * l;
-        if (e < NE) {
-            const bool occ = lv[l] >= 0 && ev[l].y != 0u && (ev[l].y & kMask) == 0u;
-            dl[e] = ev[l];
-            s0[e] = occ ? (uint16_t)e : kNone16;
+            for (int ez = 0; ez < EZ; ++ez) {
+                const int z = bz - R + ez;
+                const bool ok = inxy && z >= 0 && z < Dz;
+                // unconditional (voxel 0 exists): no branch to wait at
+                ev[k][ez] = dir[vb + (ok ? uxy + plane * (uint32_t)z : 0u)];
+                const bool occ = ok && ev[k][ez].y != 0u && (ev[k][ez].y & kMask) == 0u;
+                st[k][ez] = occ ? (uint32_t)(ez * NC + c) : kNone32;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            if (col[k] < NC) {
+#pragma unroll
+                for (int ez = 0; ez < EZ; ++ez) {
+                    dl[ez * NC + col[k]] = ev[k][ez];
+                    sb[0][ez * NC + col[k]] = (uint16_t)st[k][ez];
+                }
+            }
     }
     __syncthreads();
-    uint16_t* cur = s0;
-    uint16_t* nxt = s1;
 #pragma unroll
     for (int r = 1; r <= R; ++r) {
+        const uint16_t* cur = sb[(r - 1) & 1];
+        uint16_t* nxt = sb[r & 1];
 #pragma unroll
-        for (int l = 0; l < kLoads; ++l) {
-            const int e = threadIdx.x + BS * l;
-            if (e >= NE) continue;
-            uint16_t v = cur[e];
-            if (v == kNone16 && lv[l] >= r) {
-                v = min(v, min(cur[e - 1], cur[e + 1]));
-                v = min(v, min(cur[e - EX], cur[e + EX]));
-                v = min(v, min(cur[e - EX * EY], cur[e + EX * EY]));
+        for (int k = 0; k < CPT; ++k) {
+            const int c = col[k];
+            const int ca = c < NC ? c : NC - 1;   // a thread without this column reads a real one, unused
+            const bool live = dxy[k] >= r;        // the column lies r deep in the region
+            uint32_t old[EZ];
+#pragma unroll
+            for (int ez = 0; ez < EZ; ++ez) old[ez] = st[k][ez];
+            // selects, not branches: every element of the ring reads its four
+            // x / y neighbours, which keeps the waves free of divergent paths
+#pragma unroll
+            for (int ez = r; ez < EZ - r; ++ez) {
+                const int e = ez * NC + ca;
+                uint32_t v = min(old[ez - 1], old[ez + 1]);
+                v = min(v, (uint32_t)min(cur[e - 1], cur[e + 1]));
+                v = min(v, (uint32_t)min(cur[e - EX], cur[e + EX]));
+                st[k][ez] = (live && old[ez] == kNone32) ? v : old[ez];
             }
-            nxt[e] = v;
+            if (r < R && c < NC) {
+#pragma unroll
+                for (int ez = 0; ez < EZ; ++ez) nxt[ez * NC + c] = (uint16_t)st[k][ez];
+            }
         }
-        __syncthreads();
-        uint16_t* t = cur;
-        cur = nxt;
-        nxt = t;
+        if (r < R) __syncthreads();
     }
-    for (int e = threadIdx.x; e < TX * TY * TZ; e += BS) {
-        const int ix = e % TX, iy = (e / TX) % TY, iz = e / (TX * TY);
-        const int x = bx + ix, y = by + iy, z = bz + iz;
-        if (!inside(x, y, z)) continue;
-        const int self = (iz + R) * EX * EY + (iy + R) * EX + (ix + R);
-        const uint16_t root = cur[self];
-        // an occupied voxel keeps its own element as its state: any other
-        // root marks an empty voxel that the rings reached
-        if (root == kNone16 || root == (uint16_t)self) continue;
-        const int rx = bx - R + root % EX, ry = by - R + (root / EX) % EY, rz = bz - R + root / (EX * EY);
-        const uint32_t ru = (uint32_t)rx + (uint32_t)Dx * ((uint32_t)ry + (uint32_t)Dy * (uint32_t)rz);
-        const uint32_t u = (uint32_t)x + (uint32_t)Dx * ((uint32_t)y + (uint32_t)Dy * (uint32_t)z);
-        const int64_t g = vb + u;
-        const uint2 own = dl[self], re = dl[root];
-        // an entry with the mask bit was dilated by an earlier run of the same
-        // rings (the autotuner re-runs the dilation): its words are final, and
-        // its start is the root's, not the voxel's own
-        if (own.y & kMask) continue;
-        vm[(int64_t)(uint32_t)(own.x + 2u * (uint32_t)g) + 1] = ru | kMask;
-        dir[g] = make_uint2(re.x, re.y | kMask);
+    // the tile's columns write their voxels' results
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int c = col[k];
+        const int ex = c % EX, ey = c / EX;
+        if (c >= NC || ex < R || ex >= R + TX || ey < R || ey >= R + TY) continue;
+        const int x = bx - R + ex, y = by - R + ey;
+        if (x >= Dx || y >= Dy) continue;
+#pragma unroll
+        for (int ez = R; ez < R + TZ; ++ez) {
+            const int z = bz - R + ez;
+            if (z >= Dz) continue;
+            const uint32_t self = (uint32_t)(ez * NC + c);
+            const uint32_t root = st[k][ez];
+            // an occupied voxel keeps its own element as its state: any other
+            // root marks an empty voxel that the rings reached
+            if (root == kNone32 || root == self) continue;
+            const uint2 own = dl[self], re = dl[root];
+            // an entry with the mask bit was dilated by an earlier run of the
+            // same rings (the autotuner re-runs the dilation): its words are
+            // final, and its start is the root's, not the voxel's own
+            if (own.y & kMask) continue;
+            const int rc = (int)(root % NC), rz = (int)(root / NC);
+            const uint32_t ru = (uint32_t)(bx - R + rc % EX) + (uint32_t)Dx * (uint32_t)(by - R + rc / EX) +
+                                plane * (uint32_t)(bz - R + rz);
+            const int64_t g = vb + (int64_t)((uint32_t)x + (uint32_t)Dx * (uint32_t)y + plane * (uint32_t)z);
+            vm[(int64_t)(uint32_t)(own.x + 2u * (uint32_t)g) + 1] = ru | kMask;
+            dir[g] = make_uint2(re.x, re.y | kMask);
+        }
     }
 }
 

@@ -170,9 +170,20 @@ __global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, cons
         lr = atomicAdd(&scnt[slot], 1u);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < kS; s += BS) {
-        const uint32_t k = skey[s];
-        if (k != kNone) sbase[s] = atomicAdd(&hist[P.v_base + k], scnt[s]);
+    // one global atomic per occupied slot, this thread's kS / BS slots all in
+    // flight together (a loop of atomics waits for each return in turn)
+    {
+        constexpr int kPer = kS / BS;
+        uint32_t kk[kPer], cc[kPer], bb[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            kk[j] = skey[threadIdx.x + j * BS];
+            cc[j] = scnt[threadIdx.x + j * BS];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) bb[j] = kk[j] != kNone ? atomicAdd(&hist[P.v_base + kk[j]], cc[j]) : 0u;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) sbase[threadIdx.x + j * BS] = bb[j];
     }
     __syncthreads();
     if (valid) {

@@ -141,10 +141,15 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // record is read once after the lanes combine (one more dependent load per
 // query, three fewer selects per candidate).
 //
+// kOne (a single pair of one_m source points): a block's first query is its
+// job index times the queries per block, so the query's load waits on no
+// table, and the pair record, the pose and the query load go out together
+// (with a table the chain is table -> pair record -> query).
+//
 // In registration nn_idx / nn_d2 are optional (null when not asked for): the
 // correspondence and squared distance of each locally resolved query are
 // written there too; the solve writes those of the globally searched ones.
-template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, int kMode>
+template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, int kMode, bool kOne>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
@@ -154,7 +159,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
                                                   unsigned long long* __restrict__ ctr, double* __restrict__ part,
-                                                  int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap)
+                                                  int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap,
+                                                  int64_t one_m)
 {
     static_assert(LPQ == 1 || LPQ == 2 || LPQ == 4 || LPQ == 8, "lanes per query");
     constexpr bool kReload = kMode == 1;
@@ -162,12 +168,12 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     static_assert(!kReload || (kMom && !kDirect), "position tracking needs index-ordered segments");
     constexpr int kWaves = BS / kWave;
     const int jb = xcd_job((int)blockIdx.x, (int)gridDim.x);
-    const BlockJob job = jobs[jb];
+    const BlockJob job = kOne ? BlockJob{0, jb * (BS / LPQ)} : jobs[jb];
     const PairDev& P = pd[job.pair];
     const PairState& S = st[job.pair];
     const int sub = threadIdx.x % LPQ;
     const int64_t t = (int64_t)job.start + threadIdx.x / LPQ;
-    const bool inrange = t < P.m;
+    const bool inrange = t < (kOne ? one_m : P.m);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t c = 0, i = 0;
     int64_t cs = 0;
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     // finished pairs).  An early return would let the compiler sink the load
     // below the flag's test.
     {
-        const int64_t tl = P.p_base + (inrange ? t : (int64_t)job.start);
+        const int64_t tl = (kOne ? (int64_t)0 : P.p_base) + (inrange ? t : (int64_t)job.start);
         if (kSorted) {
             const float4 pp = ps4[tl];
             x = pp.x;
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             x = px[tl];
             y = py[tl];
             z = pz[tl];
-            i = (uint32_t)(tl - P.p_base);
+            i = (uint32_t)(tl - (kOne ? (int64_t)0 : P.p_base));
         }
     }
     const bool active = inrange && S.done == 0;
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             }
         }
     }
-    const int64_t gp = P.p_base + i;
+    const int64_t gp = (kOne ? (int64_t)0 : P.p_base) + i;
     // queries for the global search: one list append per wave, each query at
     // its rank among the wave's misses (counted on its first lane)
     const bool miss = active && c == 0 && sub == 0;
@@ -426,12 +432,25 @@ __global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restr
         lr = atomicAdd(&cnt_[slot], 1u);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
-        const uint32_t k = key_[s];
-        if (k != kNone) {
-            base_[s] = atomicAdd(&sh[k], cnt_[s]);
-            if (base_[s] + cnt_[s] > kRankCap) atomicOr(&sbig[job.pair], 1);
+    // one global atomic per occupied slot, this thread's slots all in flight
+    // together (a loop of atomics waits for each return in turn)
+    {
+        constexpr int kPer = kBSlots / kBThreads;
+        uint32_t kk[kPer], cc[kPer], bb[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            kk[j] = key_[threadIdx.x + j * kBThreads];
+            cc[j] = cnt_[threadIdx.x + j * kBThreads];
         }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) bb[j] = kk[j] != kNone ? atomicAdd(&sh[kk[j]], cc[j]) : 0u;
+        bool big = false;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            base_[threadIdx.x + j * kBThreads] = bb[j];
+            big |= kk[j] != kNone && bb[j] + cc[j] > kRankCap;
+        }
+        if (big) atomicOr(&sbig[job.pair], 1);
     }
     __syncthreads();
     if (valid) {
@@ -501,7 +520,9 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
                                                          double* __restrict__ fpart,
                                                          unsigned long long* __restrict__ fctr)
 {
-    __shared__ int64_t s_pref[kMaxPairs + 1];
+    // the per-pair running sum of work items: npairs + 1 entries of dynamic
+    // LDS (a single pair needs 16 bytes, not a table for the largest batch)
+    extern __shared__ int64_t s_pref[];
     __shared__ float tx[kFbT], ty[kFbT], tz[kFbT];
     // the first kFbThreads pairs' list lengths and target counts do not
     // depend on the fold: loaded before it, used after it
@@ -654,15 +675,22 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
                       const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
                       uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      int all_global, const uint32_t* dcnt, uint32_t cap, int mode, hipStream_t s)
+                      int all_global, const uint32_t* dcnt, uint32_t cap, int mode, int64_t one_m, hipStream_t s)
 {
     if (njobs <= 0) return;
+    const bool one = one_m >= 0;
     // the position-tracking form, for many candidates per query: 4 or 8
     // lanes per query, registration over segments
     if (mode == 1 && mom && !dcnt && (lpq == 4 || lpq == 8)) {
 #define VICP_NNS_R(BS, L, SORTED)                                                                                  \
-    launch_timed(k_nns_local<BS, L, SORTED, true, false, 1>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,     \
-                 ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
+    if (one)                                                                                                       \
+        launch_timed(k_nns_local<BS, L, SORTED, true, false, 1, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py,  \
+                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     cap, one_m);                                                                                  \
+    else                                                                                                           \
+        launch_timed(k_nns_local<BS, L, SORTED, true, false, 1, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, \
+                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     cap, one_m)
 #define VICP_NNS_RL(BS, SORTED)                                     \
     if (lpq == 4) VICP_NNS_R(BS, 4, SORTED); else VICP_NNS_R(BS, 8, SORTED);
 #define VICP_NNS_RB(SORTED)                                         \
@@ -682,8 +710,14 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
         return;
     }
 #define VICP_NNS(BS, L, SORTED, MOM, DIRECT)                                                                       \
-    launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, pz,     \
-                 ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt, cap)
+    if (one && !DIRECT)                                                                                            \
+        launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py,  \
+                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     cap, one_m);                                                                                  \
+    else                                                                                                           \
+        launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, \
+                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     cap, one_m)
 #define VICP_NNS_L(BS, SORTED, MOM, DIRECT)                  \
     switch (lpq) {                                           \
     case 2: VICP_NNS(BS, 2, SORTED, MOM, DIRECT); break;     \
@@ -753,8 +787,8 @@ bool launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, c
                      unsigned long long* fctr, hipStream_t s)
 {
     if (npairs <= 0 || npairs > kMaxPairs || grid <= 0) return false;
-    launch_timed(k_fallback, dim3(grid), dim3(kFbThreads), s, pd, npairs, qx, qy, qz, px, py, pz, st, fb_count,
-                 fb_list, fb_key, fjobs, nunits, part, ctr, fpart, fctr);
+    launch_timed_lds(k_fallback, dim3(grid), dim3(kFbThreads), sizeof(int64_t) * (npairs + 1), s, pd, npairs, qx, qy,
+                     qz, px, py, pz, st, fb_count, fb_list, fb_key, fjobs, nunits, part, ctr, fpart, fctr);
     return true;
 }
 

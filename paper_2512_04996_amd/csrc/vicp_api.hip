@@ -747,7 +747,7 @@ bool queue_search(vicp_grid* g, const float* px, const float* py, const float* p
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
                          pz, g->ps4, g->st, g->dir, direct ? g->dblk : g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list,
                          g->fb_key, g->ctr, g->npart, all_global ? 1 : 0, direct ? g->dcnt : nullptr, g->dcap,
-                         g->search_mode, s);
+                         g->search_mode, g->B == 1 ? g->m[0] : -1, s);
     }
     ProfScope ps("fallback", s, cap, true);
     return launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count,
@@ -1482,7 +1482,7 @@ int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const
     hipLaunchKernelGGL(k_noalloc_setup, dim3(setup_blocks), dim3(256), 0, s, a, (int32_t)njobs, (int32_t)qpb,
                        (int32_t)njobs256, base);
     launch_nns_local(pd, jobs, (int)njobs, g->nns_block, g->nns_lpq, false, false, px, py, pz, nullptr, st, g->dir,
-                     g->qs4, nn_idx, nn_d2, cnt, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, s);
+                     g->qs4, nn_idx, nn_d2, cnt, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, m, s);
     if (!launch_fallback(pd, 1, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, st, cnt, fb_list, fb_key, nullptr, 0,
                          nullptr, nullptr, nullptr, nullptr, s))
         return fail(VICP_ERR_INVALID_ARG, "global-search grid out of range");

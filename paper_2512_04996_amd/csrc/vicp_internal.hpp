@@ -153,6 +153,19 @@ __device__ __forceinline__ int xcd_job(int b, int n)
     return ((i / kXcdChunk) * kXcds + x) * kXcdChunk + (i % kXcdChunk);
 }
 
+// XCD slabs: XCD x receives the x-th eighth of the jobs as one contiguous
+// range (block b runs on XCD b mod 8 and is its (b / 8)-th block).  For work
+// of uniform cost whose neighbouring jobs share data (the dilation's voxel
+// tiles and their halos), each XCD's L2 then holds one slab of the grid
+// instead of a share of every part of it.  A bijection on [0, n); the
+// n mod 8 jobs past the last whole round keep their index.
+__device__ __forceinline__ int xcd_slab(int b, int n)
+{
+    const int per = n / kXcds, full = per * kXcds;
+    if (b >= full) return b;
+    return (b % kXcds) * per + b / kXcds;
+}
+
 // --------------------------------------------------------------------------
 // wave64 reductions on DPP (no LDS round trips)
 // --------------------------------------------------------------------------
@@ -247,6 +260,17 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, Args...
         hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
 
+// The same with `lds` bytes of dynamic LDS.
+template <typename F, typename... Args>
+inline void launch_timed_lds(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof_take_ext_events(&a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, s, a, b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 // --------------------------------------------------------------------------
 // kernel launchers (one translation unit each; all asynchronous)
 // --------------------------------------------------------------------------
@@ -300,13 +324,14 @@ bool launch_dilate_fused(const PairDev* pd, const BlockJob* jobs, int njobs, int
 void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint32_t* cnt, float4* blk,
                       uint32_t cap, hipStream_t s);
 
-// search and moments
+// search and moments; one_m >= 0: a single pair of one_m source points with
+// jobs of block / lpq queries each (the table is not read), else -1
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
                       const float* px, const float* py, const float* pz, const float4* ps4,
                       const PairState* st, const uint2* dir, const float4* qs4,
                       int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
                       unsigned long long* fb_key, unsigned long long* ctr, double* part, int all_global,
-                      const uint32_t* dcnt, uint32_t cap, int mode, hipStream_t s);
+                      const uint32_t* dcnt, uint32_t cap, int mode, int64_t one_m, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                        const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
                        int32_t* sbig, int32_t* flags, hipStream_t s);

@@ -9,6 +9,9 @@
            runs, each scaled by what the same counter reads for a plain copy of
            N MiB (the bytes a copy must move are known exactly)
 
+    python -m paper_2512_04996_amd.profiling counters DIR [DIR...] --kernels NAME... --out OUT_MD --command "..."
+        -> per-kernel medians of every counter collected in the given runs
+
 The counter runs must include one plain device-to-device copy of N MiB
 (``bench.py --calib-copy-mib N``); its dispatch is the one whose kernel name
 contains "copyBuffer".
@@ -89,6 +92,35 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_mib: float) -> dic
     return out
 
 
+def counters_table(dirs, kernels, command: str) -> str:
+    """Median per dispatch of every counter found under the given counter
+    directories, one column per kernel (matched by substring of its name)."""
+    table = {}
+    names = []
+    for d in dirs:
+        rows = _counter_rows(d)
+        for cname in sorted({r.get("Counter_Name") or r.get("counter_name") for r in rows}):
+            per = _per_dispatch(rows, cname)
+            names.append(cname)
+            for k in kernels:
+                vals = [v for kn, v in per.values() if k in kn]
+                table[(cname, k)] = (statistics.median(vals), len(vals)) if vals else None
+    head = "| counter | " + " | ".join(f"`{k}`" for k in kernels) + " |"
+    lines = [head, "|---|" + "---|" * len(kernels)]
+    for cname in names:
+        cells = []
+        for k in kernels:
+            v = table.get((cname, k))
+            cells.append("-" if v is None else f"{v[0]:,.0f}")
+        lines.append(f"| {cname} | " + " | ".join(cells) + " |")
+    disp = []
+    for k in kernels:
+        ns = [table[(c, k)][1] for c in names if table.get((c, k))]
+        disp.append(f"`{k}`: {max(ns) if ns else 0}")
+    return (f"Command:\n\n```\n{command}\n```\n\nMedians over the dispatches of each kernel "
+            f"({', '.join(disp)}), summed over the device.\n\n" + "\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -105,7 +137,17 @@ def main(argv=None):
     t.add_argument("--source", default=os.path.join(HERE, "csrc", "k_nns.hip"))
     t.add_argument("--out", required=True)
     t.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="Counters (rocprofv3 --pmc)")
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        with open(a.out, "w") as f:
+            f.write(f"# {a.title}\n\n" + counters_table(a.dirs, a.kernels, a.command))
+        return 0
     if a.cmd == "stats":
         with open(a.out, "w") as f:
             f.write(f"# {a.title}\n\n" + stats_table(a.csv, a.command))
