@@ -62,13 +62,13 @@ def parse():
     return ap.parse_args()
 
 
-def nns_local_bytes(m, F, cand, nblocks):
+def nns_local_bytes(m, F, cand, nrecords):
     """Algorithmic bytes of one registration-search launch (each logical
     access once): per query 16 (the bucketed source point, float4) + 8 (its
     voxel's search-directory entry); 16 per candidate (float4 x, y, z,
     index); 12 per query sent to the global search (list slot + 64-bit key);
-    per block 19 float64 moment partials + 3 counters (176)."""
-    return m * 24 + 16 * cand + 12 * F + 176 * nblocks
+    per wave one record of 19 float64 moments + 3 counters (176)."""
+    return m * 24 + 16 * cand + 12 * F + 176 * nrecords
 
 
 def main():
@@ -109,7 +109,8 @@ def main():
     tf = lambda b: "true" if b else "false"
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
                    f"{tf(schedule['sort_source'])}, true, false, {schedule['search_mode']}>")
-    nns_blocks = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block'])
+    # one moment record per search wave
+    nns_records = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block']) * (schedule['nns_block'] // 64)
     build_schedule = g.build_schedule
 
     def step():
@@ -185,7 +186,7 @@ def main():
     F = np.asarray(res.fallbacks[0], np.int64)
     cand = np.asarray(res.candidates[0], np.int64)
     dil = np.asarray(res.dilated_lookups[0], np.int64)
-    per_launch = [nns_local_bytes(P.m, int(F[k]), int(cand[k]), nns_blocks) for k in range(K)]
+    per_launch = [nns_local_bytes(P.m, int(F[k]), int(cand[k]), nns_records) for k in range(K)]
     bytes_per_launch = float(np.mean(per_launch))
     roofline = None
     if "nns_local" in kernels:

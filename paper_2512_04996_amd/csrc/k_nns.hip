@@ -119,15 +119,15 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // (distance, index) -- the same result as one lane scanning everything, with
 // LPQ times more waves in flight to hide the load latency.
 //
-// kMom (registration): instead of writing each correspondence, the block
+// kMom (registration): instead of writing each correspondence, each wave
 // adds the float64 moments of Eq. 1 over its locally resolved queries (sum p,
 // sum q, sum p q^T, sum |p|^2, sum |q|^2 about the grid centre, sum d, count)
-// in a fixed lane and wave order and writes one partial per block, with its
-// counters (candidates scanned, dilated lookups, queries sent to the global
-// search).  Partials and counters are stored block-major: entry j of block
-// b at [b * kMoments + j], counter k at [b * 3 + k], one contiguous record per
-// block.  Queries sent to the global search add their moments later, once
-// resolved.  Launch blocks are mapped to jobs XCD by XCD (xcd_job).
+// in a fixed lane order and writes one record, with its counters
+// (candidates scanned, dilated lookups, queries sent to the global search).
+// Records are wave-major: wave w of job b is record r = b * (BS / 64) + w,
+// entry j at [r * kMoments + j], counter k at [r * 3 + k].  Queries sent to
+// the global search add their moments later, once resolved.  Launch blocks
+// are mapped to jobs XCD by XCD (xcd_job).
 //
 // kDirect: VANICP's monolithic layout (the comparator).  Voxel g's
 // candidates are the records of its own fixed block, at g * cap, and its
@@ -295,89 +295,82 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         nn_idx[gp] = (int32_t)bidx;
         nn_d2[gp] = bd;
     }
-    // Reductions over the block in a fixed order.  Counters are exact
-    // integers (candidates scanned per 16-lane row by DPP, dilated lookups and
-    // global-search queries per wave by popcount).
-    constexpr int kRows = 4 * kWaves;
-    const int row = w * 4 + (lane >> 4);
-    const bool row_end = (lane & 15) == 16 - LPQ;
-    __shared__ uint32_t cred[kRows];
-    __shared__ uint32_t wred[2][kWaves];
-    const uint32_t cw = row_sum_u32<LPQ>((sub == 0) ? c : 0u);
-    if (row_end) cred[row] = cw;
-    const uint32_t ndil = (uint32_t)__popcll(__ballot(dil && sub == 0));   // whole wave: outside any branch
-    if (lane == 0) {
-        wred[0][w] = ndil;
-        wred[1][w] = (uint32_t)__popcll(mmask);
-    }
-    if (kMom) {
-        // Moments of this lane's query about the grid centre, zero for a
-        // query not resolved here (selects, so nothing else is read).  Each
-        // query's first lane stores its 18 values in LDS (LDS stores, not
-        // vector instructions: cross-lane float64 sums by DPP cost the search
-        // more issue slots than its gather), one row of kStride (odd) words
-        // per query so that neither the row stores nor the column reads
-        // below fall on one bank; then kSlices threads per entry each add an
-        // interleaved slice of the queries in order, and one thread per entry
-        // adds its slices in order.  The count is a popcount.
-        constexpr int kQ = BS / LPQ;
-        constexpr int kSums = kMoments - 1;
-        constexpr int kSlices = 18 * 16 <= BS ? 16 : (18 * 8 <= BS ? 8 : 4);
-        static_assert(kSums * kSlices <= BS && kQ % kSlices == 0, "slice layout");
-        constexpr int kStride = kSums | 1;
-        __shared__ double mq[kQ * kStride];
-        __shared__ double ms[kSums][kSlices];
-        __shared__ uint32_t mcnt[kWaves];
+    if (!kMom) return;
+    // Registration: one record per wave, the float64 moments of Eq. 1 over
+    // the wave's locally resolved queries about the grid centre (sum p,
+    // sum q, sum p q^T, sum |p|^2, sum |q|^2, sum d, count) and three exact
+    // counters (candidates scanned, dilated lookups, queries sent to the
+    // global search), reduced inside the wave in a fixed order.  No block
+    // barrier: the waves of a block finish independently.  Each query's
+    // first lane stores its 18 values as one row of the wave's LDS rows
+    // (kStride odd words, so neither the row stores nor the column reads
+    // fall on one bank); then three lanes per entry each add an interleaved
+    // slice of the rows in order, and one lane per entry adds the three
+    // slices in order.  A wave's LDS accesses execute in order, so a wave
+    // barrier (no instruction, it only keeps the compiler from moving LDS
+    // accesses across it) is all the rows need between store and read.
+    constexpr int kQw = kWave / LPQ;   // queries per wave
+    constexpr int kSums = kMoments - 1;
+    constexpr int kStride = kSums | 1;
+    constexpr int kSl = 3;             // slices per entry
+    static_assert(kSums * kSl <= kWave, "slice layout");
+    __shared__ double mq[kWaves][kQw * kStride];
+    __shared__ double ms[kWaves][kSums * kSl];
+    const int64_t rec = (int64_t)jb * kWaves + w;
+    const uint32_t ndil = (uint32_t)__popcll(__ballot(dil && sub == 0));
+    const uint32_t nfound = (uint32_t)__popcll(__ballot(found));
+    const uint32_t cw = row_sum_u32<LPQ>((sub == 0) ? c : 0u);   // each 16-lane row's total in its lane 16 - LPQ
+    const uint32_t ncand = (uint32_t)__builtin_amdgcn_readlane((int)cw, 16 - LPQ) +
+                           (uint32_t)__builtin_amdgcn_readlane((int)cw, 32 - LPQ) +
+                           (uint32_t)__builtin_amdgcn_readlane((int)cw, 48 - LPQ) +
+                           (uint32_t)__builtin_amdgcn_readlane((int)cw, 64 - LPQ);
+    {
         const double c0 = P.cx, c1 = P.cy, c2 = P.cz;
         const double p[3] = {found ? (double)x - c0 : 0.0, found ? (double)y - c1 : 0.0,
                              found ? (double)z - c2 : 0.0};
         const double q[3] = {found ? (double)bx - c0 : 0.0, found ? (double)by - c1 : 0.0,
                              found ? (double)bz - c2 : 0.0};
         if (sub == 0) {
-            double* row = mq + (threadIdx.x / LPQ) * kStride;
+            double* rowp = mq[w] + (lane / LPQ) * kStride;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                row[r] = p[r];
-                row[3 + r] = q[r];
+                rowp[r] = p[r];
+                rowp[3 + r] = q[r];
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) row[6 + 3 * r + cc] = p[r] * q[cc];
+                for (int cc = 0; cc < 3; ++cc) rowp[6 + 3 * r + cc] = p[r] * q[cc];
             }
-            row[15] = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-            row[16] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-            row[17] = found ? (double)bd : 0.0;
+            rowp[15] = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+            rowp[16] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+            rowp[17] = found ? (double)bd : 0.0;
         }
-        const uint32_t nfound = (uint32_t)__popcll(__ballot(found));
-        if (lane == 0) mcnt[w] = nfound;
-        __syncthreads();
-        if (threadIdx.x < kSums * kSlices) {
-            const int j = threadIdx.x / kSlices, sl = threadIdx.x % kSlices;
-            double sm = mq[sl * kStride + j];
-#pragma unroll
-            for (int e = 1; e < kQ / kSlices; ++e) sm += mq[(sl + e * kSlices) * kStride + j];
-            ms[j][sl] = sm;
-        }
-        __syncthreads();
-        if (threadIdx.x < kSums) {
-            double sm = ms[threadIdx.x][0];
-#pragma unroll
-            for (int e = 1; e < kSlices; ++e) sm += ms[threadIdx.x][e];
-            part[(int64_t)jb * kMoments + threadIdx.x] = sm;
-        } else if (threadIdx.x == kSums) {
-            uint32_t cn = 0;
-            for (int q2 = 0; q2 < kWaves; ++q2) cn += mcnt[q2];
-            part[(int64_t)jb * kMoments + kMoments - 1] = (double)cn;
-        }
-    } else {
-        __syncthreads();
     }
-    if (threadIdx.x >= 32 && threadIdx.x < 35) {
-        const int k = threadIdx.x - 32;
-        unsigned long long sm = 0;
-        if (k == 0)
-            for (int r = 0; r < kRows; ++r) sm += cred[r];
-        else
-            for (int q2 = 0; q2 < kWaves; ++q2) sm += wred[k - 1][q2];
-        ctr[(int64_t)jb * 3 + k] = sm;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < kSums * kSl) {
+        const int j = lane / kSl, sl = lane % kSl;
+        double sm = 0.0;
+#pragma unroll
+        for (int e = 0; e < (kQw + kSl - 1) / kSl; ++e) {
+            const int r = sl + kSl * e;
+            if (r < kQw) sm += mq[w][r * kStride + j];
+        }
+        ms[w][j * kSl + sl] = sm;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < kSums) {
+        double sm = ms[w][lane * kSl];
+#pragma unroll
+        for (int e = 1; e < kSl; ++e) sm += ms[w][lane * kSl + e];
+        part[rec * kMoments + lane] = sm;
+    } else if (lane == kSums) {
+        part[rec * kMoments + kMoments - 1] = (double)nfound;
+    } else if (lane >= 32 && lane < 35) {
+        const int k = lane - 32;
+        ctr[rec * 3 + k] = k == 0 ? (unsigned long long)ncand
+                                  : (unsigned long long)(k == 1 ? ndil : (uint32_t)__popcll(mmask));
     }
 }
 
@@ -529,14 +522,15 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
     const bool own0 = (int)threadIdx.x < npairs;
     const int64_t F0 = own0 ? fb_count[threadIdx.x] : 0;
     const int64_t n0 = own0 ? pd[threadIdx.x].n : 0;
-    // registration: first fold the search blocks' moment partials, kFoldChunk
-    // blocks per unit, each summed in block order (the launch runs anyway,
+    // registration: first fold the search waves' moment records, kFoldChunk
+    // records per unit, each summed in record order (the launch runs anyway,
     // and the fold does not depend on the global search)
     if (fjobs) {
         // rows padded by one element: the moment rows then start in different
         // banks, so neither the transposing stores nor the row sums conflict
         __shared__ double fv[kMoments][kFoldChunk + 1];
         __shared__ unsigned long long fc[2][kFoldChunk + 1];
+        __shared__ double fsl[kMoments][8 + 1];
         for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
             // a finished pair's units are folded too (their sums go unused):
             // testing its flag first would delay every load behind it
@@ -568,17 +562,33 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(const PairDev* __restri
                 if (j < 2) fc[j][bb] = cv;
             }
             __syncthreads();
-            if (threadIdx.x < kMoments) {
+            // kFoldSlices threads per moment each add an interleaved slice of
+            // the blocks in order, then one adds the slices in order (a fixed
+            // order, eight dependent adds each instead of 64)
+            constexpr int kFoldSlices = 8;
+            static_assert(kMoments * kFoldSlices <= kFbThreads - 2 && kFoldChunk % kFoldSlices == 0, "fold slices");
+            if (threadIdx.x < kMoments * kFoldSlices) {
+                const int j = threadIdx.x / kFoldSlices, sl = threadIdx.x % kFoldSlices;
                 double sm = 0.0;
-                for (int bb = 0; bb < cnt; ++bb) sm += fv[threadIdx.x][bb];
-                fpart[(int64_t)threadIdx.x * nunits + u] = sm;
-            } else if (threadIdx.x < kMoments + 2) {
-                const int j = threadIdx.x - kMoments;
+#pragma unroll
+                for (int e = 0; e < kFoldChunk / kFoldSlices; ++e) {
+                    const int bb = sl + e * kFoldSlices;
+                    sm += bb < cnt ? fv[j][bb] : 0.0;
+                }
+                fsl[j][sl] = sm;
+            } else if (threadIdx.x >= kFbThreads - 2) {
+                const int j = threadIdx.x - (kFbThreads - 2);
                 unsigned long long sm = 0;
                 for (int bb = 0; bb < cnt; ++bb) sm += fc[j][bb];
                 fctr[(int64_t)j * nunits + u] = sm;
             }
             __syncthreads();
+            if (threadIdx.x < kMoments) {
+                double sm = fsl[threadIdx.x][0];
+#pragma unroll
+                for (int e = 1; e < kFoldSlices; ++e) sm += fsl[threadIdx.x][e];
+                fpart[(int64_t)threadIdx.x * nunits + u] = sm;
+            }
         }
     }
     // items per pair (64-bit), loaded in parallel, then an in-LDS running sum

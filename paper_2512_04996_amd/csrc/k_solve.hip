@@ -284,7 +284,9 @@ constexpr int kWave = 64;
 constexpr int kSolveThreads = 256;
 constexpr int kSolveWaves = kSolveThreads / kWave;
 constexpr int kFbWindow = 32 * kSolveThreads;   // queries per pass over the global-search list
-constexpr int kFoldBatch = 64;                  // fold-unit loads in flight per thread
+constexpr int kUnitSlices = 12;                 // threads per fold-unit sum: (19 + 2) * 12 <= 256
+constexpr int kUnitBatch = 16;                  // fold-unit loads in flight per thread
+static_assert((kMoments + 2) * kUnitSlices <= kSolveThreads, "unit slices");
 
 // Adds the moments of one correspondence (p, q about the centre c, squared
 // distance d) to a[].
@@ -306,9 +308,9 @@ __device__ __forceinline__ void add_moments(double* a, float px, float py, float
     a[18] += 1.0;
 }
 
-// One block per pair.  (1) Thread j < 19 sums moment j of the pair's fold
-// units (moment-major, stride nunits) in unit order, kFoldBatch loads in
-// flight; two more threads sum the counters.  (2) Queries resolved by the
+// One block per pair.  (1) The pair's fold units (moment-major, stride
+// nunits) are summed per moment and counter by kUnitSlices threads each, in
+// a fixed order.  (2) Queries resolved by the
 // global search, when there are any: their list is in arbitrary order, so it
 // is replayed in windows of kFbWindow source indices through an LDS bitmap;
 // each thread adds the correspondences of its own 32 indices per window in
@@ -326,6 +328,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
 {
     __shared__ double tot[kMoments];
     __shared__ unsigned long long ctot[2];
+    __shared__ double usl[kMoments][kUnitSlices + 1];
+    __shared__ unsigned long long ucsl[2][kUnitSlices + 1];
     __shared__ double red[kMoments][kSolveWaves];
     __shared__ uint32_t wbits[kFbWindow / 32];
     __shared__ uint32_t wslot[kFbWindow];
@@ -344,27 +348,54 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     double Rp[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) Rp[j] = S.Rt[j];
-    if (threadIdx.x < kMoments) {
-        const double* row = fpart + (int64_t)threadIdx.x * nunits;
-        double sm = 0.0;
-        for (int32_t u = u0; u < u1; u += kFoldBatch) {
-            double v[kFoldBatch];
+    // the pair's fold units: kUnitSlices threads per sum each add an
+    // interleaved slice of the units in order (kUnitBatch loads in flight,
+    // added as a fixed tree), then one thread adds the slices in order
+    if (threadIdx.x < (kMoments + 2) * kUnitSlices) {
+        const int j = threadIdx.x / kUnitSlices, sl = threadIdx.x % kUnitSlices;
+        if (j < kMoments) {
+            const double* row = fpart + (int64_t)j * nunits;
+            double sm = 0.0;
+            for (int32_t u = u0 + sl; u < u1; u += kUnitSlices * kUnitBatch) {
+                double v[kUnitBatch];
 #pragma unroll
-            for (int i = 0; i < kFoldBatch; ++i) v[i] = (u + i < u1) ? row[u + i] : 0.0;
+                for (int i = 0; i < kUnitBatch; ++i) {
+                    const int32_t ui = u + i * kUnitSlices;
+                    v[i] = ui < u1 ? row[ui] : 0.0;
+                }
 #pragma unroll
-            for (int i = 0; i < kFoldBatch; ++i) sm += v[i];
+                for (int w = kUnitBatch / 2; w >= 1; w >>= 1)
+#pragma unroll
+                    for (int i = 0; i < w; ++i) v[i] += v[i + w];
+                sm += v[0];
+            }
+            usl[j][sl] = sm;
+        } else {
+            const unsigned long long* row = fctr + (int64_t)(j - kMoments) * nunits;
+            unsigned long long sm = 0;
+            for (int32_t u = u0 + sl; u < u1; u += kUnitSlices * kUnitBatch) {
+                unsigned long long v[kUnitBatch];
+#pragma unroll
+                for (int i = 0; i < kUnitBatch; ++i) {
+                    const int32_t ui = u + i * kUnitSlices;
+                    v[i] = ui < u1 ? row[ui] : 0ull;
+                }
+#pragma unroll
+                for (int i = 0; i < kUnitBatch; ++i) sm += v[i];
+            }
+            ucsl[j - kMoments][sl] = sm;
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMoments) {
+        double sm = usl[threadIdx.x][0];
+#pragma unroll
+        for (int e = 1; e < kUnitSlices; ++e) sm += usl[threadIdx.x][e];
         tot[threadIdx.x] = sm;
     } else if (threadIdx.x < kMoments + 2) {
-        const unsigned long long* row = fctr + (int64_t)(threadIdx.x - kMoments) * nunits;
         unsigned long long sm = 0;
-        for (int32_t u = u0; u < u1; u += kFoldBatch) {
-            unsigned long long v[kFoldBatch];
 #pragma unroll
-            for (int i = 0; i < kFoldBatch; ++i) v[i] = (u + i < u1) ? row[u + i] : 0ull;
-#pragma unroll
-            for (int i = 0; i < kFoldBatch; ++i) sm += v[i];
-        }
+        for (int e = 0; e < kUnitSlices; ++e) sm += ucsl[threadIdx.x - kMoments][e];
         ctot[threadIdx.x - kMoments] = sm;
     }
     // tested after the fold, whose loads do not depend on it, so that the

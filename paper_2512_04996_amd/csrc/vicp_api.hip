@@ -342,6 +342,16 @@ void make_jobs(const std::vector<int64_t>& counts, int items, std::vector<BlockJ
 constexpr int kNumTables = 6;
 constexpr int kQpb[kNumTables] = {16, 32, 64, 128, 256, 512};
 constexpr int kT256 = 4;   // the 256-per-block table (one lane per point kernels)
+// Waves per search block (128, 256 or 512 threads): the search writes one
+// moment record per wave.
+constexpr int kNumWpb = 3;
+constexpr int kWpb[kNumWpb] = {2, 4, 8};
+
+int wpb_index(int nns_block)
+{
+    const int w = nns_block / 64;
+    return w <= 2 ? 0 : (w <= 4 ? 1 : 2);
+}
 
 int table_of(int qpb)
 {
@@ -444,9 +454,11 @@ struct vicp_grid {
     int32_t* job_begin6 = nullptr;      // per pair, blocks of each source table
     BlockJob* jobs_p[kNumTables] = {};
     int njobs_p[kNumTables] = {};
-    FoldJob* fjobs[kNumTables] = {};    // fold units of each search table
-    int nfjobs[kNumTables] = {};
-    int32_t* fold_begin6 = nullptr;     // per table and pair, first fold unit
+    // fold units of the search's per-wave records, per search table and
+    // waves per block (kWpb): units of up to kFoldChunk consecutive records
+    FoldJob* fjobs[kNumTables][kNumWpb] = {};
+    int nfjobs[kNumTables][kNumWpb] = {};
+    int32_t* fold_begin6 = nullptr;     // per table, waves per block and pair: first fold unit
     double* fpart = nullptr;            // per fold unit: folded moment partials
     unsigned long long* fctr = nullptr; // per fold unit: folded counters
     int32_t* flags = nullptr;
@@ -587,16 +599,24 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     std::vector<BlockJob> jobs[kNumTables];
     std::vector<int32_t> begin;
     std::vector<int32_t> begin6;
-    std::vector<FoldJob> folds[kNumTables];
+    std::vector<FoldJob> folds[kNumTables][kNumWpb];
     std::vector<int32_t> fbegin6;
+    size_t max_rec = 1, max_units = 1;
     for (int k = 0; k < kNumTables; ++k) {
         make_jobs(m, kQpb[k], jobs[k], &begin);
         begin6.insert(begin6.end(), begin.begin(), begin.end());
-        fbegin6.push_back(0);
-        for (int p = 0; p < B; ++p) {
-            for (int32_t b = begin[p]; b < begin[p + 1]; b += kFoldChunk)
-                folds[k].push_back({p, b, std::min(b + kFoldChunk, begin[p + 1]), 0});
-            fbegin6.push_back((int32_t)folds[k].size());
+        for (int wi = 0; wi < kNumWpb; ++wi) {
+            // pair p's records are [begin[p] * wpb, begin[p + 1] * wpb)
+            const int32_t wpb = kWpb[wi];
+            fbegin6.push_back(0);
+            for (int p = 0; p < B; ++p) {
+                const int32_t r1 = begin[p + 1] * wpb;
+                for (int32_t r = begin[p] * wpb; r < r1; r += kFoldChunk)
+                    folds[k][wi].push_back({p, r, std::min(r + kFoldChunk, r1), 0});
+                fbegin6.push_back((int32_t)folds[k][wi].size());
+            }
+            max_rec = std::max(max_rec, (size_t)begin[B] * wpb);
+            max_units = std::max(max_units, folds[k][wi].size());
         }
     }
     const int64_t nb = source_buckets(g, m);
@@ -641,13 +661,11 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     g->part = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[kT256].size(), 1), s, L, ok);
     g->job_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * (B + 1), s, L, ok);
     g->jl6 = (double*)g->take(sizeof(double) * 36 * B, s, L, ok);
-    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 3 * std::max<size_t>(jobs[0].size(), 1), s, L,
-                                          ok);
-    g->npart = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(jobs[0].size(), 1), s, L, ok);
-    g->fpart = (double*)g->take(sizeof(double) * kMoments * std::max<size_t>(folds[0].size(), 1), s, L, ok);
-    g->fctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * std::max<size_t>(folds[0].size(), 1), s,
-                                           L, ok);
-    g->fold_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * (B + 1), s, L, ok);
+    g->ctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 3 * max_rec, s, L, ok);
+    g->npart = (double*)g->take(sizeof(double) * kMoments * max_rec, s, L, ok);
+    g->fpart = (double*)g->take(sizeof(double) * kMoments * max_units, s, L, ok);
+    g->fctr = (unsigned long long*)g->take(sizeof(unsigned long long) * 2 * max_units, s, L, ok);
+    g->fold_begin6 = (int32_t*)g->take(sizeof(int32_t) * kNumTables * kNumWpb * (B + 1), s, L, ok);
     g->sh = (uint32_t*)g->take(sizeof(uint32_t) * nb, s, L, ok);
     g->soff = (uint32_t*)g->take(sizeof(uint32_t) * (nb + 1), s, L, ok);
     g->skey = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
@@ -660,8 +678,10 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     for (int k = 0; k < kNumTables; ++k) {
         g->jobs_p[k] = (BlockJob*)g->take(sizeof(BlockJob) * std::max<size_t>(jobs[k].size(), 1), s, L, ok);
         g->njobs_p[k] = (int)jobs[k].size();
-        g->fjobs[k] = (FoldJob*)g->take(sizeof(FoldJob) * std::max<size_t>(folds[k].size(), 1), s, L, ok);
-        g->nfjobs[k] = (int)folds[k].size();
+        for (int wi = 0; wi < kNumWpb; ++wi) {
+            g->fjobs[k][wi] = (FoldJob*)g->take(sizeof(FoldJob) * std::max<size_t>(folds[k][wi].size(), 1), s, L, ok);
+            g->nfjobs[k][wi] = (int)folds[k][wi].size();
+        }
     }
     if (!ok) {
         g->release(g->ws_bufs, s);
@@ -675,11 +695,12 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
         if (!jobs[k].empty())
             VICP_HIP(hipMemcpyAsync(g->jobs_p[k], jobs[k].data(), sizeof(BlockJob) * jobs[k].size(),
                                     hipMemcpyHostToDevice, s));
-        if (!folds[k].empty())
-            VICP_HIP(hipMemcpyAsync(g->fjobs[k], folds[k].data(), sizeof(FoldJob) * folds[k].size(),
-                                    hipMemcpyHostToDevice, s));
+        for (int wi = 0; wi < kNumWpb; ++wi)
+            if (!folds[k][wi].empty())
+                VICP_HIP(hipMemcpyAsync(g->fjobs[k][wi], folds[k][wi].data(), sizeof(FoldJob) * folds[k][wi].size(),
+                                        hipMemcpyHostToDevice, s));
     }
-    VICP_HIP(hipMemcpyAsync(g->fold_begin6, fbegin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
+    VICP_HIP(hipMemcpyAsync(g->fold_begin6, fbegin6.data(), sizeof(int32_t) * kNumTables * kNumWpb * (B + 1),
                             hipMemcpyHostToDevice, s));
     VICP_HIP(hipMemcpyAsync(g->job_begin6, begin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
                             hipMemcpyHostToDevice, s));
@@ -751,7 +772,8 @@ bool queue_search(vicp_grid* g, const float* px, const float* py, const float* p
     }
     ProfScope ps("fallback", s, cap, true);
     return launch_fallback(g->d_pd, g->B, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count,
-                           g->fb_list, g->fb_key, mom ? g->fjobs[tab] : nullptr, g->nfjobs[tab], g->npart, g->ctr,
+                           g->fb_list, g->fb_key, mom ? g->fjobs[tab][wpb_index(g->nns_block)] : nullptr,
+                           g->nfjobs[tab][wpb_index(g->nns_block)], g->npart, g->ctr,
                            g->fpart, g->fctr, s);
 }
 
@@ -763,7 +785,9 @@ bool queue_iteration(vicp_grid* g, const float* px, const float* py, const float
     if (!queue_search(g, px, py, pz, nn_idx, nn_d2, s, cap, true, all_global, direct)) return false;
     ProfScope ps("solve", s, cap, true);
     const int tab = table_of(g->nns_block / g->nns_lpq);
-    launch_solve(g->d_pd, g->B, g->fold_begin6 + tab * (g->B + 1), g->nfjobs[tab], g->fpart, g->fctr, g->st,
+    const int wi = wpb_index(g->nns_block);
+    launch_solve(g->d_pd, g->B, g->fold_begin6 + (tab * kNumWpb + wi) * (g->B + 1), g->nfjobs[tab][wi], g->fpart,
+                 g->fctr, g->st,
                  g->fb_count, g->fb_list, g->fb_key, px, py, pz, g->qx, g->qy, g->qz, g->flags, g->rmse_hist,
                  g->fb_hist, g->deg_hist, g->ctr_hist, k, K, early, eps, nn_idx, nn_d2, s);
     return true;
@@ -2053,7 +2077,8 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
                 hipLaunchKernelGGL(k_synthetic_misses, dim3(g->B), dim3(256), 0, s, g->d_pd, g->B, g->fb_count,
                                    g->fb_list, g->fb_key);
                 (void)launch_fallback(g->d_pd, g->B, fg, g->qx, g->qy, g->qz, px, py, pz, g->st, g->fb_count,
-                                      g->fb_list, g->fb_key, g->fjobs[tab], g->nfjobs[tab], g->npart, g->ctr,
+                                      g->fb_list, g->fb_key, g->fjobs[tab][wpb_index(g->nns_block)],
+                                      g->nfjobs[tab][wpb_index(g->nns_block)], g->npart, g->ctr,
                                       g->fpart, g->fctr, s);
             });
             const float t = t0 + t1 / (float)searches_per_plan;

@@ -108,8 +108,8 @@ struct BlockJob {
     int32_t start;
 };
 
-// First-level fold of the search blocks' moment partials: up to kFoldChunk
-// consecutive search blocks [b0, b1) of one pair.
+// First-level fold of the search's moment records (one per search wave): up
+// to kFoldChunk consecutive records [b0, b1) of one pair.
 constexpr int kFoldChunk = 64;
 struct FoldJob {
     int32_t pair;
