@@ -36,6 +36,20 @@ FP32_PEAK_TFLOPS = 157.3        # published dense float32 vector peak
 SEARCH_FLOPS_PER_BYTE = 8.0 / 16.0
 PROFILE_PMC = os.path.join(ROOT, "profiles", "nns_local_room_226k_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_04996_amd", "csrc", "k_nns.hip")
+PROFILE_PMC_DIL = os.path.join(ROOT, "profiles", "dilate_fused_room_226k_pmc.json")
+KERNEL_SRC_DIL = os.path.join(ROOT, "paper_2512_04996_amd", "csrc", "k_dilate.hip")
+
+
+def counter_traffic(pmc_path, src_path, kernel):
+    """HBM bytes per launch from a stored FETCH_SIZE + WRITE_SIZE summary, or
+    None when the kernel variant or its source changed since it was taken."""
+    if not os.path.exists(pmc_path):
+        return None
+    pmc = json.load(open(pmc_path))
+    src_hash = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
+    if pmc.get("kernel_source_sha256") == src_hash and pmc.get("kernel") == kernel:
+        return pmc.get("hbm_bytes_per_launch")
+    return None
 
 
 def log(msg):
@@ -107,8 +121,9 @@ def main():
             g.set_build_schedule(cb, bool(fu), ti, rb)
     schedule = g.schedule
     tf = lambda b: "true" if b else "false"
+    # the variant that runs: registration form over segments, single pair
     nns_variant = (f"k_nns_local<{schedule['nns_block']}, {schedule['lanes_per_query']}, "
-                   f"{tf(schedule['sort_source'])}, true, false, {schedule['search_mode']}>")
+                   f"{tf(schedule['sort_source'])}, true, false, {schedule['search_mode']}, true>")
     # one moment record per search wave
     nns_records = -(-P.m * schedule['lanes_per_query'] // schedule['nns_block']) * (schedule['nns_block'] // 64)
     build_schedule = g.build_schedule
@@ -192,13 +207,8 @@ def main():
     if "nns_local" in kernels:
         dur_s = kernels["nns_local"]["avg_us"] * 1e-6
         achieved = bytes_per_launch / dur_s / 1e9
-        traffic = None
-        if os.path.exists(PROFILE_PMC):
-            pmc = json.load(open(PROFILE_PMC))
-            src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-            # counters of this very kernel variant, taken from the current source
-            if pmc.get("kernel_source_sha256") == src_hash and pmc.get("kernel") == nns_variant:
-                traffic = pmc.get("hbm_bytes_per_launch")
+        # counters of this very kernel variant, taken from the current source
+        traffic = counter_traffic(PROFILE_PMC, KERNEL_SRC, nns_variant)
         # the roofline that bounds the kernel, from its arithmetic intensity
         # against the machine balance (peak flops / peak bytes)
         balance = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -261,11 +271,20 @@ def main():
         dbytes = 8 * V + 12 * nd
         ach = dbytes / dur / 1e9
         t = tiles[build_schedule["dilate_tile"]].split("x")
-        dilation_roof = {"kernel": f"k_dilate_fused<{P.rings}, {t[0]}, {t[1]}, {t[2]}>", "bound": "hbm",
+        dname = f"k_dilate_fused<{P.rings}, {t[0]}, {t[1]}, {t[2]}>"
+        dtraffic = counter_traffic(PROFILE_PMC_DIL, KERNEL_SRC_DIL, dname)
+        dmeas = None if dtraffic is None else dtraffic / dur / 1e9
+        dilation_roof = {"kernel": dname, "bound": "hbm",
                          "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "compulsory_bytes_per_launch": int(dbytes),
                          "ring_model_bytes": int(ring_model),
                          "ring_model_frac": round(ring_model / dur / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": dtraffic,
+                         "hbm_frac": None if dmeas is None else round(dmeas / HBM_PEAK_GBS, 4),
+                         "limiter": ("unknown (no counter traffic for this kernel source)" if dmeas is None else
+                                     f"latency: one round of about 1.6 blocks per CU, each a chain of a load "
+                                     f"round, the rings in LDS and the writes; the counters see "
+                                     f"{dmeas:.0f} GB/s of HBM traffic"),
                          "avg_us": round(kernels["dilate"]["avg_us"], 3)}
     elif "dilate_ring" in kernels:
         dur = kernels["dilate_ring"]["avg_us"] * 1e-6 * P.rings

@@ -335,10 +335,11 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
  * candidate's index and coordinates; 1 (4 or 8 lanes per query) each lane
  * keeps its best segment position and the winner's record is read once,
  * fewer instructions per candidate and one more dependent load per query.
- * No setting changes a correspondence or a count; the queries per block
- * (threads per block / lanes per query) and the source order group the
- * float64 moment sums, so they can change the last bits of a pose; the
- * search mode does not.  INVALID_ARG for an unsupported value or
+ * No setting changes a correspondence or a count.  The lanes per query (a
+ * search wave sums the moments of 64 / lanes-per-query queries) and the
+ * source order group the float64 moment sums, so they can change the last
+ * bits of a pose; the threads per block, the global-search grid and the
+ * search mode do not.  INVALID_ARG for an unsupported value or
  * combination. */
 int vicp_get_schedule(const vicp_grid* g, int32_t* nns_block, int32_t* lanes_per_query,
                       int32_t* sort_source, int32_t* fallback_grid, int32_t* search_mode);

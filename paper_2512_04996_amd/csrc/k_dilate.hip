@@ -266,11 +266,11 @@ static bool launch_fused_r(int shape, const PairDev* pd, const BlockJob* jobs, i
                            hipStream_t s)
 {
     switch (shape) {
-    case 0: hipLaunchKernelGGL((k_dilate_fused<R, 8, 8, 4>), dim3(njobs), dim3(256), 0, s, pd, jobs, vm, dir); return true;
-    case 1: hipLaunchKernelGGL((k_dilate_fused<R, 16, 8, 4>), dim3(njobs), dim3(256), 0, s, pd, jobs, vm, dir); return true;
-    case 2: hipLaunchKernelGGL((k_dilate_fused<R, 8, 8, 8>), dim3(njobs), dim3(256), 0, s, pd, jobs, vm, dir); return true;
-    case 3: hipLaunchKernelGGL((k_dilate_fused<R, 32, 8, 4>), dim3(njobs), dim3(256), 0, s, pd, jobs, vm, dir); return true;
-    case 4: hipLaunchKernelGGL((k_dilate_fused<R, 16, 16, 4>), dim3(njobs), dim3(256), 0, s, pd, jobs, vm, dir); return true;
+    case 0: launch_timed(k_dilate_fused<R, 8, 8, 4>, dim3(njobs), dim3(256), s, pd, jobs, vm, dir); return true;
+    case 1: launch_timed(k_dilate_fused<R, 16, 8, 4>, dim3(njobs), dim3(256), s, pd, jobs, vm, dir); return true;
+    case 2: launch_timed(k_dilate_fused<R, 8, 8, 8>, dim3(njobs), dim3(256), s, pd, jobs, vm, dir); return true;
+    case 3: launch_timed(k_dilate_fused<R, 32, 8, 4>, dim3(njobs), dim3(256), s, pd, jobs, vm, dir); return true;
+    case 4: launch_timed(k_dilate_fused<R, 16, 16, 4>, dim3(njobs), dim3(256), s, pd, jobs, vm, dir); return true;
     default: return false;
     }
 }

@@ -503,7 +503,7 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
                  int njobs, int items_per_block, uint32_t* box, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_aabb, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, items_per_block, box);
+    launch_timed(k_aabb, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, items_per_block, box);
 }
 
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
@@ -512,17 +512,16 @@ void launch_count(const float* qx, const float* qy, const float* qz, const PairD
 {
     if (njobs <= 0) return;
     if (packed)
-        hipLaunchKernelGGL(k_count_packed, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
-                           err);
+        launch_timed(k_count_packed, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
     else if (block == 1024)
-        hipLaunchKernelGGL((k_count<false, 1024>), dim3(njobs), dim3(1024), 0, s, qx, qy, qz, pd, jobs, hist, vox,
-                           rank, err, (float4*)nullptr, 0u);
+        launch_timed(k_count<false, 1024>, dim3(njobs), dim3(1024), s, qx, qy, qz, pd, jobs, hist, vox, rank, err,
+                     (float4*)nullptr, 0u);
     else if (block == 512)
-        hipLaunchKernelGGL((k_count<false, 512>), dim3(njobs), dim3(512), 0, s, qx, qy, qz, pd, jobs, hist, vox, rank,
-                           err, (float4*)nullptr, 0u);
+        launch_timed(k_count<false, 512>, dim3(njobs), dim3(512), s, qx, qy, qz, pd, jobs, hist, vox, rank, err,
+                     (float4*)nullptr, 0u);
     else
-        hipLaunchKernelGGL((k_count<false, kThreads>), dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, hist,
-                           vox, rank, err, (float4*)nullptr, 0u);
+        launch_timed(k_count<false, kThreads>, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, hist, vox, rank,
+                     err, (float4*)nullptr, 0u);
 }
 
 void launch_count_direct(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
@@ -551,18 +550,16 @@ void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* v
     const int tiles = scan_tiles(total);
     if (tiles <= 0) return;
     if (vm)
-        hipLaunchKernelGGL(k_scan<true>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, dir, status,
-                           ticket);
+        launch_timed(k_scan<true>, dim3(tiles), dim3(kThreads), s, hist, total, off, vm, dir, status, ticket);
     else
-        hipLaunchKernelGGL(k_scan<false>, dim3(tiles), dim3(kThreads), 0, s, hist, total, off, vm, dir, status,
-                           ticket);
+        launch_timed(k_scan<false>, dim3(tiles), dim3(kThreads), s, hist, total, off, vm, dir, status, ticket);
 }
 
 void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* rank,
                   const uint32_t* off, uint32_t* tmp, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_place, dim3(njobs), dim3(kThreads), 0, s, pd, jobs, vox, rank, off, tmp);
+    launch_timed(k_place, dim3(njobs), dim3(kThreads), s, pd, jobs, vox, rank, off, tmp);
 }
 
 void launch_rank_sort(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
@@ -570,8 +567,7 @@ void launch_rank_sort(const float* qx, const float* qy, const float* qz, const P
                       uint32_t* vm, float4* qs4, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_rank_sort, dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm,
-                       qs4);
+    launch_timed(k_rank_sort, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm, qs4);
 }
 
 void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, uint32_t* c, int64_t nc, uint32_t* d,

@@ -861,7 +861,7 @@ float unordered(uint32_t k)
 // packed-hash ablation always runs 256 points per block).
 void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz, bool packed, hipStream_t s)
 {
-    ProfScope ps("count", s, false);
+    ProfScope ps("count", s, false, true);
     const BlockJob* jobs = g->jobs_q;
     int nj = g->njobs_q, bs = 256;
     if (!packed && g->count_block == 512) {
@@ -883,7 +883,7 @@ void queue_dilate(vicp_grid* g, int rings, hipStream_t s, bool cap)
 {
     if (rings < 1) return;
     if (rings <= kFusedRings && g->dil_fused) {
-        ProfScope ps("dilate", s, cap);
+        ProfScope ps("dilate", s, cap, true);
         launch_dilate_fused(g->d_pd, g->jobs_t[g->dil_shape], g->njobs_t[g->dil_shape], rings, g->dil_shape, g->vm,
                             g->dir, s);
         return;
@@ -913,7 +913,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         words = pairs[0].n + 2 * pairs[0].V;
     } else {
     {
-        ProfScope ps("aabb", s, false);
+        ProfScope ps("aabb", s, false, true);
         launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
     }
     const size_t nbox = 8 * (size_t)g->njobs_q8;
@@ -1046,15 +1046,15 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         launch_seg_headers(g->hist, g->off, Vt, g->vm, g->dir, s);
         VICP_HIP(hipStreamSynchronize(s));   // the host arrays are reused by the next build
     } else {
-        ProfScope ps("scan", s, false);
+        ProfScope ps("scan", s, false, true);
         launch_scan(g->hist, Vt, g->off, g->vm, g->dir, g->scan_status, g->scan_ticket, s);
     }
     {
-        ProfScope ps("place", s, false);
+        ProfScope ps("place", s, false, true);
         launch_place(g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->rank, g->off, g->slots, s);
     }
     {
-        ProfScope ps("rank_sort", s, false);
+        ProfScope ps("rank_sort", s, false, true);
         launch_rank_sort(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots, g->vm,
                          g->qs4, s);
     }

@@ -165,13 +165,33 @@ def test_register_matches_oracle(case, use_graph):
 
 def assert_same_registration(a, b, extent):
     """Two registrations under different search schedules: the moment sums
-    are grouped by search block, so float64 rounding may differ in the last
-    bits; correspondences, fallback counts and the pose to 1e-10 may not."""
+    are grouped by search wave (64 / lanes-per-query queries) and follow the
+    source order, so float64 rounding may differ in the last bits;
+    correspondences, fallback counts and the pose to 1e-10 may not."""
     assert np.array_equal(a.fallbacks[0], b.fallbacks[0])
     assert np.array_equal(a.candidates[0], b.candidates[0])
     assert np.abs(a.Rt[:9] - b.Rt[:9]).max() <= 1e-10
     assert np.abs(a.Rt[9:] - b.Rt[9:]).max() <= 1e-10 * extent
     assert np.allclose(a.rmse[0], b.rmse[0], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("name", ["bumpy_40k", "room_226k"])
+@pytest.mark.parametrize("lpq,sort_source", [(1, True), (2, True), (4, False), (8, True)])
+def test_block_size_leaves_the_pose_bit_identical(name, lpq, sort_source):
+    # each search wave sums the same queries whatever the block size, and the
+    # fold takes the wave records in the same units, so the block size (and
+    # the global-search grid) change no bit of a registration
+    P = synth.config(name)
+    g = build_grid(dev(P.q), P.voxel, P.rings).dilate(P.rings)
+    p = dev(P.p)
+    runs = []
+    for bs, fg in ((128, 64), (256, 1024), (512, 256)):
+        g.set_schedule(bs, lpq, sort_source, fg)
+        runs.append(g.register(p, P.iters))
+    for r in runs[1:]:
+        assert np.array_equal(r.Rt, runs[0].Rt)
+        assert np.array_equal(r.rmse[0], runs[0].rmse[0])
+        assert np.array_equal(r.fallbacks[0], runs[0].fallbacks[0])
 
 
 def test_register_with_global_searches_over_several_windows():

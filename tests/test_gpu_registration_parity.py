@@ -8,7 +8,8 @@ compares the last iteration's nearest-neighbour index and squared distance of
 every source point, the per-iteration global-search counts, the RMSE history
 (1e-9 relative) and the final pose (1e-5 rad, 1e-6 x extent).  Schedules:
 the autotuned one and both candidate loops (search_mode 0 and 1, 4 and 8
-lanes per query, bucketed and not), eager and graph-replayed; with global
+lanes per query, bucketed and not), eager and graph-replayed; on sources
+shorter than one wave's queries and with ragged tails; with global
 searches in the compared iteration (listed queries resolved by the exact
 search and added by the solve), the exhaustive comparator, VANICP's layout
 and the early stop.
@@ -162,3 +163,18 @@ def test_grid_beyond_the_coordinate_limit_is_refused():
     idx, d2, _ = g.nns(dev(q), np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32))
     assert np.isfinite(d2.cpu().numpy()).all()
     assert math.isfinite(float(d2.max()))
+
+
+@pytest.mark.parametrize("m", [31, 1000, 70001])
+def test_registration_on_ragged_sources(m):
+    # sources shorter than one wave's queries, a few blocks, and a ragged tail
+    P = synth.bumpy_pair(seed=61, n=20000, m=m, voxel=0.05, rings=2, iters=4)
+    ref = oracle.register(P.q, P.p, P.voxel, 2, 4)
+    g = build_grid(dev(P.q), P.voxel, 2).dilate(2)
+    p = dev(P.p)
+    for sched in ((128, 2, True, 64, 0), (256, 4, True, 64, 1), (512, 8, False, 64, 0), (256, 1, True, 64, 0)):
+        g.set_schedule(*sched)
+        for use_graph in (False, True):
+            res = g.register(p, 4, use_graph=use_graph, correspondences=True)
+            assert_registration_equal(res, ref, P.extent)
+            assert_correspondences_equal(res.nn_idx, res.nn_d2, ref)
