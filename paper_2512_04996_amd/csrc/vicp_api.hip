@@ -476,11 +476,21 @@ struct vicp_grid {
     uint32_t* s_ticket = nullptr;
     std::vector<Buf> ws_bufs;
 
-    // captured registration
-    hipGraphExec_t gexec = nullptr;
+    // Captured work: the registration (plan + iterations).
+    struct Captured {
+        hipGraphExec_t exec = nullptr;
+        std::vector<uintptr_t> key;
+        std::vector<ProfRec> events;   // per-kernel event pairs inside the graph (timing on)
+        void drop()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+            key.clear();
+            prof_return(events);
+        }
+    };
+    Captured reg;
     hipStream_t cap_stream = nullptr;
-    std::vector<uintptr_t> gkey;
-    std::vector<ProfRec> gevents;   // per-kernel event pairs inside the graph (timing on)
 
     void* take(size_t bytes, hipStream_t s, std::vector<Buf>& list, bool& ok)
     {
@@ -496,13 +506,7 @@ struct vicp_grid {
         for (auto& b : list) mem.put(b.p, b.bytes, s);
         list.clear();
     }
-    void drop_graph()
-    {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        gexec = nullptr;
-        gkey.clear();
-        prof_return(gevents);
-    }
+    void drop_graph() { reg.drop(); }
     int64_t extra_bytes() const
     {
         int64_t b = 0;
@@ -859,9 +863,10 @@ float unordered(uint32_t k)
 
 // The count (Alg. 1 GPU part) under the grid's count schedule (the
 // packed-hash ablation always runs 256 points per block).
-void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz, bool packed, hipStream_t s)
+void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz, bool packed, hipStream_t s,
+                 bool cap = false)
 {
-    ProfScope ps("count", s, false, true);
+    ProfScope ps("count", s, cap, true);
     const BlockJob* jobs = g->jobs_q;
     int nj = g->njobs_q, bs = 256;
     if (!packed && g->count_block == 512) {
@@ -898,9 +903,11 @@ void queue_dilate(vicp_grid* g, int rings, hipStream_t s, bool cap)
     }
 }
 
-// Fills (or refills) a grid from target coordinates: bounding box (the one
-// synchronisation), grid specification, then counts, offsets, segments.
-int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
+// The host part of a refill: the bounding box (read back), the grid
+// specification, new buffers when the shape changes, and the pair records
+// on the device (passed in launch arguments, so no pageable copy holds the
+// host).
+int grid_fill_host(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
 {
     const int B = g->B;
     g->direct_ready = false;
@@ -1011,11 +1018,58 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     }
     std::vector<PairDev> pd;
     fill_pairdev(g, pd);
-    VICP_HIP(hipMemcpyAsync(g->d_pd, pd.data(), sizeof(PairDev) * B, hipMemcpyHostToDevice, s));
-    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    upload(pd.data(), sizeof(PairDev) * B, g->d_pd, s);
+    return VICP_OK;
+}
+
+// The packed-hash ablation applies when every pair's voxel ids fit its key.
+bool count_packed(const vicp_grid* g)
+{
     bool packed = g->packed_hash;
-    for (int p = 0; p < B && packed; ++p) packed = count_packed_fits(pairs[p].V);
-    queue_count(g, qx, qy, qz, packed, s);
+    for (int p = 0; p < g->B && packed; ++p) packed = count_packed_fits(g->pairs[p].V);
+    return packed;
+}
+
+// The device part of a refill whose pair records are on the device:
+// histogram (Alg. 1 GPU part), offsets, and the segments in ascending
+// order (Alg. 2).  The fixed-grid check and the host-side offset scan
+// synchronise, so grid_fill runs those forms itself.
+void queue_build(vicp_grid* g, hipStream_t s, bool cap)
+{
+    const int64_t Vt = g->V_total;
+    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    queue_count(g, g->qx, g->qy, g->qz, count_packed(g), s, cap);
+    {
+        ProfScope ps("scan", s, cap, true);
+        launch_scan(g->hist, Vt, g->off, g->vm, g->dir, g->scan_status, g->scan_ticket, s);
+    }
+    {
+        ProfScope ps("place", s, cap, true);
+        launch_place(g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->rank, g->off, g->slots, s);
+    }
+    {
+        ProfScope ps("rank_sort", s, cap, true);
+        launch_rank_sort(g->qx, g->qy, g->qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots,
+                         g->vm, g->qs4, s);
+    }
+}
+
+// Fills (or refills) a grid from target coordinates: bounding box (the one
+// synchronisation), grid specification, then counts, offsets, segments.
+int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, hipStream_t s)
+{
+    int rc = grid_fill_host(g, qx, qy, qz, s);
+    if (rc) return rc;
+    const int64_t Vt = g->V_total;
+    if (!g->fixed && !g->host_offsets) {
+        queue_build(g, s, false);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e));
+        g->usable = true;
+        return VICP_OK;
+    }
+    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    queue_count(g, qx, qy, qz, count_packed(g), s);
     if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
         uint32_t herr = 0;
         VICP_HIP(hipMemcpyAsync(&herr, g->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1517,22 +1571,83 @@ int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const
     return VICP_OK;
 }
 
-int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz,
-                          const int64_t* m_per_pair, const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats,
-                          hipStream_t s)
+}  // extern "C"
+
+namespace {
+
+// Captures the work `body` queues on the capture stream into c, unless c
+// already holds it under the same key.  With timing on, the first attempt
+// records kernel events inside the graph; if the runtime refuses that, the
+// work is captured without them.  body returns false when the batch is too
+// large for the global search: nothing is kept and the result is
+// INVALID_ARG.
+template <class F>
+int capture_into(vicp_grid* g, vicp_grid::Captured& c, const std::vector<uintptr_t>& key, F&& body)
 {
-    (void)hipGetLastError();   // an error left by other code is not ours to report
-    vicp_grid* g = const_cast<vicp_grid*>(gc);
-    int rc = check_grid(g);
-    if (rc) return rc;
+    if (c.exec && key == c.key) return VICP_OK;
+    c.drop();
+    if (!g->cap_stream) VICP_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    std::string why;
+    for (int attempt = (g_prof.on ? 0 : 1); attempt < 2 && !c.exec; ++attempt) {
+        hipGraph_t graph = nullptr;
+        VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+        t_capture_events = attempt == 0 ? &c.events : nullptr;
+        const bool queued = body(g->cap_stream);
+        t_capture_events = nullptr;
+        hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
+        hipError_t e = ec;
+        if (ec == hipSuccess) {
+            e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+        if (e != hipSuccess || !queued) {
+            (void)hipGetLastError();
+            if (c.exec) (void)hipGraphExecDestroy(c.exec);
+            c.exec = nullptr;
+            prof_return(c.events);
+            if (!queued) return fail(VICP_ERR_INVALID_ARG, "too many pairs for the global search");
+            why = hipGetErrorString(e);
+        }
+    }
+    if (!c.exec) return fail(VICP_ERR_HIP, "graph capture: " + why);
+    c.key = key;
+    return VICP_OK;
+}
+
+// The registration's argument checks (none touches the grid).
+int check_register(const vicp_grid* g, const float* px, const float* py, const float* pz,
+                   const int64_t* m_per_pair, const vicp_icp_opts* o, const double* Rt_io)
+{
     if (!m_per_pair || !o || !Rt_io) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     if (o->max_iter < 0 || o->max_iter > 100000) return fail(VICP_ERR_INVALID_ARG, "max_iter out of range");
     if (!(o->rmse_eps >= 0.0)) return fail(VICP_ERR_INVALID_ARG, "rmse_eps must be >= 0");
-    const int B = g->B;
-    for (int i = 0; i < 12 * B; ++i)
+    for (int i = 0; i < 12 * g->B; ++i)
         if (!isfinite(Rt_io[i])) return fail(VICP_ERR_INVALID_ARG, "non-finite initial pose");
     int64_t mt = 0;
-    for (int p = 0; p < B; ++p) mt += std::max<int64_t>(m_per_pair[p], 0);
+    for (int p = 0; p < g->B; ++p) {
+        if (m_per_pair[p] < 0 || m_per_pair[p] > (int64_t)INT32_MAX)
+            return fail(VICP_ERR_INVALID_ARG, "source size out of range");
+        mt += m_per_pair[p];
+    }
+    if (mt > 0 && o->max_iter > 0 && (!px || !py || !pz)) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    if (o->layout != 0 && o->global_only != 0)
+        return fail(VICP_ERR_INVALID_ARG, "global_only and the direct layout exclude each other");
+    if ((o->nn_idx == nullptr) != (o->nn_d2 == nullptr))
+        return fail(VICP_ERR_INVALID_ARG, "nn_idx and nn_d2 are given together or not at all");
+    return VICP_OK;
+}
+
+// The registration (vicp_register_batched).
+int register_impl(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                  const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats, hipStream_t s)
+{
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = check_register(g, px, py, pz, m_per_pair, o, Rt_io);
+    if (rc) return rc;
+    const int B = g->B;
+    int64_t mt = 0;
+    for (int p = 0; p < B; ++p) mt += m_per_pair[p];
     if (stats)
         for (int p = 0; p < B; ++p) {
             stats[p].iters = 0;
@@ -1555,6 +1670,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     float* out_d2 = o->nn_d2;
     constexpr const char* kTooMany = "too many pairs for the global search";
     queue_start(g, Rt_io, px, py, pz, s);
+    vicp_grid::Captured& cg = g->reg;
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
                                       (uintptr_t)g->nns_block, (uintptr_t)g->nns_lpq, (uintptr_t)g->fb_grid,
@@ -1567,42 +1683,17 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
         memcpy(&eb, &eps, 8);
         key.push_back((uintptr_t)eb);
         key.push_back((uintptr_t)(g_prof.on ? 1 : 0));
-        if (!g->gexec || key != g->gkey) {
-            g->drop_graph();
-            if (!g->cap_stream) VICP_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            // with timing on, the first attempt records kernel events inside
-            // the graph; if the runtime refuses that, capture without them
-            std::string why;
-            for (int attempt = (g_prof.on ? 0 : 1); attempt < 2 && !g->gexec; ++attempt) {
-                hipGraph_t graph = nullptr;
-                VICP_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-                t_capture_events = attempt == 0 ? &g->gevents : nullptr;
-                if (g->sort_src) queue_plan(g, px, py, pz, g->cap_stream, true);
-                bool queued = true;
-                for (int k = 0; k < K && queued; ++k)
-                    queued = queue_iteration(g, px, py, pz, k, K, early, eps, g->cap_stream, true, all_global, direct,
-                                             out_idx, out_d2);
-                t_capture_events = nullptr;
-                hipError_t ec = hipStreamEndCapture(g->cap_stream, &graph);
-                hipError_t e = ec;
-                if (ec == hipSuccess) {
-                    e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
-                    (void)hipGraphDestroy(graph);
-                }
-                if (e != hipSuccess || !queued) {
-                    (void)hipGetLastError();
-                    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-                    g->gexec = nullptr;
-                    prof_return(g->gevents);
-                    if (!queued) return fail(VICP_ERR_INVALID_ARG, kTooMany);
-                    why = hipGetErrorString(e);
-                }
-            }
-            if (!g->gexec) return fail(VICP_ERR_HIP, "graph capture: " + why);
-            g->gkey = key;
-        }
+        rc = capture_into(g, cg, key, [&](hipStream_t cs) {
+            if (g->sort_src) queue_plan(g, px, py, pz, cs, true);
+            bool queued = true;
+            for (int k = 0; k < K && queued; ++k)
+                queued = queue_iteration(g, px, py, pz, k, K, early, eps, cs, true, all_global, direct, out_idx,
+                                         out_d2);
+            return queued;
+        });
+        if (rc) return rc;
         ProfScope ps("icp_graph", s, false);
-        VICP_HIP(hipGraphLaunch(g->gexec, s));
+        VICP_HIP(hipGraphLaunch(cg.exec, s));
     } else {
         const bool cap = capturing(s);
         if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
@@ -1618,7 +1709,7 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     const unsigned long long* hc = (const unsigned long long*)(hb + g->o_ctr);
     const int32_t* hf = (const int32_t*)(hb + g->o_fb);
     const int32_t* hflags = (const int32_t*)(hb + g->o_flags);
-    if (o->use_graph && g_prof.on) prof_add_graph(g->gevents);
+    if (o->use_graph && g_prof.on) prof_add_graph(cg.events);
     bool nonfinite = false, degenerate = false, internal = false;
     for (int p = 0; p < B; ++p) {
         memcpy(Rt_io + 12 * p, hst[p].Rt, sizeof(double) * 12);
@@ -1642,6 +1733,18 @@ int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py,
     if (nonfinite) return fail(VICP_ERR_NONFINITE, "non-finite source coordinates");
     if (degenerate) return fail(VICP_ERR_DEGENERATE, "a solve kept the previous pose (rank < 2)");
     return VICP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz,
+                          const int64_t* m_per_pair, const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats,
+                          hipStream_t s)
+{
+    (void)hipGetLastError();   // an error left by other code is not ours to report
+    return register_impl(const_cast<vicp_grid*>(gc), px, py, pz, m_per_pair, o, Rt_io, stats, s);
 }
 
 int vicp_register(const vicp_grid* g, const float* px, const float* py, const float* pz, int64_t m,
