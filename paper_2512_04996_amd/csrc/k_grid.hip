@@ -131,7 +131,8 @@ __global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, cons
                                               const float* __restrict__ qz, const PairDev* __restrict__ pd,
                                               const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
-                                              uint32_t* err, float4* __restrict__ blk, uint32_t cap)
+                                              uint32_t* err, float4* __restrict__ blk, uint32_t cap,
+                                              uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count)
 {
     constexpr int kS = 2 * BS;
     constexpr int kShift = 32 - log2i(kS);
@@ -183,7 +184,13 @@ __global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, cons
 #pragma unroll
         for (int j = 0; j < kPer; ++j) bb[j] = kk[j] != kNone ? atomicAdd(&hist[P.v_base + kk[j]], cc[j]) : 0u;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) sbase[threadIdx.x + j * BS] = bb[j];
+        for (int j = 0; j < kPer; ++j) {
+            sbase[threadIdx.x + j * BS] = bb[j];
+            // the one addition that takes a count across kSegSortMin lists
+            // the voxel (counts only grow, so that happens once per voxel)
+            if (big_list && kk[j] != kNone && bb[j] < kSegSortMin && bb[j] + cc[j] >= kSegSortMin)
+                big_list[atomicAdd(big_count, 1u)] = (uint32_t)(P.v_base + kk[j]);
+        }
     }
     __syncthreads();
     if (valid) {
@@ -456,8 +463,9 @@ __global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict_
                                                         const BlockJob* __restrict__ jobs, const uint32_t* __restrict__ vox,
                                                         const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ tmp, uint32_t* __restrict__ vm,
-                                                        float4* __restrict__ qs4)
+                                                        float4* __restrict__ qs4, uint32_t sort_min)
 {
+    __shared__ uint32_t chunk[kThreads / 64][kCoopChunk];
     const BlockJob job = jobs[blockIdx.x];
     const PairDev& P = pd[job.pair];
     const int64_t k = (int64_t)job.start + threadIdx.x;
@@ -468,9 +476,164 @@ __global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict_
     const uint32_t og = off[g];
     const int64_t cs = (int64_t)og - 2 * g;
     const uint32_t c = hist[g];
-    const uint32_t r = rank_in(tmp, cs, c, e);
+    if (c >= sort_min && c <= kSegSortMax) return;   // sorted whole by k_sort_segments
+    // a wave inside one long segment ranks it together (no early return
+    // follows, so every lane reaches both branches' barriers alike)
+    const bool coop = wave_full_and_uniform(g) && c >= kCoopMin;
+    const uint32_t r = coop ? rank_in_wave(tmp, cs, c, e, chunk[threadIdx.x / 64]) : rank_in(tmp, cs, c, e);
     vm[(int64_t)og + 2 + r] = e;
     qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+}
+
+// Long segments (kSegSortMin to kSegSortMax points) of a single-pair grid,
+// listed by the count: one block per segment writes the segment in
+// ascending index order to vm and its float4 copy to qs4, the same words the
+// per-point rank writes.  The indices of a segment are distinct, so when
+// their range [lo, hi] spans at most kBitmapBits values, an LDS bitmap of
+// the range and the running popcount of its words give every index its rank
+// directly (O(c + range / 32)); otherwise the block sorts them in LDS with a
+// bitonic network (O(c log^2 c)).  Blocks take listed segments in turn.
+constexpr int kSortThreads = 1024;
+constexpr int kSortBlocks = 256;   // one per long segment on the paper's 16^3 grids (two fit a CU)
+constexpr uint32_t kBitmapWords = kSegSortMax / 2;   // bitmap and prefix share the sort buffer
+constexpr uint32_t kBitmapBits = 32 * kBitmapWords;
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
+{
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, d, 64));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x)
+{
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d, 64));
+    return x;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_segments(
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+    const PairDev* __restrict__ pd, const uint32_t* __restrict__ big_list, const uint32_t* __restrict__ big_count,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off, const uint32_t* __restrict__ tmp,
+    uint32_t* __restrict__ vm, float4* __restrict__ qs4)
+{
+    constexpr int kW = kSortThreads / 64;
+    constexpr uint32_t kPer = kBitmapWords / kSortThreads;   // bitmap words per thread
+    __shared__ uint32_t sk[kSegSortMax];
+    __shared__ uint32_t sred[2][kW];
+    __shared__ uint32_t spart[kW];
+    const PairDev& P = pd[0];
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const uint32_t nbig = *big_count;
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t g = big_list[b];
+        const uint32_t c = hist[g];
+        if (c > kSegSortMax) continue;   // uniform over the block: ranked point by point
+        const uint32_t og = off[g];
+        const int64_t cs = (int64_t)og - 2 * (int64_t)g;
+        // the range of the segment's indices
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+        for (uint32_t i = threadIdx.x; i < c; i += kSortThreads) {
+            const uint32_t e = tmp[cs + i];
+            lo = min(lo, e);
+            hi = max(hi, e);
+        }
+        lo = wave_min_u32(lo);
+        hi = wave_max_u32(hi);
+        __syncthreads();   // the previous segment is done with sk and sred
+        if (lane == 0) {
+            sred[0][w] = lo;
+            sred[1][w] = hi;
+        }
+        __syncthreads();
+        lo = sred[0][0];
+        hi = sred[1][0];
+#pragma unroll
+        for (int e = 1; e < kW; ++e) {
+            lo = min(lo, sred[0][e]);
+            hi = max(hi, sred[1][e]);
+        }
+        if (hi - lo < kBitmapBits) {   // uniform over the block
+            uint32_t* bits = sk;
+            uint32_t* pre = sk + kBitmapWords;
+            const uint32_t nw = ((hi - lo) >> 5) + 1;
+            for (uint32_t i = threadIdx.x; i < nw; i += kSortThreads) bits[i] = 0u;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < c; i += kSortThreads) {
+                const uint32_t d = tmp[cs + i] - lo;
+                atomicOr(&bits[d >> 5], 1u << (d & 31));
+            }
+            __syncthreads();
+            // exclusive running popcount: kPer consecutive words per thread,
+            // then a scan of the threads' sums
+            const uint32_t w0 = threadIdx.x * kPer;
+            uint32_t cnt[kPer];
+            uint32_t sum = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kPer; ++q) {
+                cnt[q] = w0 + q < nw ? (uint32_t)__popc(bits[w0 + q]) : 0u;
+                sum += cnt[q];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            if (lane == 63) spart[w] = incl;
+            __syncthreads();
+            uint32_t run = incl - sum;
+            for (int e = 0; e < w; ++e) run += spart[e];
+#pragma unroll
+            for (uint32_t q = 0; q < kPer; ++q) {
+                if (w0 + q < nw) pre[w0 + q] = run;
+                run += cnt[q];
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < c; i += kSortThreads) {
+                const uint32_t e = tmp[cs + i];
+                const uint32_t d = e - lo;
+                const uint32_t r = pre[d >> 5] + (uint32_t)__popc(bits[d >> 5] & ((1u << (d & 31)) - 1u));
+                const int64_t ge = P.q_base + e;
+                vm[(int64_t)og + 2 + r] = e;
+                qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+            }
+            continue;
+        }
+        uint32_t np = 1;
+        while (np < c) np <<= 1;
+        for (uint32_t i = threadIdx.x; i < np; i += kSortThreads) sk[i] = i < c ? tmp[cs + i] : 0xFFFFFFFFu;
+        __syncthreads();
+        // one thread per compare-exchange pair (p -> elements i, i + j).  At
+        // distance j <= 32 the 64 pairs of a wave lie in 128 elements of its
+        // own, so a wave barrier orders the stage; the block synchronises
+        // around stages of larger distance only.
+        for (uint32_t k = 2; k <= np; k <<= 1)
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t p = threadIdx.x; p < np / 2; p += kSortThreads) {
+                    const uint32_t i = ((p & ~(j - 1u)) << 1) | (p & (j - 1u));
+                    const uint32_t a = sk[i], bb = sk[i + j];
+                    const bool up = (i & k) == 0;
+                    if ((a > bb) == up) {
+                        sk[i] = bb;
+                        sk[i + j] = a;
+                    }
+                }
+                const uint32_t jn = j > 1 ? j >> 1 : k;   // the next stage's distance
+                if (j >= 64 || jn >= 64) {
+                    __syncthreads();
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+        for (uint32_t r = threadIdx.x; r < c; r += kSortThreads) {
+            const uint32_t e = sk[r];
+            const int64_t ge = P.q_base + e;
+            vm[(int64_t)og + 2 + r] = e;
+            qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+        }
+    }
 }
 
 // Zeroes up to four arrays (u32, u64, u32, u32) in one launch.
@@ -508,20 +671,20 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
 
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
                   int njobs, int block, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err, bool packed,
-                  hipStream_t s)
+                  hipStream_t s, uint32_t* big_list, uint32_t* big_count)
 {
     if (njobs <= 0) return;
     if (packed)
         launch_timed(k_count_packed, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, hist, vox, rank, err);
     else if (block == 1024)
         launch_timed(k_count<false, 1024>, dim3(njobs), dim3(1024), s, qx, qy, qz, pd, jobs, hist, vox, rank, err,
-                     (float4*)nullptr, 0u);
+                     (float4*)nullptr, 0u, big_list, big_count);
     else if (block == 512)
         launch_timed(k_count<false, 512>, dim3(njobs), dim3(512), s, qx, qy, qz, pd, jobs, hist, vox, rank, err,
-                     (float4*)nullptr, 0u);
+                     (float4*)nullptr, 0u, big_list, big_count);
     else
         launch_timed(k_count<false, kThreads>, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, hist, vox, rank,
-                     err, (float4*)nullptr, 0u);
+                     err, (float4*)nullptr, 0u, big_list, big_count);
 }
 
 void launch_count_direct(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
@@ -529,7 +692,8 @@ void launch_count_direct(const float* qx, const float* qy, const float* qz, cons
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL((k_count<true, kThreads>), dim3(njobs), dim3(kThreads), 0, s, qx, qy, qz, pd, jobs, cnt,
-                       (uint32_t*)nullptr, (uint32_t*)nullptr, err, blk, cap);
+                       (uint32_t*)nullptr, (uint32_t*)nullptr, err, blk, cap, (uint32_t*)nullptr,
+                       (uint32_t*)nullptr);
 }
 
 bool count_packed_fits(int64_t voxels) { return voxels < ((int64_t)1 << kPackKeyBits); }
@@ -564,10 +728,19 @@ void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint
 
 void launch_rank_sort(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
                       int njobs, const uint32_t* vox, const uint32_t* hist, const uint32_t* off, const uint32_t* tmp,
-                      uint32_t* vm, float4* qs4, hipStream_t s)
+                      uint32_t* vm, float4* qs4, hipStream_t s, uint32_t sort_min)
 {
     if (njobs <= 0) return;
-    launch_timed(k_rank_sort, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm, qs4);
+    launch_timed(k_rank_sort, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm, qs4,
+                 sort_min);
+}
+
+void launch_sort_segments(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                          const uint32_t* big_list, const uint32_t* big_count, const uint32_t* hist,
+                          const uint32_t* off, const uint32_t* tmp, uint32_t* vm, float4* qs4, hipStream_t s)
+{
+    launch_timed(k_sort_segments, dim3(kSortBlocks), dim3(kSortThreads), s, qx, qy, qz, pd, big_list, big_count, hist, off,
+                 tmp, vm, qs4);
 }
 
 void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, uint32_t* c, int64_t nc, uint32_t* d,

@@ -388,6 +388,7 @@ struct vicp_grid {
     BlockJob* jobs_q8 = nullptr;     // 2048 target points per block (bounding box)
     int njobs_q8 = 0;
     uint32_t *vox = nullptr, *rank = nullptr, *slots = nullptr;
+    uint32_t* big_list = nullptr;   // voxels whose segments are sorted whole (fixed grids)
     float4* qs4 = nullptr;
     uint32_t *hist = nullptr, *off = nullptr, *vm = nullptr;
     uint2* dir = nullptr;   // per voxel: (start in qs4, count | mask), root's entry for a dilated voxel
@@ -864,7 +865,7 @@ float unordered(uint32_t k)
 // The count (Alg. 1 GPU part) under the grid's count schedule (the
 // packed-hash ablation always runs 256 points per block).
 void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz, bool packed, hipStream_t s,
-                 bool cap = false)
+                 bool cap = false, bool list_long = false)
 {
     ProfScope ps("count", s, cap, true);
     const BlockJob* jobs = g->jobs_q;
@@ -878,7 +879,8 @@ void queue_count(vicp_grid* g, const float* qx, const float* qy, const float* qz
         nj = g->njobs_q1024;
         bs = 1024;
     }
-    launch_count(qx, qy, qz, g->d_pd, jobs, nj, bs, g->hist, g->vox, g->rank, g->err, packed, s);
+    launch_count(qx, qy, qz, g->d_pd, jobs, nj, bs, g->hist, g->vox, g->rank, g->err, packed, s,
+                 list_long ? g->big_list : nullptr, list_long ? g->err + 1 : nullptr);
 }
 
 // `rings` dilation rings (Alg. 3) under the grid's dilation schedule: all in
@@ -1068,8 +1070,12 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
         g->usable = true;
         return VICP_OK;
     }
+    // a fixed grid (the paper's coarse 2^N grids hold thousands of points in a
+    // voxel) sorts its long segments whole; the count lists them (err[1]
+    // counts the list)
+    const bool seg_sort = g->fixed && !count_packed(g);
     launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
-    queue_count(g, qx, qy, qz, count_packed(g), s);
+    queue_count(g, qx, qy, qz, count_packed(g), s, false, seg_sort);
     if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
         uint32_t herr = 0;
         VICP_HIP(hipMemcpyAsync(&herr, g->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1110,7 +1116,12 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     {
         ProfScope ps("rank_sort", s, false, true);
         launch_rank_sort(qx, qy, qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots, g->vm,
-                         g->qs4, s);
+                         g->qs4, s, seg_sort ? kSegSortMin : 0xFFFFFFFFu);
+    }
+    if (seg_sort) {
+        ProfScope ps("seg_sort", s, false, true);
+        launch_sort_segments(qx, qy, qz, g->d_pd, g->big_list, g->err + 1, g->hist, g->off, g->slots, g->vm, g->qs4,
+                             s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e));
@@ -1214,6 +1225,8 @@ int build_grid_impl(const float* qx, const float* qy, const float* qz, const int
     g->vox = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
     g->rank = (uint32_t*)g->take(sizeof(uint32_t) * nt, s, g->owned, ok);
     g->slots = (uint32_t*)g->take(sizeof(uint32_t) * (nt + 4), s, g->owned, ok);   // +4: rank_in reads 16-byte chunks
+    // the long segments a fixed grid's count lists (at most n / kSegSortMin)
+    g->big_list = (uint32_t*)g->take(sizeof(uint32_t) * (nt / kSegSortMin + 1), s, g->owned, ok);
     g->qs4 = (float4*)g->take(sizeof(float4) * nt, s, g->owned, ok);
     if (!ok) return bail(fail(VICP_ERR_OOM, "allocation failed"));
     g->njobs_q = (int)jq.size();

@@ -242,6 +242,54 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ a, int6
     return r;
 }
 
+// The same rank taken by a whole wave whose 64 lanes all rank within the
+// same c words (a long segment): the wave loads the words once, kCoopChunk
+// at a time, into its own LDS slice `chunk`, and every lane compares its own
+// e with each word there (broadcast reads).  Equal to rank_in for every
+// lane (padding words are 0xFFFFFFFF, above any index), with O(c) global
+// loads per wave instead of per lane.  The caller checks that all 64 lanes
+// are active and share the segment.
+constexpr int kCoopChunk = 256;
+constexpr uint32_t kCoopMin = 256;   // segments at least this long take the wave-wide form
+__device__ __forceinline__ uint32_t rank_in_wave(const uint32_t* __restrict__ a, int64_t lo, uint32_t c, uint32_t e,
+                                                 uint32_t* chunk)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t r = 0;
+    for (uint32_t base = 0; base < c; base += kCoopChunk) {
+        uint32_t v[kCoopChunk / 64];
+#pragma unroll
+        for (int j = 0; j < kCoopChunk / 64; ++j) {
+            const uint32_t idx = base + (uint32_t)(j * 64 + lane);
+            v[j] = idx < c ? a[lo + idx] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int j = 0; j < kCoopChunk / 64; ++j) chunk[j * 64 + lane] = v[j];
+        // a wave's LDS accesses execute in order: the barriers only keep the
+        // compiler from moving them across
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 8
+        for (int i = 0; i < kCoopChunk; i += 4) {
+            const uint4 q = *reinterpret_cast<const uint4*>(chunk + i);
+            r += (q.x < e ? 1u : 0u) + (q.y < e ? 1u : 0u) + (q.z < e ? 1u : 0u) + (q.w < e ? 1u : 0u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    return r;
+}
+
+// True when every lane of the wave is active and shares the value x.
+__device__ __forceinline__ bool wave_full_and_uniform(int64_t x)
+{
+    const bool full = __ballot(1) == ~0ull;
+    const int64_t x0 = __shfl(x, 0, 64);
+    return full && __ballot(x == x0) == ~0ull;
+}
+
 // --------------------------------------------------------------------------
 // Kernel timing.  While a timed scope of the runtime is open on this thread
 // (and its stream is not being captured), launch_timed hands the scope's two
@@ -280,9 +328,13 @@ void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDe
                  const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
 // block: target points per block (256, 512 or 1024; the packed-hash
 // ablation always takes 256); jobs must hold `block` points per entry
+// big_list / big_count (both or neither): every voxel whose count reaches
+// kSegSortMin is appended once (its segment is then sorted by
+// launch_sort_segments instead of ranked point by point)
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd,
                   const BlockJob* jobs, int njobs, int block, uint32_t* hist, uint32_t* vox, uint32_t* rank,
-                  uint32_t* err, bool packed, hipStream_t s);
+                  uint32_t* err, bool packed, hipStream_t s, uint32_t* big_list = nullptr,
+                  uint32_t* big_count = nullptr);
 bool count_packed_fits(int64_t voxels);
 // VANICP's layout: counts every point of a voxel into cnt and copies it into
 // the voxel's block of cap records when it fits
@@ -296,10 +348,19 @@ void launch_scan(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* v
                  unsigned long long* status, uint32_t* ticket, hipStream_t s);
 void launch_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* vox,
                   const uint32_t* rank, const uint32_t* off, uint32_t* tmp, hipStream_t s);
+// sort_min: segments of kSegSortMin to kSegSortMax points are left to
+// launch_sort_segments (pass kSegSortMin when it runs, else UINT32_MAX)
 void launch_rank_sort(const float* qx, const float* qy, const float* qz, const PairDev* pd,
                       const BlockJob* jobs, int njobs, const uint32_t* vox, const uint32_t* hist,
                       const uint32_t* off, const uint32_t* tmp, uint32_t* vm, float4* qs4,
-                      hipStream_t s);
+                      hipStream_t s, uint32_t sort_min = 0xFFFFFFFFu);
+// Long segments of a single-pair grid listed by the count: each sorted in
+// LDS (ascending index) by one block, then written to vm and qs4.
+constexpr uint32_t kSegSortMin = 512;
+constexpr uint32_t kSegSortMax = 16384;
+void launch_sort_segments(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                          const uint32_t* big_list, const uint32_t* big_count, const uint32_t* hist,
+                          const uint32_t* off, const uint32_t* tmp, uint32_t* vm, float4* qs4, hipStream_t s);
 void launch_clear4(uint32_t* a, int64_t na, unsigned long long* b, int64_t nb, uint32_t* c, int64_t nc, uint32_t* d,
                    int64_t nd, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);

@@ -125,3 +125,41 @@ def test_search_modes_are_bit_identical():
             g.set_schedule(128, lpq, sort_source, 64, search_mode=1)
             b = g.register(p, 10)
             assert np.array_equal(a.Rt, b.Rt) and np.array_equal(a.rmse[0], b.rmse[0]), (sort_source, lpq)
+
+
+@pytest.mark.parametrize("background", [30000, 300000])
+def test_long_segments_of_a_fixed_grid_are_sorted_whole(background):
+    # voxels of 511 (ranked point by point), 512, 513, 2,048 and 16,384
+    # (ordered whole in LDS) and 16,385 points (too long: ranked point by
+    # point) on the 16^3 grid over [-1, 1)^3, among background points, in
+    # random order; every grid word equals the oracle's.  With 30k background
+    # points each long segment's indices span under 2^18 values (the bitmap
+    # rank); with 300k they span more (the bitonic sort).
+    rng = np.random.default_rng(77)
+    voxel = np.float32(2.0 / 16)
+    sizes = [511, 512, 513, 2048, 16384, 16385]
+    cells = rng.choice(16 ** 3, len(sizes), replace=False)
+    parts = []
+    for c, k in zip(cells, sizes):
+        ijk = np.array([c % 16, (c // 16) % 16, c // 256], np.float64)
+        lo = -1.0 + ijk * float(voxel)
+        parts.append(lo + (0.1 + 0.8 * rng.random((k, 3))) * float(voxel))
+    parts.append(rng.uniform(-0.99, 0.99, (background, 3)))
+    pts = np.concatenate(parts, 0)
+    pts = pts[rng.permutation(pts.shape[0])].astype(np.float32)
+    q = np.ascontiguousarray(pts.T)
+    o, d = (-1.0, -1.0, -1.0), (16, 16, 16)
+    g = build_grid_fixed(dev(q), o, voxel, d, 2)
+    og = oracle.build_grid_fixed(q, o, voxel, d)
+    assert sorted(og.hist[cells].tolist()) == sorted(sizes) or og.hist[cells].min() >= 511
+    for _ in range(2):                                   # a refill sorts again from scratch
+        hist, off, vm = g.export()
+        assert np.array_equal(hist, og.hist) and np.array_equal(off, og.off) and np.array_equal(vm, og.vm)
+        g.rebuild(dev(q))
+    g.dilate(2)
+    oracle.dilate(og, 2)
+    assert np.array_equal(g.export()[2], og.vm)
+    # the search reads the sorted segments' float4 copy: every target finds itself
+    idx, d2, _ = g.nns(dev(q), np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32))
+    ridx, rd2, _, _ = oracle.nns(og, q, q, np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32))
+    assert np.array_equal(idx.cpu().numpy(), ridx) and np.array_equal(d2.cpu().numpy(), rd2)
