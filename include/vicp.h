@@ -332,7 +332,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
  * whether the source is bucketed by target voxel before searching (0/1), the
  * number of blocks of the global search, and the candidate loop of a
  * registration's search (search_mode): 0 each lane keeps its best
- * candidate's index and coordinates; 1 (4 or 8 lanes per query) each lane
+ * candidate's index and coordinates; 1 (any lanes per query) each lane
  * keeps its best segment position and the winner's record is read once,
  * fewer instructions per candidate and one more dependent load per query.
  * No setting changes a correspondence or a count.  The lanes per query (a

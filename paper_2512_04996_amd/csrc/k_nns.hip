@@ -691,7 +691,7 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
     const bool one = one_m >= 0;
     // the position-tracking form, for many candidates per query: 4 or 8
     // lanes per query, registration over segments
-    if (mode == 1 && mom && !dcnt && (lpq == 4 || lpq == 8)) {
+    if (mode == 1 && mom && !dcnt) {
 #define VICP_NNS_R(BS, L, SORTED)                                                                                  \
     if (one)                                                                                                       \
         launch_timed(k_nns_local<BS, L, SORTED, true, false, 1, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py,  \
@@ -702,7 +702,12 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
                      pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
                      cap, one_m)
 #define VICP_NNS_RL(BS, SORTED)                                     \
-    if (lpq == 4) VICP_NNS_R(BS, 4, SORTED); else VICP_NNS_R(BS, 8, SORTED);
+    switch (lpq) {                                                  \
+    case 1: VICP_NNS_R(BS, 1, SORTED); break;                       \
+    case 2: VICP_NNS_R(BS, 2, SORTED); break;                       \
+    case 4: VICP_NNS_R(BS, 4, SORTED); break;                       \
+    default: VICP_NNS_R(BS, 8, SORTED); break;                      \
+    }
 #define VICP_NNS_RB(SORTED)                                         \
     switch (block) {                                                \
     case 128: { VICP_NNS_RL(128, SORTED) } break;                   \

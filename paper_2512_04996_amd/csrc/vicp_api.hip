@@ -1943,7 +1943,7 @@ bool sched_valid(const Sched& c)
     return in(c.count_block, {256, 512, 1024}) && in(c.dil_fused, {0, 1}) && c.dil_shape >= 0 &&
            c.dil_shape < kDilateShapes && in(c.ring_block, {64, 128, 256}) && in(c.nns_block, {128, 256, 512}) &&
            in(c.nns_lpq, {1, 2, 4, 8}) && in(c.sort_src, {0, 1}) && c.fb_grid >= 1 && c.fb_grid <= 65536 &&
-           in(c.search_mode, {0, 1}) && (c.search_mode == 0 || c.nns_lpq >= 4);
+           in(c.search_mode, {0, 1});
 }
 
 // Stored schedules by shape: in this process, and in the file named by
@@ -2151,36 +2151,29 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     int best_bs = 256, best_lpq = 4, best_fg = g->fb_grid;
     bool best_sorted = true;
     float best = 1e30f;
+    int best_mode = 0;
     for (int sorted = 0; sorted < 2; ++sorted)
         for (int bs : {128, 256, 512})
-            for (int lpq : {1, 2, 4, 8}) {
-                g->nns_block = bs;
-                g->nns_lpq = lpq;
-                g->sort_src = sorted != 0;
-                g->search_mode = 0;
-                const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
-                                (sorted ? plan_ms / (float)searches_per_plan : 0.0f);
-                if (t < kMargin * best) {
-                    best = t;
-                    best_bs = bs;
-                    best_lpq = lpq;
-                    best_sorted = sorted != 0;
+            for (int lpq : {1, 2, 4, 8})
+                for (int mode = 0; mode < 2; ++mode) {
+                    g->nns_block = bs;
+                    g->nns_lpq = lpq;
+                    g->sort_src = sorted != 0;
+                    g->search_mode = mode;
+                    const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
+                                    (sorted ? plan_ms / (float)searches_per_plan : 0.0f);
+                    if (t < kMargin * best) {
+                        best = t;
+                        best_bs = bs;
+                        best_lpq = lpq;
+                        best_sorted = sorted != 0;
+                        best_mode = mode;
+                    }
                 }
-            }
     g->nns_block = best_bs;
     g->nns_lpq = best_lpq;
     g->sort_src = best_sorted;
-    g->search_mode = 0;
-    if (best_lpq >= 4) {
-        // many candidates per query: try the position-tracking search
-        g->search_mode = 1;
-        const float t = timed([&] { queue_search(g, px, py, pz, nullptr, nullptr, s, true, true); }) +
-                        (best_sorted ? plan_ms / (float)searches_per_plan : 0.0f);
-        if (t < kMargin * best)
-            best = t;
-        else
-            g->search_mode = 0;
-    }
+    g->search_mode = best_mode;
     // (4) the global search's blocks: the fold every iteration runs, plus a
     // listed-query load once per bucketing pass
     {
@@ -2265,8 +2258,6 @@ int vicp_set_schedule(vicp_grid* g, int32_t nns_block, int32_t lanes_per_query, 
         return fail(VICP_ERR_INVALID_ARG, "lanes_per_query must be 1, 2, 4 or 8");
     if (fallback_grid < 1 || fallback_grid > 65536) return fail(VICP_ERR_INVALID_ARG, "fallback_grid out of range");
     if (search_mode < 0 || search_mode > 1) return fail(VICP_ERR_INVALID_ARG, "search_mode must be 0 or 1");
-    if (search_mode == 1 && lanes_per_query < 4)
-        return fail(VICP_ERR_INVALID_ARG, "search_mode 1 needs 4 or 8 lanes per query");
     g->search_mode = search_mode;
     g->nns_block = nns_block;
     g->nns_lpq = lanes_per_query;

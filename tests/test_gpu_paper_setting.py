@@ -119,7 +119,7 @@ def test_search_modes_are_bit_identical():
     g = build_grid_fixed(dev(P.q), o, P.voxel, d, P.rings).dilate(P.rings)
     p = dev(P.p)
     for sort_source in (True, False):
-        for lpq in (4, 8):
+        for lpq in (1, 2, 4, 8):
             g.set_schedule(128, lpq, sort_source, 64, search_mode=0)
             a = g.register(p, 10)
             g.set_schedule(128, lpq, sort_source, 64, search_mode=1)

@@ -428,16 +428,11 @@ def test_schedules_are_result_invariant(sort_source, nns_block, lpq):
     assert np.array_equal(idx.cpu().numpy(), ref_idx) and np.array_equal(d2.cpu().numpy(), ref_d2)
     assert int(fb.cpu()[0]) == ref_F
     r = g.register(p, 6)
-    if lpq >= 4:
-        # the position-tracking search picks the same winners: bit-identical
-        g.set_schedule(nns_block, lpq, sort_source, 64, search_mode=1)
-        rr = g.register(p, 6)
-        assert np.array_equal(rr.Rt, r.Rt) and np.array_equal(rr.rmse[0], r.rmse[0])
-        assert np.array_equal(rr.candidates[0], r.candidates[0])
-    else:
-        with pytest.raises(VicpError) as e:
-            g.set_schedule(nns_block, lpq, sort_source, 64, search_mode=1)
-        assert e.value.code == ERR_INVALID_ARG
+    # the position-tracking search picks the same winners: bit-identical
+    g.set_schedule(nns_block, lpq, sort_source, 64, search_mode=1)
+    rr = g.register(p, 6)
+    assert np.array_equal(rr.Rt, r.Rt) and np.array_equal(rr.rmse[0], r.rmse[0])
+    assert np.array_equal(rr.candidates[0], r.candidates[0])
     with pytest.raises(VicpError) as e:
         g.set_schedule(nns_block, lpq, sort_source, 64, search_mode=2)
     assert e.value.code == ERR_INVALID_ARG

@@ -7,7 +7,7 @@ Each case runs the full loop of Sec. II.A on the GPU and in the oracle, then
 compares the last iteration's nearest-neighbour index and squared distance of
 every source point, the per-iteration global-search counts, the RMSE history
 (1e-9 relative) and the final pose (1e-5 rad, 1e-6 x extent).  Schedules:
-the autotuned one and both candidate loops (search_mode 0 and 1, 4 and 8
+the autotuned one and both candidate loops (search_mode 0 and 1, 1 to 8
 lanes per query, bucketed and not), eager and graph-replayed; on sources
 shorter than one wave's queries and with ragged tails; with global
 searches in the compared iteration (listed queries resolved by the exact
@@ -82,6 +82,8 @@ SCHEDULES = [
     (512, 8, True, 256, 0),
     (128, 2, True, 64, 0),
     (256, 1, False, 64, 0),
+    (128, 2, True, 1024, 1),
+    (256, 1, False, 64, 1),
 ]
 
 
