@@ -41,15 +41,17 @@ KERNEL_SRC_DIL = os.path.join(ROOT, "paper_2512_04996_amd", "csrc", "k_dilate.hi
 
 
 def counter_traffic(pmc_path, src_path, kernel):
-    """HBM bytes per launch from a stored FETCH_SIZE + WRITE_SIZE summary, or
-    None when the kernel variant or its source changed since it was taken."""
+    """HBM bytes per launch of this kernel variant from a stored FETCH_SIZE +
+    WRITE_SIZE summary, or None when the variant is not in it or its source
+    changed since the counters were taken."""
     if not os.path.exists(pmc_path):
         return None
     pmc = json.load(open(pmc_path))
     src_hash = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
-    if pmc.get("kernel_source_sha256") == src_hash and pmc.get("kernel") == kernel:
-        return pmc.get("hbm_bytes_per_launch")
-    return None
+    if pmc.get("kernel_source_sha256") != src_hash:
+        return None
+    v = pmc.get("variants", {}).get(kernel)
+    return None if v is None else v.get("hbm_bytes_per_launch")
 
 
 def log(msg):

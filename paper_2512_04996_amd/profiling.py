@@ -3,11 +3,13 @@
     python -m paper_2512_04996_amd.profiling stats KERNEL_STATS_CSV OUT_MD --command "..."
         -> a short markdown table of per-kernel durations (average, calls, share)
 
-    python -m paper_2512_04996_amd.profiling traffic --fetch DIR --write DIR --kernel k_nns_local
-           --copy-mib N --out OUT_JSON --command "..."
-        -> HBM bytes per launch of a kernel from FETCH_SIZE / WRITE_SIZE counter
-           runs, each scaled by what the same counter reads for a plain copy of
-           N MiB (the bytes a copy must move are known exactly)
+    python -m paper_2512_04996_amd.profiling traffic --fetch DIR [DIR...] --write DIR [DIR...]
+           --kernel NAME [NAME...] --copy-mib N --out OUT_JSON --command "..."
+        -> HBM bytes per launch of each named kernel from FETCH_SIZE / WRITE_SIZE
+           counter runs, each scaled by what the same counter reads for a plain
+           copy of N MiB (the bytes a copy must move are known exactly); one
+           entry per kernel under "variants" (several runs may be given, e.g.
+           one per schedule, each ending with its own copy)
 
     python -m paper_2512_04996_amd.profiling counters DIR [DIR...] --kernels NAME... --out OUT_MD --command "..."
         -> per-kernel medians of every counter collected in the given runs
@@ -75,14 +77,18 @@ def _per_dispatch(rows, counter: str):
 
 
 def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_mib: float) -> dict:
+    """One kernel's HBM bytes per launch from one FETCH_SIZE and one
+    WRITE_SIZE run, or None when the runs hold no dispatch of it."""
     copy_bytes = copy_mib * 2 ** 20
     out = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = _per_dispatch(_counter_rows(d), counter)
         kv = [v for k, v in per.values() if kernel in k]
         cv = [v for k, v in per.values() if "copyBuffer" in k]
-        if not kv or not cv:
-            raise RuntimeError(f"{counter}: kernel dispatches {len(kv)}, copy dispatches {len(cv)}")
+        if not kv:
+            return None
+        if not cv:
+            raise RuntimeError(f"{counter}: no calibration copy in {d}")
         copy_reading = max(cv)                     # the large calibration copy
         scale = copy_bytes / (copy_reading * 1024.0)
         out[counter] = {"kernel_kib_per_dispatch": statistics.median(kv), "dispatches": len(kv),
@@ -130,9 +136,9 @@ def main(argv=None):
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="Kernel durations (rocprofv3 --kernel-trace --stats)")
     t = sub.add_parser("traffic")
-    t.add_argument("--fetch", required=True)
-    t.add_argument("--write", required=True)
-    t.add_argument("--kernel", required=True)
+    t.add_argument("--fetch", nargs="+", required=True)
+    t.add_argument("--write", nargs="+", required=True)
+    t.add_argument("--kernel", nargs="+", required=True)
     t.add_argument("--copy-mib", type=float, required=True)
     t.add_argument("--source", default=os.path.join(HERE, "csrc", "k_nns.hip"))
     t.add_argument("--out", required=True)
@@ -152,10 +158,20 @@ def main(argv=None):
         with open(a.out, "w") as f:
             f.write(f"# {a.title}\n\n" + stats_table(a.csv, a.command))
     else:
-        res = traffic(a.fetch, a.write, a.kernel, a.copy_mib)
-        res["kernel"] = a.kernel
-        res["kernel_source_sha256"] = hashlib.sha256(open(a.source, "rb").read()).hexdigest()
-        res["command"] = a.command
+        if len(a.fetch) != len(a.write):
+            raise SystemExit("give one --write run per --fetch run")
+        variants = {}
+        for fd, wd in zip(a.fetch, a.write):
+            for k in a.kernel:
+                r = traffic(fd, wd, k, a.copy_mib)
+                if r is not None and k not in variants:
+                    variants[k] = r
+        missing = [k for k in a.kernel if k not in variants]
+        if missing:
+            raise SystemExit(f"no dispatch of {missing} in the given runs")
+        res = {"variants": variants,
+               "kernel_source_sha256": hashlib.sha256(open(a.source, "rb").read()).hexdigest(),
+               "command": a.command}
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)
     return 0
