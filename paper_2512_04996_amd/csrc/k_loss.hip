@@ -88,6 +88,7 @@ __global__ void k_se3(const double* __restrict__ xi, int npairs, PairState* __re
         S.Rtf[9 + i] = (float)t;
     }
     S.done = 0;
+    S.rot_ok = 0;
     // Qm = 1/2 P + c (F P + P F + F P F) + e (F F P + P F F - 3 F P F) + f (F P F F + F F P F)
     double Pm[3][3], FP[3][3], PF[3][3], FPF[3][3], FFP[3][3], PFF[3][3], FPFF[3][3], FFPF[3][3];
     skew(rho, Pm);

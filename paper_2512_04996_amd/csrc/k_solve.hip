@@ -149,67 +149,101 @@ __host__ __device__ bool polar3(const double A[3][3], double Q[3][3])
     return false;
 }
 
+// 1/x in the float64 solve.  On the device: the hardware reciprocal refined
+// by two Newton steps, a chain of five operations instead of the ten or so
+// of a correctly rounded division (the result is within an ulp or two; the
+// solve is compared within tolerance).  On the host: a division.
+__host__ __device__ __forceinline__ double recip(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+// Roughly 1/sqrt(x), for a scale factor whose exact value does not matter.
+__host__ __device__ __forceinline__ double rough_rsqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsq(x);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+
+// True when the rotation part of Q (row-major 3x3) is orthogonal to 1e-12.
+__host__ __device__ bool rot_orthogonal(const double* Q)
+{
+    double orth = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) {
+            const double d = Q[i] * Q[j] + Q[3 + i] * Q[3 + j] + Q[6 + i] * Q[6 + j] - (i == j ? 1.0 : 0.0);
+            orth = fmax(orth, fabs(d));
+        }
+    return orth < 1e-12;
+}
+
 // Orthogonal polar factor of A refined from a nearby rotation Q0 (the
-// previous pose's rotation): with M = R^T A, the rotation increment exp([w]x)
-// that makes M symmetric solves (tr(S) I - S) w = 2 axial(skew M) to first
-// order, S = sym(M); it is applied as the Cayley rotation of w (exactly
-// orthogonal), and the step repeats until |w| < 1e-8 (the error then is at
-// rounding: the convergence is quadratic).  Accepted only if the final S is
-// positive definite (so R is the polar factor, not another stationary point)
-// and Q0 was orthogonal; otherwise returns false.
-__host__ __device__ bool polar_refine(const double A[3][3], double fro, const double Q0[3][3], double Q[3][3])
+// previous pose's rotation, orthogonal): with M = R^T A, the rotation
+// increment exp([w]x) that makes M symmetric solves (tr(S) I - S) w =
+// 2 axial(skew M) to first order, S = sym(M); it is applied as the Cayley
+// rotation of w (exactly orthogonal), and the step repeats until |w| < 1e-8
+// (the error then is at rounding: the convergence is cubic, two steps from
+// the previous pose of an ICP iteration).  A is scaled by any positive
+// factor (the polar factor does not change) to keep the products of order
+// one.  Accepted only if the final S is positive definite (so R is the polar
+// factor, not another stationary point); otherwise returns false.
+__host__ __device__ bool polar_refine(const double A[3][3], double scale, const double Q0[3][3], double Q[3][3])
 {
     // float64 only and compared within tolerance: fused multiply-adds allowed
     // (the float32 search keeps every rounding as written)
 #pragma clang fp contract(fast)
     double R[3][3], An[3][3];
-    double orth = 0.0;
-    const double ifro = 1.0 / fro;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             R[i][j] = Q0[i][j];
-            An[i][j] = A[i][j] * ifro;
-            const double d = Q0[0][i] * Q0[0][j] + Q0[1][i] * Q0[1][j] + Q0[2][i] * Q0[2][j] - (i == j ? 1.0 : 0.0);
-            orth = fmax(orth, fabs(d));
+            An[i][j] = A[i][j] * scale;
         }
-    if (!(orth < 1e-12)) return false;
+#pragma unroll 1
     for (int it = 0; it < 8; ++it) {
         double M[3][3];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) M[i][j] = R[0][i] * An[0][j] + R[1][i] * An[1][j] + R[2][i] * An[2][j];
-        double S[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) S[i][j] = 0.5 * (M[i][j] + M[j][i]);
+        const double s00 = M[0][0], s11 = M[1][1], s22 = M[2][2];
+        const double s01 = 0.5 * (M[0][1] + M[1][0]), s02 = 0.5 * (M[0][2] + M[2][0]), s12 = 0.5 * (M[1][2] + M[2][1]);
         const double k[3] = {M[2][1] - M[1][2], M[0][2] - M[2][0], M[1][0] - M[0][1]};   // 2 axial(skew M)
-        const double tr = S[0][0] + S[1][1] + S[2][2];
         // T = tr(S) I - S is symmetric: w = adj(T) k / det T
-        const double t00 = tr - S[0][0], t11 = tr - S[1][1], t22 = tr - S[2][2];
-        const double t01 = -S[0][1], t02 = -S[0][2], t12 = -S[1][2];
-        const double a00 = t11 * t22 - t12 * t12, a01 = t02 * t12 - t01 * t22, a02 = t01 * t12 - t02 * t11;
-        const double a11 = t00 * t22 - t02 * t02, a12 = t01 * t02 - t00 * t12, a22 = t00 * t11 - t01 * t01;
-        const double dT = t00 * a00 + t01 * a01 + t02 * a02;
+        const double t00 = s11 + s22, t11 = s00 + s22, t22 = s00 + s11;
+        const double a00 = t11 * t22 - s12 * s12, a01 = s02 * s12 + s01 * t22, a02 = s01 * s12 + s02 * t11;
+        const double a11 = t00 * t22 - s02 * s02, a12 = s01 * s02 + t00 * s12, a22 = t00 * t11 - s01 * s01;
+        const double dT = t00 * a00 - s01 * a01 - s02 * a02;
         if (!(dT > 0.0)) return false;
-        const double idT = 1.0 / dT;
-        const double w[3] = {(a00 * k[0] + a01 * k[1] + a02 * k[2]) * idT, (a01 * k[0] + a11 * k[1] + a12 * k[2]) * idT,
-                             (a02 * k[0] + a12 * k[1] + a22 * k[2]) * idT};
-        const double w2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-        // Cayley rotation of w: I + 2/(1 + |h|^2) (H + H^2), h = w / 2, H = [h]x
-        const double h[3] = {0.5 * w[0], 0.5 * w[1], 0.5 * w[2]};
-        const double f = 2.0 / (1.0 + 0.25 * w2);
-        const double Hm[3][3] = {{0.0, -h[2], h[1]}, {h[2], 0.0, -h[0]}, {-h[1], h[0], 0.0}};
-        double D[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const double hh = Hm[i][0] * Hm[0][j] + Hm[i][1] * Hm[1][j] + Hm[i][2] * Hm[2][j];
-                D[i][j] = (i == j ? 1.0 : 0.0) + f * (Hm[i][j] + hh);
-            }
+        const double idT = recip(dT);
+        const double w0 = (a00 * k[0] + a01 * k[1] + a02 * k[2]) * idT;
+        const double w1 = (a01 * k[0] + a11 * k[1] + a12 * k[2]) * idT;
+        const double w2 = (a02 * k[0] + a12 * k[1] + a22 * k[2]) * idT;
+        const double ww = w0 * w0 + w1 * w1 + w2 * w2;
+        // Cayley rotation of w with h = w / 2: I + f ([h]x + h h^T - |h|^2 I),
+        // f = 2 / (1 + |h|^2)
+        const double h0 = 0.5 * w0, h1 = 0.5 * w1, h2 = 0.5 * w2;
+        const double f = 2.0 * recip(1.0 + 0.25 * ww);
+        const double h01 = h0 * h1, h02 = h0 * h2, h12 = h1 * h2;
+        const double D[3][3] = {{1.0 - f * (h1 * h1 + h2 * h2), f * (h01 - h2), f * (h02 + h1)},
+                                {f * (h01 + h2), 1.0 - f * (h0 * h0 + h2 * h2), f * (h12 - h0)},
+                                {f * (h02 - h1), f * (h12 + h0), 1.0 - f * (h0 * h0 + h1 * h1)}};
         double Rn[3][3];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) Rn[i][j] = R[i][0] * D[0][j] + R[i][1] * D[1][j] + R[i][2] * D[2][j];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) R[i][j] = Rn[i][j];
-        if (w2 < 1e-16) {
-            const bool pd = S[0][0] > 0.0 && S[0][0] * S[1][1] - S[0][1] * S[0][1] > 0.0 && det3(S) > 0.0;
+        if (ww < 1e-16) {
+            // S positive definite: its leading minors are positive
+            const bool pd = s00 > 0.0 && s00 * s11 - s01 * s01 > 0.0 &&
+                            s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) +
+                                    s02 * (s01 * s12 - s11 * s02) > 0.0;
             if (!pd) return false;
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) Q[i][j] = R[i][j];
@@ -225,7 +259,11 @@ __host__ __device__ bool polar_refine(const double A[3][3], double fro, const do
 // or below the rounding floor of the one-pass sums, 1e-13 sqrt(sum|p|^2 sum|q|^2)
 // (taken about c), so that a cross-covariance made of rounding noise (e.g.
 // every correspondence on one target point) never yields a rotation.
-__host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12], const double* Rprev)
+// Rprev (row-major, may be null): the previous rotation, from which the polar
+// factor is refined; prev_orth says it is known to be orthogonal (a previous
+// solve's result), otherwise it is checked here.
+__host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[12], const double* Rprev,
+                                bool prev_orth)
 {
     // float64 only and compared within tolerance: fused multiply-adds allowed
     // (the float32 search keeps every rounding as written)
@@ -233,36 +271,38 @@ __host__ __device__ bool kabsch(const double* mom, const double c[3], double Rt[
     const double m = mom[18];
     if (!(m > 0.0)) return false;
     double pb[3], qb[3], H[3][3];
-    const double im = 1.0 / m;
+    const double im = recip(m);
     for (int a = 0; a < 3; ++a) {
         pb[a] = mom[a] * im;
         qb[a] = mom[3 + a] * im;
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) H[a][b] = mom[6 + 3 * a + b] - m * pb[a] * qb[b];
-    const double floor_ = 1e-13 * sqrt(mom[15] * mom[16]);
+    const double pq = mom[15] * mom[16];
     double R[3][3];
     // R = V U^T is the orthogonal polar factor of H^T (H^T = V S U^T =
     // (V U^T)(U S U^T)); when H is far above the rounding floor and det H is
     // clearly positive, no reflection fix is needed: the polar factor is
-    // refined from the previous rotation (Rprev, row-major, may be null), or
-    // else taken by the Newton polar iteration
+    // refined from the previous rotation, or else taken by the Newton polar
+    // iteration.  The tests ||H|| > 1e6 floor and det H > 1e-6 ||H||^3 are
+    // taken on squares (no square root on the way to the refinement).
     double Ht[3][3], nh = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             Ht[i][j] = H[j][i];
             nh += H[i][j] * H[i][j];
         }
-    const double fro = sqrt(nh);
-    const bool well = fro > 1e6 * floor_ && det3(Ht) > 1e-6 * nh * fro;
+    const double dH = det3(Ht);
+    const bool well = nh > 1e-14 * pq && dH > 0.0 && dH * dH > 1e-12 * nh * nh * nh;
     bool fast = false;
-    if (well && Rprev) {
+    if (well && Rprev && (prev_orth || rot_orthogonal(Rprev))) {
         const double Q0[3][3] = {{Rprev[0], Rprev[1], Rprev[2]}, {Rprev[3], Rprev[4], Rprev[5]},
                                  {Rprev[6], Rprev[7], Rprev[8]}};
-        fast = polar_refine(Ht, fro, Q0, R);
+        fast = polar_refine(Ht, rough_rsqrt(nh), Q0, R);
     }
     if (well && !fast) fast = polar3(Ht, R);
     if (!fast) {
+        const double floor_ = 1e-13 * sqrt(pq);
         double U[3][3], sig[3], V[3][3];
         svd3(H, U, sig, V);
         if (!(sig[0] > 0.0) || sig[1] <= 1e-12 * sig[0] || sig[1] <= floor_) return false;
@@ -458,12 +498,13 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     double Rt[12];   // written by kabsch only when it succeeds
     const double m = tot[18];
     const double rmse = m > 0.0 ? sqrt(tot[17] / m) : 0.0;
-    const bool ok = kabsch(tot, cen, Rt, Rp);
+    const bool ok = kabsch(tot, cen, Rt, Rp, S.rot_ok != 0);
     if (ok) {
         for (int j = 0; j < 12; ++j) {
             S.Rt[j] = Rt[j];
             S.Rtf[j] = (float)Rt[j];
         }
+        S.rot_ok = 1;
     } else {
         S.degenerate += 1;
     }
@@ -502,6 +543,7 @@ __device__ __forceinline__ void set_state_one(const PairDev* __restrict__ pd, Pa
     S.iters = 0;
     S.degenerate = 0;
     S.status = 0;
+    S.rot_ok = 0;   // a caller's rotation: the first solve checks it
 }
 
 // The poses travel in the launch's arguments (up to kInlinePairs pairs).

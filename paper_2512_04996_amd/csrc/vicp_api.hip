@@ -1514,6 +1514,7 @@ __global__ void k_noalloc_setup(NaSetup a, int32_t njobs, int32_t qpb, int32_t n
         S.iters = 0;
         S.degenerate = 0;
         S.status = 0;
+        S.rot_ok = 0;
         int32_t* cnt = reinterpret_cast<int32_t*>(base + kNaOffCnt);
         cnt[0] = 0;   // global-search count
         cnt[1] = 0;   // fault flags

@@ -126,6 +126,7 @@ struct PairState {
     int32_t iters;
     int32_t degenerate;
     int32_t status;     // latched device faults (bit 0: non-finite source)
+    int32_t rot_ok;     // Rt's rotation is a solve's result (orthogonal to rounding)
 };
 
 // --------------------------------------------------------------------------

@@ -12,11 +12,11 @@ bool vicp::prof_take_ext_events(hipEvent_t*, hipEvent_t*) { return false; }
 
 extern "C" int vicp_test_kabsch(const double* mom, const double* c, double* Rt)
 {
-    return vicp::kabsch(mom, c, Rt, nullptr) ? 1 : 0;
+    return vicp::kabsch(mom, c, Rt, nullptr, false) ? 1 : 0;
 }
 
 // The same, with the polar factor refined from a given starting rotation.
 extern "C" int vicp_test_kabsch_from(const double* mom, const double* c, const double* Rprev, double* Rt)
 {
-    return vicp::kabsch(mom, c, Rt, Rprev) ? 1 : 0;
+    return vicp::kabsch(mom, c, Rt, Rprev, false) ? 1 : 0;
 }
