@@ -46,12 +46,15 @@ __device__ __forceinline__ bool voxel_id(const PairDev& P, float x, float y, flo
 }
 
 // --------------------------------------------------------------------------
-// bounding box per pair: box[8 p + 0..2] = ordered min, [3..5] = ordered max,
-// [6] = non-finite flag
+// bounding box partial per block: box[8 b + 0..2] = ordered min, [3..5] =
+// ordered max, [6] = non-finite flag, [7] = the build's tag.  box is host
+// memory mapped for the device: the host waits for the tags instead of a
+// copy and a stream synchronisation.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx, const float* __restrict__ qy,
                                                    const float* __restrict__ qz, const PairDev* __restrict__ pd,
-                                                   const BlockJob* __restrict__ jobs, int items, uint32_t* box)
+                                                   const BlockJob* __restrict__ jobs, int items, uint32_t* box,
+                                                   uint32_t tag)
 {
     __shared__ uint32_t red[7][kThreads / kWave];
     const BlockJob job = jobs[blockIdx.x];
@@ -100,13 +103,19 @@ __global__ __launch_bounds__(kThreads) void k_aabb(const float* __restrict__ qx,
     }
     __syncthreads();
     // one partial per block (no atomics: same-address atomics from many
-    // blocks serialise across the XCDs); the host, which reads the box back
-    // anyway, combines the partials per pair
-    if (threadIdx.x < 7) {
-        uint32_t r = red[threadIdx.x][0];
-        for (int k = 1; k < kThreads / kWave; ++k)
-            r = (threadIdx.x < 3) ? min(r, red[threadIdx.x][k]) : max(r, red[threadIdx.x][k]);
-        box[8 * (int64_t)blockIdx.x + threadIdx.x] = r;
+    // blocks serialise across the XCDs); the host, which needs the box
+    // anyway, combines the partials per pair.  One thread writes the seven
+    // values, then, after a system-scope fence (the host must never see the
+    // tag before the values), the tag.
+    if (threadIdx.x == 0) {
+        uint32_t* out = box + 8 * (int64_t)blockIdx.x;
+        for (int f = 0; f < 7; ++f) {
+            uint32_t r = red[f][0];
+            for (int k = 1; k < kThreads / kWave; ++k) r = (f < 3) ? min(r, red[f][k]) : max(r, red[f][k]);
+            out[f] = r;
+        }
+        __threadfence_system();
+        __hip_atomic_store(out + 7, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -663,10 +672,10 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 }  // namespace
 
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
-                 int njobs, int items_per_block, uint32_t* box, hipStream_t s)
+                 int njobs, int items_per_block, uint32_t* box, uint32_t tag, hipStream_t s)
 {
     if (njobs <= 0) return;
-    launch_timed(k_aabb, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, items_per_block, box);
+    launch_timed(k_aabb, dim3(njobs), dim3(kThreads), s, qx, qy, qz, pd, jobs, items_per_block, box, tag);
 }
 
 void launch_count(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,

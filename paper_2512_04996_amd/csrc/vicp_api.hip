@@ -52,6 +52,50 @@ __global__ void k_upload(Blob b, uint32_t* dst, int nwords)
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = b.w[i];
 }
 
+// Zeroes up to four arrays (u32, u64, u32, u32) and writes one blob, in one
+// launch.
+__global__ void k_clear4_blob(Blob blob, uint32_t* __restrict__ dst, int nwords, uint32_t* __restrict__ a, int64_t na,
+                              unsigned long long* __restrict__ b, int64_t nb, uint32_t* __restrict__ c, int64_t nc,
+                              uint32_t* __restrict__ d, int64_t nd, int64_t n)
+{
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = blob.w[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < na) a[i] = 0u;
+        if (i < nb) b[i] = 0ull;
+        if (i < nc) c[i] = 0u;
+        if (i < nd) d[i] = 0u;
+    }
+}
+
+void launch_clear4_blob(const Blob& blob, uint32_t* dst, int nwords, uint32_t* a, int64_t na, unsigned long long* b,
+                        int64_t nb, uint32_t* c, int64_t nc, uint32_t* d, int64_t nd, hipStream_t s)
+{
+    const int64_t n = std::max(std::max(na, nb), std::max(nc, nd));
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_clear4_blob, dim3(blocks), dim3(256), 0, s, blob, dst, nwords, a, na, b, nb, c, nc, d, nd, n);
+}
+
+// Waits until each of the nblocks bounding-box partials in pinned host
+// memory carries the tag (the box kernel writes it after the values).  Spins
+// on the host for up to two seconds (no stream synchronisation, whose
+// wake-up is slower), then synchronises the stream and looks once more.
+hipError_t wait_box_tags(const uint32_t* box, int nblocks, uint32_t tag, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int next = 0;
+    for (;;) {
+        while (next < nblocks && __atomic_load_n(&box[8 * (size_t)next + 7], __ATOMIC_ACQUIRE) == tag) ++next;
+        if (next == nblocks) return hipSuccess;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (; next < nblocks; ++next)
+        if (__atomic_load_n(&box[8 * (size_t)next + 7], __ATOMIC_ACQUIRE) != tag) return hipErrorUnknown;
+    return hipSuccess;
+}
+
 void upload(const void* host, size_t bytes, void* dst, hipStream_t s)
 {
     const uint32_t* src = (const uint32_t*)host;
@@ -377,7 +421,6 @@ struct vicp_grid {
     std::vector<Buf> vbufs;     // sized by the voxel counts (change when a rebuild changes V)
 
     PairDev* d_pd = nullptr;
-    uint32_t* box = nullptr;
     uint32_t* err = nullptr;
     BlockJob* jobs_q = nullptr;      // 256 target points per block
     int njobs_q = 0;
@@ -424,7 +467,12 @@ struct vicp_grid {
     size_t o_rmse = 0, o_ctr = 0, o_fb = 0, o_deg = 0, o_flags = 0;
     void* h_res = nullptr;
     size_t h_res_cap = 0;
-    uint32_t* h_box = nullptr;   // pinned: per-block bounding-box partials read back by each build
+    // pinned host memory mapped for the device: the per-block bounding-box
+    // partials, each tagged with its build's number (box_gen)
+    uint32_t* h_box = nullptr;
+    uint32_t* d_box = nullptr;
+    uint32_t box_gen = 0;
+    std::vector<PairDev> h_pd;   // the pair records of the last refill, written by its first launch
     // a given grid geometry (single pair) instead of the target's padded box
     bool fixed = false;
     bool usable = true;   // false after a build whose target did not fit the given grid
@@ -921,18 +969,27 @@ int grid_fill_host(vicp_grid* g, const float* qx, const float* qy, const float* 
         Vt = pairs[0].V;
         words = pairs[0].n + 2 * pairs[0].V;
     } else {
+    const size_t nbox = 8 * (size_t)g->njobs_q8;
+    if (!g->h_box && nbox) {
+        if (hipHostMalloc((void**)&g->h_box, sizeof(uint32_t) * nbox, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess) {
+            g->h_box = nullptr;
+            return fail(VICP_ERR_OOM, "pinned host allocation failed");
+        }
+        memset(g->h_box, 0, sizeof(uint32_t) * nbox);   // no tag is 0
+        if (hipHostGetDevicePointer((void**)&g->d_box, g->h_box, 0) != hipSuccess) {
+            (void)hipHostFree(g->h_box);
+            g->h_box = nullptr;
+            return fail(VICP_ERR_HIP, "pinned host memory not mapped for the device");
+        }
+    }
+    if (++g->box_gen == 0) g->box_gen = 1;
     {
         ProfScope ps("aabb", s, false, true);
-        launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->box, s);
+        launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->d_box, g->box_gen, s);
     }
-    const size_t nbox = 8 * (size_t)g->njobs_q8;
-    if (!g->h_box && nbox &&
-        hipHostMalloc((void**)&g->h_box, sizeof(uint32_t) * nbox, hipHostMallocDefault) != hipSuccess) {
-        g->h_box = nullptr;
-        return fail(VICP_ERR_OOM, "pinned host allocation failed");
-    }
-    if (nbox) VICP_HIP(hipMemcpyAsync(g->h_box, g->box, sizeof(uint32_t) * nbox, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipStreamSynchronize(s));
+    VICP_HIP(hipGetLastError());
+    if (nbox) VICP_HIP(wait_box_tags(g->h_box, g->njobs_q8, g->box_gen, s));
     // per pair: min of the block minima, max of the block maxima, any
     // non-finite flag (a pair with no points keeps the empty box)
     std::vector<uint32_t> hbox(8 * (size_t)B);
@@ -1018,10 +1075,26 @@ int grid_fill_host(vicp_grid* g, const float* qx, const float* qy, const float* 
                                         hipMemcpyHostToDevice, s));
         }
     }
-    std::vector<PairDev> pd;
-    fill_pairdev(g, pd);
-    upload(pd.data(), sizeof(PairDev) * B, g->d_pd, s);
+    fill_pairdev(g, g->h_pd);
     return VICP_OK;
+}
+
+// The first launch of a refill's device part: zeroes the histogram, the
+// scan's tile states, its tickets and the error words, and writes the pair
+// records when they fit the launch (else a separate upload first).
+void clear_for_build(vicp_grid* g, hipStream_t s)
+{
+    const int64_t Vt = g->V_total;
+    const size_t bytes = sizeof(PairDev) * g->h_pd.size();
+    if (bytes <= sizeof(Blob)) {
+        Blob b;
+        memcpy(b.w, g->h_pd.data(), bytes);
+        launch_clear4_blob(b, (uint32_t*)g->d_pd, (int)(bytes / 4), g->hist, Vt, g->scan_status, scan_tiles(Vt),
+                           g->scan_ticket, 4, g->err, 4, s);
+    } else {
+        upload(g->h_pd.data(), bytes, g->d_pd, s);
+        launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    }
 }
 
 // The packed-hash ablation applies when every pair's voxel ids fit its key.
@@ -1039,7 +1112,7 @@ bool count_packed(const vicp_grid* g)
 void queue_build(vicp_grid* g, hipStream_t s, bool cap)
 {
     const int64_t Vt = g->V_total;
-    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    clear_for_build(g, s);
     queue_count(g, g->qx, g->qy, g->qz, count_packed(g), s, cap);
     {
         ProfScope ps("scan", s, cap, true);
@@ -1074,7 +1147,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
     // voxel) sorts its long segments whole; the count lists them (err[1]
     // counts the list)
     const bool seg_sort = g->fixed && !count_packed(g);
-    launch_clear4(g->hist, Vt, g->scan_status, scan_tiles(Vt), g->scan_ticket, 4, g->err, 4, s);
+    clear_for_build(g, s);
     queue_count(g, qx, qy, qz, count_packed(g), s, false, seg_sort);
     if (g->fixed) {   // the one synchronisation of a fixed-grid build: every target inside the grid?
         uint32_t herr = 0;
@@ -1216,7 +1289,6 @@ int build_grid_impl(const float* qx, const float* qy, const float* qz, const int
     make_jobs(ncount, 1024, jq1024, nullptr);
     bool ok = true;
     g->d_pd = (PairDev*)g->take(sizeof(PairDev) * npairs, s, g->owned, ok);
-    g->box = (uint32_t*)g->take(sizeof(uint32_t) * 8 * std::max<size_t>(jq8.size(), 1), s, g->owned, ok);
     g->err = (uint32_t*)g->take(sizeof(uint32_t) * 4, s, g->owned, ok);
     g->jobs_q = (BlockJob*)g->take(sizeof(BlockJob) * jq.size(), s, g->owned, ok);
     g->jobs_q8 = (BlockJob*)g->take(sizeof(BlockJob) * jq8.size(), s, g->owned, ok);

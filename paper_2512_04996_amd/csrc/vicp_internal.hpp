@@ -326,7 +326,7 @@ inline void launch_timed_lds(F kernel, dim3 grid, dim3 block, size_t lds, hipStr
 
 // grid build
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd,
-                 const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, hipStream_t s);
+                 const BlockJob* jobs, int njobs, int items_per_block, uint32_t* box, uint32_t tag, hipStream_t s);
 // block: target points per block (256, 512 or 1024; the packed-hash
 // ablation always takes 256); jobs must hold `block` points per entry
 // big_list / big_count (both or neither): every voxel whose count reaches
