@@ -26,12 +26,16 @@
  *            hipMallocAsync on the given stream when that is NULL.
  * Streams    All device work is queued on the caller's stream in order.  Calls
  *            that must read a value back (grid sizing, registration results)
- *            synchronise that stream, and say so.
+ *            wait for it, and say so: the grid sizing and the registration
+ *            results arrive through pinned host memory that the device
+ *            writes, with a tag the host waits for (every kernel that
+ *            produced the value has finished by then; the stream may still
+ *            be finishing the small kernel that wrote it).
  * Errors     Every call returns VICP_OK (0) or a negative VICP_ERR_* code and
  *            never aborts or prints; vicp_last_error() gives a message for the
  *            calling thread.  Faults found on the device (non-finite source
  *            coordinates, degenerate cross-covariance) are latched in the grid
- *            and returned by the next call that synchronises.
+ *            and returned by the next call that waits for the device.
  * Threads    A grid may be used by one host thread at a time.  Distinct grids
  *            are independent.
  */
@@ -166,7 +170,7 @@ int vicp_build_grid_fixed(const float* qx, const float* qy, const float* qz, int
  * specification, counts, offsets and segments are recomputed exactly as by
  * vicp_build_grid, while allocations, work tables and captured graphs are
  * reused when the voxel counts are unchanged.  The grid is left undilated:
- * call vicp_dilate again.  Synchronises the stream once (bounding box).
+ * call vicp_dilate again.  Waits once for the device (bounding box).
  * Errors as vicp_build_grid; STATE for a grid that was never built.  After a
  * rebuild of a given-geometry grid fails because a target point lies outside
  * it, every other entry point returns STATE for that grid until a rebuild
@@ -265,7 +269,9 @@ int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const
  * float32-rounded pose, then the closed-form rigid transform of Eq. 1 on
  * (original p_i, q_c(i)) in float64, repeated opts->max_iter times or until
  * the RMSE difference rule stops it.  Rt_io: 12 HOST doubles, initial pose in,
- * final pose out.  `stats` may be NULL.  Synchronises the stream at the end.
+ * final pose out.  `stats` may be NULL.  Waits at the end until the results
+ * are in host memory (written there by the device after every kernel of the
+ * loop has finished).
  * Returns DEGENERATE (pose still valid) if any solve kept the previous pose. */
 int vicp_register(const vicp_grid* g, const float* px, const float* py, const float* pz,
                   int64_t m, const vicp_icp_opts* opts, double Rt_io[12],

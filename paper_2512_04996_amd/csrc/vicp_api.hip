@@ -76,24 +76,43 @@ void launch_clear4_blob(const Blob& blob, uint32_t* dst, int nwords, uint32_t* a
     hipLaunchKernelGGL(k_clear4_blob, dim3(blocks), dim3(256), 0, s, blob, dst, nwords, a, na, b, nb, c, nc, d, nd, n);
 }
 
-// Waits until each of the nblocks bounding-box partials in pinned host
-// memory carries the tag (the box kernel writes it after the values).  Spins
-// on the host for up to two seconds (no stream synchronisation, whose
-// wake-up is slower), then synchronises the stream and looks once more.
-hipError_t wait_box_tags(const uint32_t* box, int nblocks, uint32_t tag, hipStream_t s)
+// Waits until each of `count` words in pinned host memory, `stride` words
+// apart, holds the tag (device kernels write it after the values it
+// guards).  Spins on the host for up to two seconds (no stream
+// synchronisation, whose wake-up is slower), then synchronises the stream
+// and looks once more.
+hipError_t wait_tags(const uint32_t* first, int count, size_t stride, uint32_t tag, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
     int next = 0;
     for (;;) {
-        while (next < nblocks && __atomic_load_n(&box[8 * (size_t)next + 7], __ATOMIC_ACQUIRE) == tag) ++next;
-        if (next == nblocks) return hipSuccess;
+        while (next < count && __atomic_load_n(&first[stride * (size_t)next], __ATOMIC_ACQUIRE) == tag) ++next;
+        if (next == count) return hipSuccess;
         if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
     }
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    for (; next < nblocks; ++next)
-        if (__atomic_load_n(&box[8 * (size_t)next + 7], __ATOMIC_ACQUIRE) != tag) return hipErrorUnknown;
+    for (; next < count; ++next)
+        if (__atomic_load_n(&first[stride * (size_t)next], __ATOMIC_ACQUIRE) != tag) return hipErrorUnknown;
     return hipSuccess;
+}
+
+// Copies the registration's result block (state, histories, counters,
+// flags) into mapped pinned host memory, then writes the call's tag after
+// it: each thread's stores are fenced at system scope before the barrier,
+// and the tag is the last store.
+__global__ __launch_bounds__(256) void k_publish(const uint32_t* __restrict__ src, uint32_t* dst, int64_t words,
+                                                 uint32_t tag)
+{
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(dst + words, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const uint32_t* src, uint32_t* dst, int64_t words, uint32_t tag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, src, dst, words, tag);
 }
 
 void upload(const void* host, size_t bytes, void* dst, hipStream_t s)
@@ -465,8 +484,12 @@ struct vicp_grid {
     char* res = nullptr;
     size_t res_bytes = 0;
     size_t o_rmse = 0, o_ctr = 0, o_fb = 0, o_deg = 0, o_flags = 0;
+    // pinned host memory mapped for the device: the result block, then the
+    // tag of the registration that wrote it (res_gen)
     void* h_res = nullptr;
+    void* d_hres = nullptr;
     size_t h_res_cap = 0;
+    uint32_t res_gen = 0;
     // pinned host memory mapped for the device: the per-block bounding-box
     // partials, each tagged with its build's number (box_gen)
     uint32_t* h_box = nullptr;
@@ -698,11 +721,19 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
         if (g->h_res_cap < g->res_bytes) {
             if (g->h_res) (void)hipHostFree(g->h_res);
             g->h_res = nullptr;
+            g->d_hres = nullptr;
             g->h_res_cap = 0;
-            if (hipHostMalloc(&g->h_res, g->res_bytes, hipHostMallocDefault) == hipSuccess)
+            const size_t bytes = g->res_bytes + 8;   // the tag after the block
+            if (hipHostMalloc(&g->h_res, bytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                hipHostGetDevicePointer(&g->d_hres, g->h_res, 0) == hipSuccess) {
+                memset(g->h_res, 0, bytes);   // no tag is 0
                 g->h_res_cap = g->res_bytes;
-            else
+            } else {
+                if (g->h_res) (void)hipHostFree(g->h_res);
+                g->h_res = nullptr;
+                g->d_hres = nullptr;
                 ok = false;
+            }
         }
     }
     g->staging = g->take(sizeof(double) * 12 * B, s, L, ok);
@@ -989,7 +1020,7 @@ int grid_fill_host(vicp_grid* g, const float* qx, const float* qy, const float* 
         launch_aabb(qx, qy, qz, g->d_pd, g->jobs_q8, g->njobs_q8, 2048, g->d_box, g->box_gen, s);
     }
     VICP_HIP(hipGetLastError());
-    if (nbox) VICP_HIP(wait_box_tags(g->h_box, g->njobs_q8, g->box_gen, s));
+    if (nbox) VICP_HIP(wait_tags(g->h_box + 7, g->njobs_q8, 8, g->box_gen, s));
     // per pair: min of the block minima, max of the block maxima, any
     // non-finite flag (a pair with no points keeps the empty box)
     std::vector<uint32_t> hbox(8 * (size_t)B);
@@ -1787,8 +1818,17 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
             if (!queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global, direct, out_idx, out_d2))
                 return fail(VICP_ERR_INVALID_ARG, kTooMany);
     }
-    VICP_HIP(hipMemcpyAsync(g->h_res, g->res, g->res_bytes, hipMemcpyDeviceToHost, s));
-    VICP_HIP(hipStreamSynchronize(s));
+    // the results go into mapped pinned memory, followed by this call's tag,
+    // which the host waits for (the stream itself is synchronised only when
+    // timing events are to be read)
+    if (++g->res_gen == 0) g->res_gen = 1;
+    const int64_t rwords = (int64_t)(g->res_bytes / 4);
+    // the tag's word may hold another layout's data from an earlier call
+    __atomic_store_n((uint32_t*)g->h_res + rwords, 0u, __ATOMIC_RELEASE);
+    launch_publish((const uint32_t*)g->res, (uint32_t*)g->d_hres, rwords, g->res_gen, s);
+    VICP_HIP(hipGetLastError());
+    VICP_HIP(wait_tags((const uint32_t*)g->h_res + rwords, 1, 0, g->res_gen, s));
+    if (g_prof.on) VICP_HIP(hipStreamSynchronize(s));
     const char* hb = (const char*)g->h_res;
     const PairState* hst = (const PairState*)hb;
     const double* hr = (const double*)(hb + g->o_rmse);
