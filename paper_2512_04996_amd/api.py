@@ -20,7 +20,14 @@ __all__ = ["Grid", "build_grid", "build_grid_batched", "IcpResult", "prof_enable
            "prof_reset", "autotune_cache_clear"]
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream():
+    # torch's current stream as a raw handle (without building a Stream
+    # object when torch exposes the handle directly)
+    if _raw_stream is not None:
+        return C.c_void_p(_raw_stream(torch.cuda.current_device()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -37,14 +44,19 @@ def _soa(x: torch.Tensor, what: str) -> torch.Tensor:
 
 
 def _ptrs(x: torch.Tensor):
+    # the three rows of a contiguous (3, k) float32 tensor
     if x.shape[1] == 0:
         return C.c_void_p(0), C.c_void_p(0), C.c_void_p(0)
-    return tuple(C.c_void_p(x[a].data_ptr()) for a in range(3))
+    base, row = x.data_ptr(), x.stride(0) * x.element_size()
+    return C.c_void_p(base), C.c_void_p(base + row), C.c_void_p(base + 2 * row)
 
 
 def _i64(vals):
     arr = (C.c_int64 * len(vals))(*[int(v) for v in vals])
     return arr
+
+
+_IDENTITY = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float64)
 
 
 @dataclass
@@ -71,6 +83,9 @@ class Grid:
         self.voxels = [float(v) for v in voxels]
         self.pad_rings = int(pad_rings)
         self.npairs = len(self.n_per_pair)
+        self.n_total = sum(self.n_per_pair)
+        self._stats_key = None           # host arrays the registration's statistics land in, per (B, K)
+        self._stats = None
 
     # -- lifetime
     def free(self):
@@ -93,7 +108,7 @@ class Grid:
     def rebuild(self, q: torch.Tensor):
         """Refill the grid from a new target with the same per-pair point counts."""
         q = _soa(q, "q")
-        if q.shape[1] != sum(self.n_per_pair):
+        if q.shape[1] != self.n_total:
             raise ValueError("rebuild needs the same number of target points")
         qx, qy, qz = _ptrs(q)
         check(lib().vicp_grid_rebuild(self.handle, qx, qy, qz, _stream()), "vicp_grid_rebuild")
@@ -213,19 +228,11 @@ class Grid:
         if sum(m_per_pair) != m:
             raise ValueError("m_per_pair does not add up to the source size")
         if Rt0 is None:
-            Rt0 = np.tile(np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float64), (B, 1))
-        rt = np.ascontiguousarray(np.asarray(Rt0, np.float64).reshape(B * 12)).copy()
+            rt = np.tile(_IDENTITY, B)
+        else:
+            rt = np.ascontiguousarray(np.asarray(Rt0, np.float64).reshape(B * 12)).copy()
         K = int(max_iter)
-        rm = np.zeros((B, max(K, 1)), np.float64)
-        fbk = np.zeros((B, max(K, 1)), np.int64)
-        cnd = np.zeros((B, max(K, 1)), np.int64)
-        dil = np.zeros((B, max(K, 1)), np.int64)
-        stats = (IcpStats * B)()
-        for b in range(B):
-            stats[b].rmse = rm[b].ctypes.data_as(C.POINTER(C.c_double))
-            stats[b].fallbacks = fbk[b].ctypes.data_as(C.POINTER(C.c_int64))
-            stats[b].candidates = cnd[b].ctypes.data_as(C.POINTER(C.c_int64))
-            stats[b].dilated_lookups = dil[b].ctypes.data_as(C.POINTER(C.c_int64))
+        rm, fbk, cnd, dil, stats = self._stats_arrays(B, K)
         if layout not in ("segmented", "direct"):
             raise ValueError("layout must be 'segmented' or 'direct'")
         out_idx = out_d2 = None
@@ -248,6 +255,21 @@ class Grid:
                          [cnd[b, :iters[b]].copy() for b in range(B)],
                          [dil[b, :iters[b]].copy() for b in range(B)], rc,
                          out_idx[:m] if correspondences else None, out_d2[:m] if correspondences else None)
+
+    def _stats_arrays(self, B: int, K: int):
+        # reused from call to call (a grid serves one thread at a time); the
+        # results returned are copies
+        if self._stats_key != (B, K):
+            arrs = [np.zeros((B, max(K, 1)), dt) for dt in (np.float64, np.int64, np.int64, np.int64)]
+            stats = (IcpStats * B)()
+            for b in range(B):
+                stats[b].rmse = arrs[0][b].ctypes.data_as(C.POINTER(C.c_double))
+                stats[b].fallbacks = arrs[1][b].ctypes.data_as(C.POINTER(C.c_int64))
+                stats[b].candidates = arrs[2][b].ctypes.data_as(C.POINTER(C.c_int64))
+                stats[b].dilated_lookups = arrs[3][b].ctypes.data_as(C.POINTER(C.c_int64))
+            self._stats = (*arrs, stats)
+            self._stats_key = (B, K)
+        return self._stats
 
     # -- helpers
     def describe(self, pair: int = 0) -> dict:
