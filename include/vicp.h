@@ -129,8 +129,8 @@ typedef struct vicp_icp_stats {
  * exclusive-scans count + 2 into segment offsets, and scatters point indices
  * into their segments [lock = 0, count, indices ascending].  Waits once for
  * the device, for the bounding box that sizes the grid (per-block partials
- * written into pinned host memory; the stream itself is not synchronised
- * unless that takes over two seconds).
+ * written into pinned host memory; the stream itself is synchronised only
+ * when that takes over a millisecond).
  * Errors: n <= 0, voxel <= 0 or non-finite, pad_rings < 0 -> INVALID_ARG;
  * non-finite target coordinates -> NONFINITE; grid too large -> GRID_TOO_LARGE;
  * a padded grid reaching beyond +-VICP_COORD_LIMIT on any axis (float32

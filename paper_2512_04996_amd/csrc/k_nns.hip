@@ -113,6 +113,146 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
     bz = better ? q.z : bz;
 }
 
+// Exact global search by voxel shells.  A query whose voxel is empty and
+// undilated, or outside the grid, takes the exact minimum of (d, j) over all
+// n targets (Alg. 4's global search).  Rather than scanning all n, the wave
+// visits the occupied voxels of a growing cube of voxels around the query's
+// voxel (clamped into the grid) and stops once every target outside the
+// visited cube is provably farther than the best found: its squared
+// distance is then above the best one even after the float32 rounding of
+// the distance, so it can neither win nor tie.  The bound takes each face of
+// the cube that is not on the grid's boundary: a target beyond it lies
+// beyond that face on its axis and inside the grid box on the other two.
+// Faces and the grid box are widened by a margin for the float32 rounding
+// of the voxel assignment (floor((q - o) * inv)), so a target assigned to a
+// voxel may lie slightly outside it.  All 64 lanes call it with the same
+// point; every lane gets the result.  False (nothing found) when a cube of
+// kShellMax voxels around does not settle it: the query then goes to the
+// exhaustive search.
+constexpr int kShellFirst = 2;   // the first cube: 5^3 voxels
+constexpr int kShellMax = 8;     // the largest: 17^3 voxels
+constexpr int kShellBatch = 4;   // directory loads in flight per lane
+
+// The point and every quantity derived from it are the same in all lanes
+// (scalar registers); a lane keeps only its best candidate's (d, j) and
+// segment slot, and the winner's coordinates are read once at the end.
+__device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __restrict__ dir,
+                                              const float4* __restrict__ qs4, float sx, float sy, float sz,
+                                              float& rd, uint32_t& rj, float& rx, float& ry, float& rz)
+{
+    if (!(isfinite(sx) && isfinite(sy) && isfinite(sz))) return false;   // left to the exhaustive search
+    const int lane = threadIdx.x & (kWave - 1);
+    const float inv = P.inv, vox = 1.0f / P.inv;
+    const float s[3] = {sx, sy, sz};
+    const float o[3] = {P.ox, P.oy, P.oz};
+    const int D[3] = {P.Dx, P.Dy, P.Dz};
+    int c[3];
+    float mg[3], d2box[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float f = (s[a] - o[a]) * inv;
+        c[a] = f < 0.0f ? 0 : (f >= (float)(D[a] - 1) ? D[a] - 1 : (int)floorf(f));
+        c[a] = __builtin_amdgcn_readfirstlane(c[a]);
+        // 1e-5 of the coordinates' magnitude and 1e-3 of a voxel: far above
+        // the float32 rounding of the assignment and of this arithmetic
+        mg[a] = 1e-5f * (fabsf(o[a]) + ((float)D[a] + 1.0f) * vox) + 1e-3f * vox;
+        const float lo = o[a] - mg[a], hi = o[a] + (float)D[a] * vox + mg[a];
+        const float g = s[a] < lo ? lo - s[a] : (s[a] > hi ? s[a] - hi : 0.0f);
+        d2box[a] = g * g;
+    }
+    float bd = INFINITY;
+    uint32_t bj = 0xFFFFFFFFu, bslot = 0u;
+    int done_r = -1;   // the cube of this radius has been visited
+    int R = kShellFirst;
+    while (true) {
+        const int w = 2 * R + 1;
+        const int items = w * w * w;
+        for (int i0 = lane; i0 < items; i0 += kWave * kShellBatch) {
+            uint2 e[kShellBatch];
+#pragma unroll
+            for (int u = 0; u < kShellBatch; ++u) {
+                e[u] = make_uint2(0u, 0u);
+                const int it = i0 + u * kWave;
+                if (it >= items) continue;
+                const int dz = it / (w * w) - R, rem = it % (w * w);
+                const int dy = rem / w - R, dx = rem % w - R;
+                if (max(abs(dx), max(abs(dy), abs(dz))) <= done_r) continue;   // visited before
+                const int vx = c[0] + dx, vy = c[1] + dy, vz = c[2] + dz;
+                if (vx < 0 || vy < 0 || vz < 0 || vx >= D[0] || vy >= D[1] || vz >= D[2]) continue;
+                e[u] = dir[P.v_base + vx + (int64_t)D[0] * (vy + (int64_t)D[1] * vz)];
+            }
+#pragma unroll
+            for (int u = 0; u < kShellBatch; ++u) {
+                // an occupied voxel: its own count, no mask (a dilated voxel's
+                // entry points at its root, visited as itself)
+                const uint32_t cnt = (e[u].y & kMask) ? 0u : e[u].y;
+                for (uint32_t k = 0; k < cnt; k += 4) {
+                    float4 q[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) q[t] = qs4[e[u].x + min(k + (uint32_t)t, cnt - 1u)];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float d = dist2(sx, sy, sz, q[t].x, q[t].y, q[t].z);
+                        const uint32_t j = __float_as_uint(q[t].w);
+                        const bool better = d < bd || (d == bd && j < bj);
+                        bd = better ? d : bd;
+                        bj = better ? j : bj;
+                        bslot = better ? e[u].x + min(k + (uint32_t)t, cnt - 1u) : bslot;
+                    }
+                }
+            }
+        }
+        // the wave's minimum of (d, j): distances are >= 0, so their bits
+        // order as the values do
+        unsigned long long key = ((unsigned long long)__float_as_uint(bd) << 32) | bj;
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) {
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(key >> 32), m, kWave);
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)key, m, kWave);
+            const unsigned long long other = ((unsigned long long)hi << 32) | lo;
+            key = other < key ? other : key;
+        }
+        const float best = __uint_as_float((uint32_t)(key >> 32));
+        // lower bound on the squared distance of any target outside the
+        // visited cube
+        float lb2 = INFINITY;
+        bool all = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float rest = d2box[(a + 1) % 3] + d2box[(a + 2) % 3];
+            if (c[a] - R > 0) {   // targets below the cube's low face on axis a
+                all = false;
+                const float g = s[a] - (o[a] + (float)(c[a] - R) * vox + mg[a]);
+                lb2 = fminf(lb2, (g > 0.0f ? g * g : 0.0f) + rest);
+            }
+            if (c[a] + R < D[a] - 1) {   // above its high face
+                all = false;
+                const float g = (o[a] + (float)(c[a] + R + 1) * vox - mg[a]) - s[a];
+                lb2 = fminf(lb2, (g > 0.0f ? g * g : 0.0f) + rest);
+            }
+        }
+        const bool found = (uint32_t)(key >> 32) != 0x7F800000u;   // a finite best
+        if (found && (all || lb2 * (1.0f - 1e-4f) > best)) {
+            const unsigned long long mine = ((unsigned long long)__float_as_uint(bd) << 32) | bj;
+            const int owner = __ffsll((long long)__ballot(mine == key)) - 1;
+            const float4 wq = qs4[__builtin_amdgcn_readlane((int)bslot, owner)];
+            rd = best;
+            rj = (uint32_t)key;
+            rx = wq.x;
+            ry = wq.y;
+            rz = wq.z;
+            return true;
+        }
+        if (all || R >= kShellMax) return false;
+        // the next cube: large enough for the bound to pass the best found
+        // (its radius in voxels, plus one), or twice as large
+        done_r = R;
+        int next = 2 * R + 1;
+        if (found) next = (int)fminf((float)kShellMax, ceilf(sqrtf(best) * inv) + 1.0f);
+        R = max(R + 1, min(next, kShellMax));
+    }
+}
+
 // LPQ lanes cooperate on one query: each scans every LPQ-th candidate of the
 // segment in ascending order (so it keeps the lowest index among its equal
 // distances), then the lanes combine by the lexicographic minimum of
@@ -154,9 +294,10 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
                                                   const float* __restrict__ px, const float* __restrict__ py,
                                                   const float* __restrict__ pz, const float4* __restrict__ ps4,
                                                   const PairState* __restrict__ st, const uint2* __restrict__ dir,
-                                                  const float4* __restrict__ qs4,
+                                                  const float4* __restrict__ qs4, const float4* __restrict__ qsg,
                                                   int32_t* __restrict__ nn_idx, float* __restrict__ nn_d2,
-                                                  int32_t* __restrict__ fb_count, uint32_t* __restrict__ fb_list,
+                                                  int32_t* __restrict__ fb_count, int32_t* __restrict__ fb_miss,
+                                                  uint32_t* __restrict__ fb_list,
                                                   unsigned long long* __restrict__ fb_key,
                                                   unsigned long long* __restrict__ ctr, double* __restrict__ part,
                                                   int all_global, const uint32_t* __restrict__ dcnt, uint32_t cap,
@@ -224,22 +365,9 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         }
     }
     const int64_t gp = (kOne ? (int64_t)0 : P.p_base) + i;
-    // queries for the global search: one list append per wave, each query at
-    // its rank among the wave's misses (counted on its first lane)
+    // queries for the global search (counted on their first lane)
     const bool miss = active && c == 0 && sub == 0;
     const unsigned long long mmask = __ballot(miss);
-    if (mmask) {
-        const int leader = __ffsll((long long)mmask) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&fb_count[job.pair], (int32_t)__popcll(mmask));
-        base = __shfl(base, leader, kWave);
-        if (miss) {
-            const int32_t pos = base + (int32_t)__popcll(mmask & ((1ull << lane) - 1ull));
-            fb_list[P.p_base + pos] = i;
-            fb_key[P.p_base + pos] = ~0ull;
-            if (!kMom) nn_idx[gp] = -1 - pos;
-        }
-    }
     float bd = INFINITY;
     uint32_t bj = 0xFFFFFFFFu;
     float bx = 0.0f, by = 0.0f, bz = 0.0f;
@@ -290,7 +418,56 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
         bz = wv.z;
         bidx = __float_as_uint(wv.w);
     }
-    const bool found = active && c > 0 && sub == 0;
+    // The wave resolves its global searches itself, one query at a time, by
+    // the exact shell search over the segments (qsg, whichever layout the
+    // local search reads; not for the exhaustive comparator); those the
+    // shells do not settle are appended to the pair's list for the
+    // exhaustive search, one append per wave, each query at its rank among
+    // the wave's unresolved ones.  Every global search is counted in
+    // fb_miss.
+    bool shelled = false;
+    unsigned long long left = mmask;
+    if (mmask && !all_global) {
+        unsigned long long pend = mmask;
+        left = 0ull;
+        while (pend) {   // uniform over the wave
+            const int L = __ffsll((long long)pend) - 1;
+            pend &= pend - 1ull;
+            float rd, rx, ry, rz;
+            uint32_t rj;
+            const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), L));
+            const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), L));
+            const float lz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz), L));
+            if (shell_nearest(P, dir, qsg, lx, ly, lz, rd, rj, rx, ry, rz)) {
+                if (lane == L) {
+                    shelled = true;
+                    bd = rd;
+                    bidx = rj;
+                    bx = rx;
+                    by = ry;
+                    bz = rz;
+                }
+            } else {
+                left |= 1ull << L;
+            }
+        }
+    }
+    if (mmask) {
+        const int leader = __ffsll((long long)mmask) - 1;
+        int32_t base = 0;
+        if (lane == leader) {
+            if (fb_miss) atomicAdd(&fb_miss[job.pair], (int32_t)__popcll(mmask));
+            if (left) base = atomicAdd(&fb_count[job.pair], (int32_t)__popcll(left));
+        }
+        base = __shfl(base, leader, kWave);
+        if ((left >> lane) & 1ull) {
+            const int32_t pos = base + (int32_t)__popcll(left & ((1ull << lane) - 1ull));
+            fb_list[P.p_base + pos] = i;
+            fb_key[P.p_base + pos] = ~0ull;
+            if (!kMom) nn_idx[gp] = -1 - pos;
+        }
+    }
+    const bool found = (active && c > 0 && sub == 0) || shelled;
     if (found && (!kMom || nn_idx)) {
         nn_idx[gp] = (int32_t)bidx;
         nn_d2[gp] = bd;
@@ -683,9 +860,10 @@ __global__ void k_copy_fb(const int32_t* __restrict__ fb_count, int32_t* __restr
 
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
                       const float* px, const float* py, const float* pz, const float4* ps4, const PairState* st,
-                      const uint2* dir, const float4* qs4, int32_t* nn_idx, float* nn_d2, int32_t* fb_count,
-                      uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr, double* part,
-                      int all_global, const uint32_t* dcnt, uint32_t cap, int mode, int64_t one_m, hipStream_t s)
+                      const uint2* dir, const float4* qs4, const float4* qsg, int32_t* nn_idx, float* nn_d2,
+                      int32_t* fb_count, int32_t* fb_miss, uint32_t* fb_list, unsigned long long* fb_key, unsigned long long* ctr,
+                      double* part, int all_global, const uint32_t* dcnt, uint32_t cap, int mode, int64_t one_m,
+                      hipStream_t s)
 {
     if (njobs <= 0) return;
     const bool one = one_m >= 0;
@@ -695,11 +873,11 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 #define VICP_NNS_R(BS, L, SORTED)                                                                                  \
     if (one)                                                                                                       \
         launch_timed(k_nns_local<BS, L, SORTED, true, false, 1, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py,  \
-                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     pz, ps4, st, dir, qs4, qsg, nn_idx, nn_d2, fb_count, fb_miss, fb_list, fb_key, ctr, part, all_global, dcnt,    \
                      cap, one_m);                                                                                  \
     else                                                                                                           \
         launch_timed(k_nns_local<BS, L, SORTED, true, false, 1, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, \
-                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     pz, ps4, st, dir, qs4, qsg, nn_idx, nn_d2, fb_count, fb_miss, fb_list, fb_key, ctr, part, all_global, dcnt,    \
                      cap, one_m)
 #define VICP_NNS_RL(BS, SORTED)                                     \
     switch (lpq) {                                                  \
@@ -727,11 +905,11 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 #define VICP_NNS(BS, L, SORTED, MOM, DIRECT)                                                                       \
     if (one && !DIRECT)                                                                                            \
         launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0, true>, dim3(njobs), dim3(BS), s, pd, jobs, px, py,  \
-                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     pz, ps4, st, dir, qs4, qsg, nn_idx, nn_d2, fb_count, fb_miss, fb_list, fb_key, ctr, part, all_global, dcnt,    \
                      cap, one_m);                                                                                  \
     else                                                                                                           \
         launch_timed(k_nns_local<BS, L, SORTED, MOM, DIRECT, 0, false>, dim3(njobs), dim3(BS), s, pd, jobs, px, py, \
-                     pz, ps4, st, dir, qs4, nn_idx, nn_d2, fb_count, fb_list, fb_key, ctr, part, all_global, dcnt,    \
+                     pz, ps4, st, dir, qs4, qsg, nn_idx, nn_d2, fb_count, fb_miss, fb_list, fb_key, ctr, part, all_global, dcnt,    \
                      cap, one_m)
 #define VICP_NNS_L(BS, SORTED, MOM, DIRECT)                  \
     switch (lpq) {                                           \

@@ -381,6 +381,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     const bool one = gridDim.x == 1;
     const int32_t u0 = one ? 0 : fold_begin[pair], u1 = one ? nunits : fold_begin[pair + 1];
     const int32_t nfb = fb_count[pair];
+    const int32_t nmiss = fb_count[gridDim.x + pair];   // every global search, shell-resolved or listed
     const double prev = S.prev_rmse;
     // the current rotation, the start of the polar refinement: read by every
     // thread (uniform loads, all in flight together; a per-thread condition
@@ -510,11 +511,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(
     }
     const int64_t h = (int64_t)pair * K + k;
     rmse_hist[h] = rmse;
-    fb_hist[h] = nfb;
+    fb_hist[h] = nmiss;
     deg_hist[h] = ok ? 0 : 1;
     ctr_hist[2 * h] = ctot[0];
     ctr_hist[2 * h + 1] = ctot[1];
     fb_count[pair] = 0;
+    fb_count[gridDim.x + pair] = 0;
     S.iters = k + 1;
     if (early_stop && k >= 1 && fabs(rmse - prev) < eps) S.done = 1;
     S.prev_rmse = rmse;
@@ -528,10 +530,11 @@ struct PoseBlob {
 };
 
 __device__ __forceinline__ void set_state_one(const PairDev* __restrict__ pd, PairState* __restrict__ st, int p,
-                                              const double* rt, int32_t* __restrict__ fb_count,
+                                              const double* rt, int npairs, int32_t* __restrict__ fb_count,
                                               int32_t* __restrict__ flags)
 {
     fb_count[p] = 0;
+    fb_count[npairs + p] = 0;
     flags[p] = 0;
     PairState& S = st[p];
     S.done = pd[p].m > 0 ? 0 : 1;
@@ -551,7 +554,7 @@ __global__ void k_set_state_inline(const PairDev* __restrict__ pd, PairState* __
                                    int npairs, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
 {
     const int p = threadIdx.x;
-    if (p < npairs) set_state_one(pd, st, p, b.rt + 12 * p, fb_count, flags);
+    if (p < npairs) set_state_one(pd, st, p, b.rt + 12 * p, npairs, fb_count, flags);
 }
 
 __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restrict__ st, const double* __restrict__ rt64,
@@ -559,7 +562,7 @@ __global__ void k_set_state(const PairDev* __restrict__ pd, PairState* __restric
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
-    set_state_one(pd, st, p, rt64 + 12 * p, fb_count, flags);
+    set_state_one(pd, st, p, rt64 + 12 * p, npairs, fb_count, flags);
 }
 
 }  // namespace

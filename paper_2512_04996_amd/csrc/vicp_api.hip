@@ -78,9 +78,9 @@ void launch_clear4_blob(const Blob& blob, uint32_t* dst, int nwords, uint32_t* a
 
 // Waits until each of `count` words in pinned host memory, `stride` words
 // apart, holds the tag (device kernels write it after the values it
-// guards).  Spins on the host for up to two seconds (no stream
-// synchronisation, whose wake-up is slower), then synchronises the stream
-// and looks once more.
+// guards).  Spins on the host for up to a millisecond (no stream
+// synchronisation, whose wake-up is slower); a longer wait synchronises
+// the stream instead (no busy host thread) and then looks once more.
 hipError_t wait_tags(const uint32_t* first, int count, size_t stride, uint32_t tag, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -88,7 +88,7 @@ hipError_t wait_tags(const uint32_t* first, int count, size_t stride, uint32_t t
     for (;;) {
         while (next < count && __atomic_load_n(&first[stride * (size_t)next], __ATOMIC_ACQUIRE) == tag) ++next;
         if (next == count) return hipSuccess;
-        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(1)) break;
     }
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
@@ -737,7 +737,9 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
         }
     }
     g->staging = g->take(sizeof(double) * 12 * B, s, L, ok);
-    g->fb_count = (int32_t*)g->take(sizeof(int32_t) * B, s, L, ok);
+    // per pair: the global-search list's length, then (fb_count + B) every
+    // query that needed a global search, shell-resolved or listed
+    g->fb_count = (int32_t*)g->take(sizeof(int32_t) * 2 * B, s, L, ok);
     g->fb_list = (uint32_t*)g->take(sizeof(uint32_t) * mt1, s, L, ok);
     g->fb_key = (unsigned long long*)g->take(sizeof(unsigned long long) * mt1, s, L, ok);
     g->nn_idx = (int32_t*)g->take(sizeof(int32_t) * mt1, s, L, ok);
@@ -789,7 +791,7 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
     VICP_HIP(hipMemcpyAsync(g->job_begin6, begin6.data(), sizeof(int32_t) * kNumTables * (B + 1),
                             hipMemcpyHostToDevice, s));
     g->job_begin = g->job_begin6 + kT256 * (B + 1);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, B, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, 2 * B, s);
     VICP_HIP(hipStreamSynchronize(s));
     g->m_total = mt;
     g->K_cap = Kc;
@@ -850,7 +852,8 @@ bool queue_search(vicp_grid* g, const float* px, const float* py, const float* p
     {
         ProfScope ps(direct ? "nns_direct" : "nns_local", s, cap, true);
         launch_nns_local(g->d_pd, g->jobs_p[tab], g->njobs_p[tab], g->nns_block, g->nns_lpq, g->sort_src, mom, px, py,
-                         pz, g->ps4, g->st, g->dir, direct ? g->dblk : g->qs4, nn_idx, nn_d2, g->fb_count, g->fb_list,
+                         pz, g->ps4, g->st, g->dir, direct ? g->dblk : g->qs4, g->qs4, nn_idx, nn_d2, g->fb_count,
+                         g->fb_count + g->B, g->fb_list,
                          g->fb_key, g->ctr, g->npart, all_global ? 1 : 0, direct ? g->dcnt : nullptr, g->dcap,
                          g->search_mode, g->B == 1 ? g->m[0] : -1, s);
     }
@@ -1523,7 +1526,7 @@ int vicp_nns_batched(const vicp_grid* gc, const float* px, const float* py, cons
         ProfScope ps("fb_finalize", s, cap);
         launch_fb_finalize(g->d_pd, g->jobs_p[kT256], g->njobs_p[kT256], g->fb_key, nn_idx, nn_d2, g->flags, s);
     }
-    if (n_fallback) launch_copy_fb(g->fb_count, n_fallback, g->B, s);
+    if (n_fallback) launch_copy_fb(g->fb_count + g->B, n_fallback, g->B, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("nns: ") + hipGetErrorString(e));
     return VICP_OK;
@@ -1619,8 +1622,9 @@ __global__ void k_noalloc_setup(NaSetup a, int32_t njobs, int32_t qpb, int32_t n
         S.status = 0;
         S.rot_ok = 0;
         int32_t* cnt = reinterpret_cast<int32_t*>(base + kNaOffCnt);
-        cnt[0] = 0;   // global-search count
+        cnt[0] = 0;   // global-search list length
         cnt[1] = 0;   // fault flags
+        cnt[2] = 0;   // queries that needed a global search
     }
     BlockJob* jobs = reinterpret_cast<BlockJob*>(base + kNaOffJobs);
     BlockJob* jobs256 = reinterpret_cast<BlockJob*>(base + kNaOffJobs256);
@@ -1677,12 +1681,12 @@ int vicp_nns_noalloc(const vicp_grid* g, const float* px, const float* py, const
     hipLaunchKernelGGL(k_noalloc_setup, dim3(setup_blocks), dim3(256), 0, s, a, (int32_t)njobs, (int32_t)qpb,
                        (int32_t)njobs256, base);
     launch_nns_local(pd, jobs, (int)njobs, g->nns_block, g->nns_lpq, false, false, px, py, pz, nullptr, st, g->dir,
-                     g->qs4, nn_idx, nn_d2, cnt, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, m, s);
+                     g->qs4, g->qs4, nn_idx, nn_d2, cnt, cnt + 2, fb_list, fb_key, ctr, nullptr, 0, nullptr, 0u, 0, m, s);
     if (!launch_fallback(pd, 1, g->fb_grid, g->qx, g->qy, g->qz, px, py, pz, st, cnt, fb_list, fb_key, nullptr, 0,
                          nullptr, nullptr, nullptr, nullptr, s))
         return fail(VICP_ERR_INVALID_ARG, "global-search grid out of range");
     launch_fb_finalize(pd, jobs256, (int)njobs256, fb_key, nn_idx, nn_d2, cnt + 1, s);
-    if (n_fallback) launch_copy_fb(cnt, n_fallback, 1, s);
+    if (n_fallback) launch_copy_fb(cnt + 2, n_fallback, 1, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("nns_noalloc: ") + hipGetErrorString(e));
     return VICP_OK;
@@ -1893,7 +1897,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     if (g->m_total > 0 && (!px || !py || !pz)) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     const bool cap = capturing(s);
     launch_se3(xi, g->B, g->st, g->jl6, s);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, 2 * g->B, s);
     launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     if (!queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap, false))
@@ -2210,7 +2214,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     };
     auto timed = [&](auto&& work) -> float {
         return timed_raw([&] {
-            launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+            launch_fill_u32((uint32_t*)g->fb_count, 0u, 2 * g->B, s);
             work();
         });
     };
@@ -2314,7 +2318,7 @@ int vicp_autotune(vicp_grid* g, const float* px, const float* py, const float* p
     g->drop_graph();
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, g->B, s);
+    launch_fill_u32((uint32_t*)g->fb_count, 0u, 2 * g->B, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
     VICP_HIP(hipStreamSynchronize(s));

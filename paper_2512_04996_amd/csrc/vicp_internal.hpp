@@ -390,8 +390,8 @@ void launch_replicate(const PairDev* pd, int64_t V, const uint32_t* state, uint3
 // jobs of block / lpq queries each (the table is not read), else -1
 void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int block, int lpq, bool sorted, bool mom,
                       const float* px, const float* py, const float* pz, const float4* ps4,
-                      const PairState* st, const uint2* dir, const float4* qs4,
-                      int32_t* nn_idx, float* nn_d2, int32_t* fb_count, uint32_t* fb_list,
+                      const PairState* st, const uint2* dir, const float4* qs4, const float4* qsg,
+                      int32_t* nn_idx, float* nn_d2, int32_t* fb_count, int32_t* fb_miss, uint32_t* fb_list,
                       unsigned long long* fb_key, unsigned long long* ctr, double* part, int all_global,
                       const uint32_t* dcnt, uint32_t cap, int mode, int64_t one_m, hipStream_t s);
 void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
