@@ -128,10 +128,12 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // voxel may lie slightly outside it.  All 64 lanes call it with the same
 // point; every lane gets the result.  False (nothing found) when a cube of
 // kShellMax voxels around does not settle it: the query then goes to the
-// exhaustive search.
-constexpr int kShellFirst = 2;   // the first cube: 5^3 voxels
+// exhaustive search.  Each batch of a lane's voxels loads its directory
+// entries together, then the points of its occupied voxels as one flat run
+// (so a lane waits for two rounds of loads per batch, not one per voxel).
+constexpr int kShellFirst = 2;   // the smallest first cube: 5^3 voxels
 constexpr int kShellMax = 8;     // the largest: 17^3 voxels
-constexpr int kShellBatch = 4;   // directory loads in flight per lane
+constexpr int kShellBatch = 6;   // directory loads in flight per lane
 
 // The point and every quantity derived from it are the same in all lanes
 // (scalar registers); a lane keeps only its best candidate's (d, j) and
@@ -163,11 +165,14 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
     float bd = INFINITY;
     uint32_t bj = 0xFFFFFFFFu, bslot = 0u;
     int done_r = -1;   // the cube of this radius has been visited
-    int R = kShellFirst;
+    // the first cube reaches one voxel past the dilation: a global search's
+    // voxel has no occupied voxel within L1 distance L
+    int R = min(max(P.pad + 1, kShellFirst), kShellMax);
     while (true) {
         const int w = 2 * R + 1;
         const int items = w * w * w;
         for (int i0 = lane; i0 < items; i0 += kWave * kShellBatch) {
+            // the batch's directory entries, all in flight together
             uint2 e[kShellBatch];
 #pragma unroll
             for (int u = 0; u < kShellBatch; ++u) {
@@ -181,24 +186,41 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
                 if (vx < 0 || vy < 0 || vz < 0 || vx >= D[0] || vy >= D[1] || vz >= D[2]) continue;
                 e[u] = dir[P.v_base + vx + (int64_t)D[0] * (vy + (int64_t)D[1] * vz)];
             }
+            // the points of the batch's occupied voxels (own count, no mask:
+            // a dilated voxel's entry points at its root, visited as itself)
+            // as one flat run, four loads in flight; a lane past its last
+            // point repeats it (a repeat never wins)
+            uint32_t end[kShellBatch];
+            uint32_t total = 0u;
 #pragma unroll
             for (int u = 0; u < kShellBatch; ++u) {
-                // an occupied voxel: its own count, no mask (a dilated voxel's
-                // entry points at its root, visited as itself)
-                const uint32_t cnt = (e[u].y & kMask) ? 0u : e[u].y;
-                for (uint32_t k = 0; k < cnt; k += 4) {
-                    float4 q[4];
+                total += (e[u].y & kMask) ? 0u : e[u].y;
+                end[u] = total;
+            }
+            for (uint32_t t0 = 0; t0 < total; t0 += 4) {
+                float4 q[4];
+                uint32_t sl[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) q[t] = qs4[e[u].x + min(k + (uint32_t)t, cnt - 1u)];
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t f = min(t0 + (uint32_t)t, total - 1u);
+                    uint32_t slot = 0u, start = 0u;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const float d = dist2(sx, sy, sz, q[t].x, q[t].y, q[t].z);
-                        const uint32_t j = __float_as_uint(q[t].w);
-                        const bool better = d < bd || (d == bd && j < bj);
-                        bd = better ? d : bd;
-                        bj = better ? j : bj;
-                        bslot = better ? e[u].x + min(k + (uint32_t)t, cnt - 1u) : bslot;
+                    for (int u = 0; u < kShellBatch; ++u) {
+                        const bool here = f >= start && f < end[u];
+                        slot = here ? e[u].x + (f - start) : slot;
+                        start = end[u];
                     }
+                    sl[t] = slot;
+                    q[t] = qs4[slot];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float d = dist2(sx, sy, sz, q[t].x, q[t].y, q[t].z);
+                    const uint32_t j = __float_as_uint(q[t].w);
+                    const bool better = d < bd || (d == bd && j < bj);
+                    bd = better ? d : bd;
+                    bj = better ? j : bj;
+                    bslot = better ? sl[t] : bslot;
                 }
             }
         }
