@@ -128,12 +128,16 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // voxel may lie slightly outside it.  All 64 lanes call it with the same
 // point; every lane gets the result.  False (nothing found) when a cube of
 // kShellMax voxels around does not settle it: the query then goes to the
-// exhaustive search.  Each batch of a lane's voxels loads its directory
-// entries together, then the points of its occupied voxels as one flat run
-// (so a lane waits for two rounds of loads per batch, not one per voxel).
+// exhaustive search, and so does a query whose cube holds so many points
+// that a lane would scan more than kShellPoints of them (coarse grids with
+// thousands of points in a voxel: the tiled exhaustive search is the faster
+// there).  Each batch of a lane's voxels loads its directory entries
+// together, then the points of its occupied voxels as one flat run (so a
+// lane waits for two rounds of loads per batch, not one per voxel).
 constexpr int kShellFirst = 2;   // the smallest first cube: 5^3 voxels
 constexpr int kShellMax = 8;     // the largest: 17^3 voxels
 constexpr int kShellBatch = 6;   // directory loads in flight per lane
+constexpr uint32_t kShellPoints = 384;   // points a lane may scan before the wave gives up
 
 // The point and every quantity derived from it are the same in all lanes
 // (scalar registers); a lane keeps only its best candidate's (d, j) and
@@ -164,6 +168,7 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
     }
     float bd = INFINITY;
     uint32_t bj = 0xFFFFFFFFu, bslot = 0u;
+    uint32_t scanned = 0u;
     int done_r = -1;   // the cube of this radius has been visited
     // the first cube reaches one voxel past the dilation: a global search's
     // voxel has no occupied voxel within L1 distance L
@@ -197,6 +202,8 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
                 total += (e[u].y & kMask) ? 0u : e[u].y;
                 end[u] = total;
             }
+            scanned += total;
+            if (__ballot(scanned > kShellPoints)) return false;   // uniform: too many points
             for (uint32_t t0 = 0; t0 < total; t0 += 4) {
                 float4 q[4];
                 uint32_t sl[4];

@@ -107,3 +107,15 @@ def test_global_searches_under_a_pose():
     a = 0.2
     Rt = np.array([np.cos(a), -np.sin(a), 0, np.sin(a), np.cos(a), 0, 0, 0, 1, 0.05, -0.03, 0.02], np.float32)
     assert check(q, p, 0.03, 2, Rt) > 500
+
+
+def test_coarse_grid_with_crowded_voxels():
+    # two dense clusters in a coarse grid (thousands of points per voxel):
+    # a query in an empty voxel has too many points around it for the shells,
+    # so the exhaustive search resolves it, with the same result
+    rng = np.random.default_rng(13)
+    a = rng.normal(size=(3, 20000)) * 0.05 + np.array([[0.0], [0.0], [0.0]])
+    b = rng.normal(size=(3, 20000)) * 0.05 + np.array([[1.5], [1.5], [1.5]])
+    q = np.concatenate([a, b], 1).astype(np.float32)
+    p = rng.uniform(-0.2, 1.7, (3, 3000)).astype(np.float32)
+    assert check(q, p, 0.3, 0) > 500
