@@ -41,10 +41,16 @@ __device__ void matmul3(const double A[3][3], const double B[3][3], double C[3][
 }
 
 // One lane per pair: the pose, its float32 rounding and the 6x6 Jacobian.
-__global__ void k_se3(const double* __restrict__ xi, int npairs, PairState* __restrict__ st, double* __restrict__ jl6)
+__global__ void k_se3(const double* __restrict__ xi, int npairs, PairState* __restrict__ st, double* __restrict__ jl6,
+                      int32_t* __restrict__ fb_count, int32_t* __restrict__ flags)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
+    // the pass's global-search list length, global-search count and fault
+    // flags start at zero
+    fb_count[p] = 0;
+    fb_count[npairs + p] = 0;
+    flags[p] = 0;
     const double rho[3] = {xi[6 * p + 0], xi[6 * p + 1], xi[6 * p + 2]};
     const double phi[3] = {xi[6 * p + 3], xi[6 * p + 4], xi[6 * p + 5]};
     const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
@@ -236,10 +242,11 @@ __global__ __launch_bounds__(256) void k_loss_finish(const PairDev* __restrict__
 
 }  // namespace
 
-void launch_se3(const double* xi, int npairs, PairState* st, double* jl6, hipStream_t s)
+void launch_se3(const double* xi, int npairs, PairState* st, double* jl6, int32_t* fb_count, int32_t* flags,
+                hipStream_t s)
 {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(k_se3, dim3((npairs + 63) / 64), dim3(64), 0, s, xi, npairs, st, jl6);
+    hipLaunchKernelGGL(k_se3, dim3((npairs + 63) / 64), dim3(64), 0, s, xi, npairs, st, jl6, fb_count, flags);
 }
 
 void launch_loss_terms(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,

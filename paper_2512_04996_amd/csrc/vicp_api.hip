@@ -1896,9 +1896,7 @@ static int p2p_common(vicp_grid* g, const float* px, const float* py, const floa
     if (rc) return rc;
     if (g->m_total > 0 && (!px || !py || !pz)) return fail(VICP_ERR_INVALID_ARG, "null pointer");
     const bool cap = capturing(s);
-    launch_se3(xi, g->B, g->st, g->jl6, s);
-    launch_fill_u32((uint32_t*)g->fb_count, 0u, 2 * g->B, s);
-    launch_fill_u32((uint32_t*)g->flags, 0u, g->B, s);
+    launch_se3(xi, g->B, g->st, g->jl6, g->fb_count, g->flags, s);
     if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
     if (!queue_search(g, px, py, pz, g->nn_idx, g->nn_d2, s, cap, false))
         return fail(VICP_ERR_INVALID_ARG, "too many pairs for the global search");

@@ -429,7 +429,8 @@ void launch_check_finite(const PairDev* pd, const BlockJob* jobs, int njobs, con
 void launch_copy_fb(const int32_t* fb_count, int32_t* out, int npairs, hipStream_t s);
 
 // differentiable loss
-void launch_se3(const double* xi, int npairs, PairState* st, double* jl6, hipStream_t s);
+void launch_se3(const double* xi, int npairs, PairState* st, double* jl6, int32_t* fb_count, int32_t* flags,
+                hipStream_t s);
 void launch_loss_terms(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px,
                        const float* py, const float* pz, const float* qx, const float* qy,
                        const float* qz, const PairState* st, const unsigned long long* fb_key,
