@@ -98,21 +98,32 @@ hipError_t wait_tags(const uint32_t* first, int count, size_t stride, uint32_t t
 }
 
 // Copies the registration's result block (state, histories, counters,
-// flags) into mapped pinned host memory, then writes the call's tag after
-// it: each thread's stores are fenced at system scope before the barrier,
-// and the tag is the last store.
+// flags) into mapped pinned host memory, block b the words [b * chunk,
+// (b + 1) * chunk), then writes the call's tag into the b-th word after the
+// block: each thread's stores are fenced at system scope before the
+// barrier, and the tag is the block's last store.
+constexpr int kPublishMaxBlocks = 64;
+constexpr int64_t kPublishChunk = 2048;   // words per block (a batch's histories span many)
+
 __global__ __launch_bounds__(256) void k_publish(const uint32_t* __restrict__ src, uint32_t* dst, int64_t words,
                                                  uint32_t tag)
 {
-    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    const int64_t chunk = (words + gridDim.x - 1) / gridDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * chunk, w1 = min(words, w0 + chunk);
+    for (int64_t i = w0 + threadIdx.x; i < w1; i += blockDim.x) dst[i] = src[i];
     __threadfence_system();
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(dst + words, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) __hip_atomic_store(dst + words + blockIdx.x, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int publish_blocks(int64_t words)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kPublishMaxBlocks, (words + kPublishChunk - 1) / kPublishChunk));
 }
 
 void launch_publish(const uint32_t* src, uint32_t* dst, int64_t words, uint32_t tag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, src, dst, words, tag);
+    hipLaunchKernelGGL(k_publish, dim3(publish_blocks(words)), dim3(256), 0, s, src, dst, words, tag);
 }
 
 void upload(const void* host, size_t bytes, void* dst, hipStream_t s)
@@ -723,7 +734,7 @@ int ensure_source(vicp_grid* g, const int64_t* m_per_pair, int K, hipStream_t s)
             g->h_res = nullptr;
             g->d_hres = nullptr;
             g->h_res_cap = 0;
-            const size_t bytes = g->res_bytes + 8;   // the tag after the block
+            const size_t bytes = g->res_bytes + 4 * kPublishMaxBlocks;   // the tags after the block
             if (hipHostMalloc(&g->h_res, bytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
                 hipHostGetDevicePointer(&g->d_hres, g->h_res, 0) == hipSuccess) {
                 memset(g->h_res, 0, bytes);   // no tag is 0
@@ -1827,11 +1838,12 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
     // timing events are to be read)
     if (++g->res_gen == 0) g->res_gen = 1;
     const int64_t rwords = (int64_t)(g->res_bytes / 4);
-    // the tag's word may hold another layout's data from an earlier call
-    __atomic_store_n((uint32_t*)g->h_res + rwords, 0u, __ATOMIC_RELEASE);
+    // the tags' words may hold another layout's data from an earlier call
+    const int npub = publish_blocks(rwords);
+    for (int b = 0; b < npub; ++b) __atomic_store_n((uint32_t*)g->h_res + rwords + b, 0u, __ATOMIC_RELEASE);
     launch_publish((const uint32_t*)g->res, (uint32_t*)g->d_hres, rwords, g->res_gen, s);
     VICP_HIP(hipGetLastError());
-    VICP_HIP(wait_tags((const uint32_t*)g->h_res + rwords, 1, 0, g->res_gen, s));
+    VICP_HIP(wait_tags((const uint32_t*)g->h_res + rwords, npub, 1, g->res_gen, s));
     if (g_prof.on) VICP_HIP(hipStreamSynchronize(s));
     const char* hb = (const char*)g->h_res;
     const PairState* hst = (const PairState*)hb;
