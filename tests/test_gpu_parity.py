@@ -194,10 +194,10 @@ def test_block_size_leaves_the_pose_bit_identical(name, lpq, sort_source):
         assert np.array_equal(r.fallbacks[0], runs[0].fallbacks[0])
 
 
-def test_register_with_global_searches_over_several_windows():
+def test_register_with_many_global_searches():
     # the source starts 0.4 (several voxels) off the target: most queries of the
-    # first iterations go to the global search; 20000 queries span three
-    # windows of the solve's replay of the global-search list
+    # first iterations take the global search (resolved by the voxel shells,
+    # the farthest by the exhaustive search)
     P = synth.bumpy_pair(seed=21, n=6000, m=20000, voxel=0.05, rings=2, iters=8)
     Rt0 = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0.4, -0.1, 0.05], np.float64)
     g = build_grid(dev(P.q), P.voxel, 2).dilate(2)
@@ -205,6 +205,21 @@ def test_register_with_global_searches_over_several_windows():
         res = g.register(dev(P.p), 8, Rt0=Rt0, use_graph=use_graph)
         ref = oracle.register(P.q, P.p, P.voxel, 2, 8, Rt0=Rt0)
         assert ref.fallbacks[0] > 8192
+        assert list(res.fallbacks[0]) == list(ref.fallbacks)
+        assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
+        assert np.linalg.norm(res.Rt[9:] - ref.Rt[9:]) <= T_TOL * P.extent
+        assert np.allclose(res.rmse[0], ref.rmse, rtol=1e-9, atol=0)
+
+
+def test_exhaustive_registration_over_several_windows():
+    # every query takes the exhaustive search: 20000 listed queries span three
+    # windows of the solve's replay of the global-search list (index order)
+    P = synth.bumpy_pair(seed=22, n=6000, m=20000, voxel=0.05, rings=2, iters=3)
+    g = build_grid(dev(P.q), P.voxel, 2).dilate(2)
+    ref = oracle.register_global(P.q, P.p, 3)
+    assert ref.fallbacks[0] == 20000
+    for use_graph in (False, True):
+        res = g.register(dev(P.p), 3, use_graph=use_graph, global_only=True)
         assert list(res.fallbacks[0]) == list(ref.fallbacks)
         assert rot_angle(res.Rt[:9], ref.Rt[:9]) <= ROT_TOL
         assert np.linalg.norm(res.Rt[9:] - ref.Rt[9:]) <= T_TOL * P.extent

@@ -107,8 +107,8 @@ def test_registration_correspondences_match_oracle(name, sched):
 
 def test_correspondences_of_globally_searched_queries():
     # the source starts several voxels off the target: in iteration 0 most
-    # queries take the global search (over 8192, three windows of the solve's
-    # replay), so their correspondences come from the solve
+    # queries (over 8192) take the global search, resolved by the search's
+    # voxel shells or, the farthest, by the exhaustive search and the solve
     P = synth.bumpy_pair(seed=21, n=6000, m=20000, voxel=0.05, rings=2, iters=8)
     Rt0 = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0.4, -0.1, 0.05], np.float64)
     g = build_grid(dev(P.q), P.voxel, 2).dilate(2)
