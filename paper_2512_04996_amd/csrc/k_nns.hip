@@ -316,8 +316,9 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
 // (with a table the chain is table -> pair record -> query).
 //
 // In registration nn_idx / nn_d2 are optional (null when not asked for): the
-// correspondence and squared distance of each locally resolved query are
-// written there too; the solve writes those of the globally searched ones.
+// correspondence and squared distance of each query resolved here (locally,
+// or by the voxel shells of its global search) are written there too; the
+// solve writes those of the exhaustively searched ones.
 template <int BS, int LPQ, bool kSorted, bool kMom, bool kDirect, int kMode, bool kOne>
 __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                   const float* __restrict__ px, const float* __restrict__ py,
