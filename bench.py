@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
+    ap.add_argument("--extra-only", choices=("batched", "diff"), default=None,
+                    help="run only this extra figure (64-pair batch or 16x40k differentiable loss) and print it")
     ap.add_argument("--calib-copy-mib", type=float, default=0.0,
                     help="after the run, one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -102,6 +104,10 @@ def main():
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if a.extra_only:
+        fig = (batched_figure if a.extra_only == "batched" else diff_figure)(api, synth, torch, dev, np)
+        print(json.dumps({"extra_only": a.extra_only, "figure": fig}), flush=True)
+        return
 
     P = synth.config(a.workload)
     q = torch.from_numpy(P.q).to(dev)
@@ -370,7 +376,6 @@ def main():
 
 def extra_figures(api, synth, torch, dev, np):
     """Batched and differentiable forms and the buffer bytes of every workload."""
-    from paper_2512_04996_amd.autograd import p2p_loss
     ex = {}
     # dilation-buffer bytes of the other workloads
     sizes = {}
@@ -478,6 +483,15 @@ def extra_figures(api, synth, torch, dev, np):
         "rotation_gap_deg": ang(Rb, Rd), "translation_gap": float(np.linalg.norm(rb.Rt[9:] - rd.Rt[9:])),
         "rotation_error_deg_exhaustive": ang(Rb, Rtrue), "rotation_error_deg_dilated": ang(Rd, Rtrue)}
     ex["vanicp_comparator"] = vanicp_comparator(api, synth, torch, dev, np)
+    ex["batched_64"] = batched_figure(api, synth, torch, dev, np)
+    ex["diff_16x40k"] = diff_figure(api, synth, torch, dev, np)
+    ex["dilation_buffer_other"] = sizes
+    return ex
+
+
+def batched_figure(api, synth, torch, dev, np):
+    """64 uneven pairs in one launch sequence, against a loop of single-pair runs."""
+    ex = {}
     # batched: 64 uneven pairs in one launch sequence, against a loop of single-pair runs
     log("[bench] batched workload")
     pairs = synth.config("batched_64")
@@ -537,6 +551,13 @@ def extra_figures(api, synth, torch, dev, np):
                         "looped_single_ms": round(tl * 1e3, 3), "speedup_vs_looped": round(tl / tb, 3),
                         "bit_identical_to_looped": bool(same), "fallbacks_iter0": fb0,
                         "vanicp_fixed_bytes": int(65536 * V_total)}
+    return ex["batched_64"]
+
+
+def diff_figure(api, synth, torch, dev, np):
+    """The differentiable loss, 16 x 40k forward + backward, against 16 single-pair calls."""
+    from paper_2512_04996_amd.autograd import p2p_loss
+    ex = {}
     # differentiable: 16 x 40k forward + backward
     log("[bench] differentiable workload")
     dpairs, xi = synth.config("diff_16x40k")
@@ -601,8 +622,7 @@ def extra_figures(api, synth, torch, dev, np):
                          "single_pair_calls_pairs_per_s": round(B / ts, 1),
                          "speedup_vs_single_pair_calls": round(ts / td, 3),
                          "bit_identical_to_single_pair_calls": bool(same)}
-    ex["dilation_buffer_other"] = sizes
-    return ex
+    return ex["diff_16x40k"]
 
 
 def vanicp_comparator(api, synth, torch, dev, np):
