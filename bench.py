@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / differentiable / bytes figures")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel HIP events in the timed region")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="time a step as rebuild, dilate and register in turn instead of one vicp_rebuild_register")
     ap.add_argument("--extra-only", choices=("batched", "diff"), default=None,
                     help="run only this extra figure (64-pair batch or 16x40k differentiable loss) and print it")
     ap.add_argument("--calib-copy-mib", type=float, default=0.0,
@@ -137,9 +139,12 @@ def main():
     build_schedule = g.build_schedule
 
     def step():
-        g.rebuild(q)
-        g.dilate(P.rings)
-        return g.register(p, P.iters, use_graph=bool(a.graph))
+        if a.separate_calls:
+            g.rebuild(q)
+            g.dilate(P.rings)
+            return g.register(p, P.iters, use_graph=bool(a.graph))
+        # the same work in one call: the refill's passes share launches with the source plan's
+        return g.rebuild_register(q, P.rings, p, P.iters, use_graph=bool(a.graph))
 
     log(f"[bench] workload {P.name}: n={P.n} m={P.m} voxel={P.voxel} rings={P.rings} iters={P.iters}")
     # the timed region runs with no timing events at all (events recorded
@@ -334,6 +339,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": P.name, "n_target": P.n, "n_source": P.m, "voxel": P.voxel, "rings": P.rings,
                    "iters": P.iters, "step": "grid build + dilation + 30 ICP iterations",
+                   "step_call": ("vicp_grid_rebuild, vicp_dilate, vicp_register in turn" if a.separate_calls else
+                                 "vicp_rebuild_register (the refill's passes paired with the source plan's in shared launches)"),
                    "icp_mode": "graph" if a.graph else "eager", "schedule": schedule,
                    "build_schedule": build_schedule,
                    "schedule_source": "autotuned" if a.schedule == "auto" else "given",

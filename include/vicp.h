@@ -284,6 +284,21 @@ int vicp_register_batched(const vicp_grid* g, const float* px, const float* py, 
                           const int64_t* m_per_pair, const vicp_icp_opts* opts, double* Rt_io,
                           vicp_icp_stats* stats, hipStream_t stream);
 
+/* The next frame in one call: vicp_grid_rebuild(qx, qy, qz), vicp_dilate(rings)
+ * and vicp_register_batched(px, ...) in turn, with the same results, errors
+ * and waits.  When the schedule buckets the source (Alg. 4's queries sorted
+ * by target voxel), each of the refill's count, scan, scatter and order
+ * passes (Alg. 1-2) shares one launch with the bucketing's matching pass, as
+ * the two are independent; everything stays on `stream`.  Given-geometry
+ * grids, host-side offsets, the packed-hash count, the direct layout,
+ * global_only and searches over the source in index order take the three
+ * calls' path.  Errors: as the three calls (the grid is left as the failing
+ * step leaves it); STATE for a grid that was never built. */
+int vicp_rebuild_register(vicp_grid* g, const float* qx, const float* qy, const float* qz,
+                          int32_t rings, const float* px, const float* py, const float* pz,
+                          const int64_t* m_per_pair, const vicp_icp_opts* opts, double* Rt_io,
+                          vicp_icp_stats* stats, hipStream_t stream);
+
 /* ---- differentiable point-to-point loss ------------------------------------
  * For pair b with pose xi_b = (rho, phi) in R^6 (device float64[npairs*6]),
  * T = Exp(xi_b) in SE(3), correspondences c_i from Alg. 4 at the float32-rounded

@@ -75,6 +75,9 @@ SYMBOLS = {
                                 C.POINTER(C.c_double), C.POINTER(IcpStats), C.c_void_p]),
     "vicp_register_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
                                         C.POINTER(IcpOpts), C.POINTER(C.c_double), C.POINTER(IcpStats), C.c_void_p]),
+    "vicp_rebuild_register": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(IcpOpts),
+                                        C.POINTER(C.c_double), C.POINTER(IcpStats), C.c_void_p]),
     "vicp_p2p_loss_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "vicp_p2p_loss_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),

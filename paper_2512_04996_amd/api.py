@@ -218,6 +218,23 @@ class Grid:
         """The ICP loop (Sec. II.A); with correspondences=True the result also
         carries the last iteration's correspondences, written by the
         registration's own kernels."""
+        return self._register(p, max_iter, rmse_eps, early_stop, use_graph, Rt0, m_per_pair, raise_degenerate,
+                              global_only, layout, correspondences)
+
+    def rebuild_register(self, q: torch.Tensor, rings: int, p: torch.Tensor, max_iter: int, **kw) -> IcpResult:
+        """rebuild(q), dilate(rings) and register(p, max_iter, **kw) in one
+        call, with the same results; the refill's count, scan, scatter and
+        order passes share their launches with the source bucketing's."""
+        q = _soa(q, "q")
+        if q.shape[1] != self.n_total:
+            raise ValueError("rebuild needs the same number of target points")
+        res = self._register(p, max_iter, refill=(q, int(rings)), **kw)
+        self.q = q
+        return res
+
+    def _register(self, p, max_iter, rmse_eps=1e-5, early_stop=False, use_graph=True, Rt0=None, m_per_pair=None,
+                  raise_degenerate=False, global_only=False, layout="segmented", correspondences=False,
+                  refill=None) -> IcpResult:
         p = _soa(p, "p")
         m = p.shape[1]
         B = self.npairs
@@ -243,10 +260,18 @@ class Grid:
                        int(layout == "direct"), out_idx.data_ptr() if correspondences else None,
                        out_d2.data_ptr() if correspondences else None)
         px, py, pz = _ptrs(p)
-        rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
-                                         rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())
+        if refill is None:
+            name = "vicp_register_batched"
+            rc = lib().vicp_register_batched(self.handle, px, py, pz, _i64(m_per_pair), C.byref(opts),
+                                             rt.ctypes.data_as(C.POINTER(C.c_double)), stats, _stream())
+        else:
+            name = "vicp_rebuild_register"
+            qx, qy, qz = _ptrs(refill[0])
+            rc = lib().vicp_rebuild_register(self.handle, qx, qy, qz, refill[1], px, py, pz, _i64(m_per_pair),
+                                             C.byref(opts), rt.ctypes.data_as(C.POINTER(C.c_double)), stats,
+                                             _stream())
         allow = () if raise_degenerate else (_lib.ERR_DEGENERATE,)
-        check(rc, "vicp_register_batched", allow)
+        check(rc, name, allow)
         iters = np.array([stats[b].iters for b in range(B)])
         deg = np.array([stats[b].degenerate for b in range(B)])
         return IcpResult(rt.reshape(B, 12) if B > 1 else rt, iters, deg,

@@ -136,7 +136,7 @@ constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 // counts every point of the voxel, so a count above `cap` marks a block that
 // overflowed.
 template <bool kDirect, int BS>
-__global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
+__device__ __forceinline__ void count_block(int bid, const float* __restrict__ qx, const float* __restrict__ qy,
                                               const float* __restrict__ qz, const PairDev* __restrict__ pd,
                                               const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, cons
         scnt[s] = 0;
     }
     __syncthreads();
-    const BlockJob job = jobs[blockIdx.x];
+    const BlockJob job = jobs[bid];
     const PairDev& P = pd[job.pair];
     const int64_t i = (int64_t)job.start + threadIdx.x;
     bool valid = i < P.n;
@@ -211,6 +211,17 @@ __global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, cons
             rank[g] = r;
         }
     }
+}
+
+template <bool kDirect, int BS>
+__global__ __launch_bounds__(BS) void k_count(const float* __restrict__ qx, const float* __restrict__ qy,
+                                              const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                              const BlockJob* __restrict__ jobs, uint32_t* __restrict__ hist,
+                                              uint32_t* __restrict__ vox, uint32_t* __restrict__ rank,
+                                              uint32_t* err, float4* __restrict__ blk, uint32_t cap,
+                                              uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count)
+{
+    count_block<kDirect, BS>((int)blockIdx.x, qx, qy, qz, pd, jobs, hist, vox, rank, err, blk, cap, big_list, big_count);
 }
 
 // --------------------------------------------------------------------------
@@ -328,7 +339,7 @@ __device__ __forceinline__ void st_status(unsigned long long* p, unsigned long l
 }
 
 template <bool kSeg>
-__global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ hist, int64_t total,
+__device__ __forceinline__ void scan_block(int bid, const uint32_t* __restrict__ hist, int64_t total,
                                                    uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
                                                    uint2* __restrict__ dir, unsigned long long* status,
                                                    uint32_t* ticket)
@@ -444,14 +455,23 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
     }
 }
 
+template <bool kSeg>
+__global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ hist, int64_t total,
+                                                   uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
+                                                   uint2* __restrict__ dir, unsigned long long* status,
+                                                   uint32_t* ticket)
+{
+    scan_block<kSeg>((int)blockIdx.x, hist, total, off, vm, dir, status, ticket);
+}
+
 // --------------------------------------------------------------------------
 // scatter: point i of pair p goes to its voxel's compact slot (any order)
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+__device__ __forceinline__ void place_block(int bid, const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
                                                     const uint32_t* __restrict__ vox, const uint32_t* __restrict__ rank,
                                                     const uint32_t* __restrict__ off, uint32_t* __restrict__ tmp)
 {
-    const BlockJob job = jobs[blockIdx.x];
+    const BlockJob job = jobs[bid];
     const PairDev& P = pd[job.pair];
     const int64_t i = (int64_t)job.start + threadIdx.x;
     if (i >= P.n) return;
@@ -461,13 +481,20 @@ __global__ __launch_bounds__(kThreads) void k_place(const PairDev* __restrict__ 
     tmp[pos] = (uint32_t)i;
 }
 
+__global__ __launch_bounds__(kThreads) void k_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ vox, const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ off, uint32_t* __restrict__ tmp)
+{
+    place_block((int)blockIdx.x, pd, jobs, vox, rank, off, tmp);
+}
+
 // --------------------------------------------------------------------------
 // canonical order: each compact slot k holds point e of voxel g; its final
 // position is the number of points of g with a smaller index (ascending
 // order, the reading of Alg. 2 that removes the lock-order dependence).
 // Also writes the segment-ordered float4 copy of the target.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict__ qx, const float* __restrict__ qy,
+__device__ __forceinline__ void rank_sort_block(int bid, const float* __restrict__ qx, const float* __restrict__ qy,
                                                         const float* __restrict__ qz, const PairDev* __restrict__ pd,
                                                         const BlockJob* __restrict__ jobs, const uint32_t* __restrict__ vox,
                                                         const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
@@ -475,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict_
                                                         float4* __restrict__ qs4, uint32_t sort_min)
 {
     __shared__ uint32_t chunk[kThreads / 64][kCoopChunk];
-    const BlockJob job = jobs[blockIdx.x];
+    const BlockJob job = jobs[bid];
     const PairDev& P = pd[job.pair];
     const int64_t k = (int64_t)job.start + threadIdx.x;
     if (k >= P.n) return;
@@ -492,6 +519,16 @@ __global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict_
     const uint32_t r = coop ? rank_in_wave(tmp, cs, c, e, chunk[threadIdx.x / 64]) : rank_in(tmp, cs, c, e);
     vm[(int64_t)og + 2 + r] = e;
     qs4[cs + r] = make_float4(qx[ge], qy[ge], qz[ge], __uint_as_float(e));
+}
+
+__global__ __launch_bounds__(kThreads) void k_rank_sort(const float* __restrict__ qx, const float* __restrict__ qy,
+                                                        const float* __restrict__ qz, const PairDev* __restrict__ pd,
+                                                        const BlockJob* __restrict__ jobs, const uint32_t* __restrict__ vox,
+                                                        const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ tmp, uint32_t* __restrict__ vm,
+                                                        float4* __restrict__ qs4, uint32_t sort_min)
+{
+    rank_sort_block((int)blockIdx.x, qx, qy, qz, pd, jobs, vox, hist, off, tmp, vm, qs4, sort_min);
 }
 
 // Long segments (kSegSortMin to kSegSortMax points) of a single-pair grid,
@@ -669,6 +706,223 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
         p[i] = v;
 }
 
+// --------------------------------------------------------------------------
+// source bucketing by target voxel at the current pose (outside -> bucket V)
+// --------------------------------------------------------------------------
+constexpr int kBThreads = 256;
+constexpr int kBSlots = 2 * kBThreads;
+
+__device__ __forceinline__ void src_bucket_block(int bid, const PairDev* __restrict__ pd,
+                                                          const BlockJob* __restrict__ jobs,
+                                                          const float* __restrict__ px, const float* __restrict__ py,
+                                                          const float* __restrict__ pz,
+                                                          const PairState* __restrict__ st, uint32_t* __restrict__ sh,
+                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank,
+                                                          int32_t* __restrict__ sbig, int32_t* __restrict__ flags)
+{
+    __shared__ uint32_t key_[kBSlots];
+    __shared__ uint32_t cnt_[kBSlots];
+    __shared__ uint32_t base_[kBSlots];
+    for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
+        key_[s] = kNone;
+        cnt_[s] = 0;
+    }
+    __syncthreads();
+    const BlockJob job = jobs[bid];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    const bool valid = i < P.m;
+    uint32_t key = 0, slot = 0, lr = 0;
+    if (valid) {
+        const int64_t gp = P.p_base + i;
+        const float x = px[gp], y = py[gp], z = pz[gp];
+        // this pass reads every source point, so it also flags non-finite
+        // coordinates (bit 0 of the pair's fault flags)
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(&flags[job.pair], 1);
+        float sx, sy, sz;
+        transform(st[job.pair].Rtf, x, y, z, sx, sy, sz);
+        uint32_t v;
+        int64_t b;
+        if (voxel_of(P, sx, sy, sz, v))
+            b = (int64_t)v * P.s_chunks + (P.s_shift < 62 ? (i >> P.s_shift) : 0);
+        else
+            b = P.V * P.s_chunks + (i >> kOutShift);
+        key = (uint32_t)(P.s_base + b);
+        slot = (key * 2654435761u) >> 23;
+        while (true) {
+            const uint32_t prev = atomicCAS(&key_[slot], kNone, key);
+            if (prev == kNone || prev == key) break;
+            slot = (slot + 1) & (kBSlots - 1);
+        }
+        lr = atomicAdd(&cnt_[slot], 1u);
+    }
+    __syncthreads();
+    // one global atomic per occupied slot, this thread's slots all in flight
+    // together (a loop of atomics waits for each return in turn)
+    {
+        constexpr int kPer = kBSlots / kBThreads;
+        uint32_t kk[kPer], cc[kPer], bb[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            kk[j] = key_[threadIdx.x + j * kBThreads];
+            cc[j] = cnt_[threadIdx.x + j * kBThreads];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) bb[j] = kk[j] != kNone ? atomicAdd(&sh[kk[j]], cc[j]) : 0u;
+        bool big = false;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            base_[threadIdx.x + j * kBThreads] = bb[j];
+            big |= kk[j] != kNone && bb[j] + cc[j] > kRankCap;
+        }
+        if (big) atomicOr(&sbig[job.pair], 1);
+    }
+    __syncthreads();
+    if (valid) {
+        skey[P.p_base + i] = key;
+        srank[P.p_base + i] = base_[slot] + lr;
+    }
+}
+
+__global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restrict__ pd,
+                                                          const BlockJob* __restrict__ jobs,
+                                                          const float* __restrict__ px, const float* __restrict__ py,
+                                                          const float* __restrict__ pz,
+                                                          const PairState* __restrict__ st, uint32_t* __restrict__ sh,
+                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank,
+                                                          int32_t* __restrict__ sbig, int32_t* __restrict__ flags)
+{
+    src_bucket_block((int)blockIdx.x, pd, jobs, px, py, pz, st, sh, skey, srank, sbig, flags);
+}
+
+// Puts each source point's index at its bucket position (a global position
+// inside the pair's range, because buckets are concatenated in pair order);
+// the order inside a bucket is whatever the counting atomics gave.
+__device__ __forceinline__ void src_place_block(int bid, const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                   const uint32_t* __restrict__ skey,
+                                                   const uint32_t* __restrict__ srank,
+                                                   const uint32_t* __restrict__ soff, uint32_t* __restrict__ sidx)
+{
+    const BlockJob job = jobs[bid];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.m) return;
+    const int64_t gp = P.p_base + i;
+    sidx[(int64_t)soff[skey[gp]] + srank[gp]] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_src_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                   const uint32_t* __restrict__ skey,
+                                                   const uint32_t* __restrict__ srank,
+                                                   const uint32_t* __restrict__ soff, uint32_t* __restrict__ sidx)
+{
+    src_place_block((int)blockIdx.x, pd, jobs, skey, srank, soff, sidx);
+}
+
+// Final position = bucket start + the number of smaller indices in the
+// bucket (ascending order within a bucket); a pair with a bucket above
+// kRankCap keeps its points in index order instead.
+__device__ __forceinline__ void src_rank_block(int bid, const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                  const float* __restrict__ px, const float* __restrict__ py,
+                                                  const float* __restrict__ pz, const uint32_t* __restrict__ skey,
+                                                  const uint32_t* __restrict__ soff, const uint32_t* __restrict__ sidx,
+                                                  const int32_t* __restrict__ sbig, float4* __restrict__ ps4)
+{
+    const BlockJob job = jobs[bid];
+    const PairDev& P = pd[job.pair];
+    const int64_t i = (int64_t)job.start + threadIdx.x;
+    if (i >= P.m) return;
+    const int64_t gp = P.p_base + i;
+    int64_t pos = gp;
+    if (sbig[job.pair] == 0) {
+        const uint32_t key = skey[gp];
+        const uint32_t lo = soff[key], hi = soff[key + 1];
+        pos = (int64_t)lo + rank_in(sidx, lo, hi - lo, (uint32_t)i);
+    }
+    ps4[pos] = make_float4(px[gp], py[gp], pz[gp], __uint_as_float((uint32_t)i));
+}
+
+__global__ __launch_bounds__(256) void k_src_rank(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
+                                                  const float* __restrict__ px, const float* __restrict__ py,
+                                                  const float* __restrict__ pz, const uint32_t* __restrict__ skey,
+                                                  const uint32_t* __restrict__ soff, const uint32_t* __restrict__ sidx,
+                                                  const int32_t* __restrict__ sbig, float4* __restrict__ ps4)
+{
+    src_rank_block((int)blockIdx.x, pd, jobs, px, py, pz, skey, soff, sidx, sbig, ps4);
+}
+
+
+// --------------------------------------------------------------------------
+// The refill and the source plan side by side (vicp_rebuild_register): the
+// two are independent, so each of their passes shares one launch with the
+// other's matching pass, the refill's blocks first, then the plan's.  A
+// block runs one of the two bodies, so each keeps its own barriers, LDS and
+// scan tickets (a scan's tiles wait only on earlier tiles of the same scan,
+// which took their tickets first and so are already running).
+// --------------------------------------------------------------------------
+static_assert(kBThreads == kThreads, "the paired passes share one block size");
+
+__global__ __launch_bounds__(kThreads) void k_count_bucket(
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+    const PairDev* __restrict__ pd, const BlockJob* __restrict__ qjobs, int nq, uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ vox, uint32_t* __restrict__ rank, uint32_t* err, const BlockJob* __restrict__ pjobs,
+    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+    const PairState* __restrict__ st, uint32_t* __restrict__ sh, uint32_t* __restrict__ skey,
+    uint32_t* __restrict__ srank, int32_t* __restrict__ sbig, int32_t* __restrict__ flags)
+{
+    const int b = (int)blockIdx.x;
+    if (b < nq)
+        count_block<false, kThreads>(b, qx, qy, qz, pd, qjobs, hist, vox, rank, err, nullptr, 0u, nullptr, nullptr);
+    else
+        src_bucket_block(b - nq, pd, pjobs, px, py, pz, st, sh, skey, srank, sbig, flags);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_pair(const uint32_t* __restrict__ hist, int64_t total,
+                                                        uint32_t* __restrict__ off, uint32_t* __restrict__ vm,
+                                                        uint2* __restrict__ dir, unsigned long long* status,
+                                                        uint32_t* ticket, int na, const uint32_t* __restrict__ sh,
+                                                        int64_t nb, uint32_t* __restrict__ soff,
+                                                        unsigned long long* s_status, uint32_t* s_ticket)
+{
+    if ((int)blockIdx.x < na)
+        scan_block<true>(0, hist, total, off, vm, dir, status, ticket);
+    else
+        scan_block<false>(0, sh, nb, soff, nullptr, nullptr, s_status, s_ticket);
+}
+
+__global__ __launch_bounds__(kThreads) void k_place_pair(const PairDev* __restrict__ pd,
+                                                         const BlockJob* __restrict__ qjobs, int nq,
+                                                         const uint32_t* __restrict__ vox,
+                                                         const uint32_t* __restrict__ rank,
+                                                         const uint32_t* __restrict__ off, uint32_t* __restrict__ tmp,
+                                                         const BlockJob* __restrict__ pjobs,
+                                                         const uint32_t* __restrict__ skey,
+                                                         const uint32_t* __restrict__ srank,
+                                                         const uint32_t* __restrict__ soff, uint32_t* __restrict__ sidx)
+{
+    const int b = (int)blockIdx.x;
+    if (b < nq)
+        place_block(b, pd, qjobs, vox, rank, off, tmp);
+    else
+        src_place_block(b - nq, pd, pjobs, skey, srank, soff, sidx);
+}
+
+__global__ __launch_bounds__(kThreads) void k_rank_pair(
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+    const PairDev* __restrict__ pd, const BlockJob* __restrict__ qjobs, int nq, const uint32_t* __restrict__ vox,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off, const uint32_t* __restrict__ tmp,
+    uint32_t* __restrict__ vm, float4* __restrict__ qs4, const BlockJob* __restrict__ pjobs,
+    const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ soff, const uint32_t* __restrict__ sidx,
+    const int32_t* __restrict__ sbig, float4* __restrict__ ps4)
+{
+    const int b = (int)blockIdx.x;
+    if (b < nq)
+        rank_sort_block(b, qx, qy, qz, pd, qjobs, vox, hist, off, tmp, vm, qs4, 0xFFFFFFFFu);
+    else
+        src_rank_block(b - nq, pd, pjobs, px, py, pz, skey, soff, sidx, sbig, ps4);
+}
+
 }  // namespace
 
 void launch_aabb(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* jobs,
@@ -773,6 +1027,72 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
     if (count <= 0) return;
     const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+}
+
+void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                       const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
+                       int32_t* sbig, int32_t* flags, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank,
+                       sbig, flags);
+}
+
+void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,
+                      const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_place, dim3(njobs), dim3(256), 0, s, pd, jobs, skey, srank, soff, sidx);
+}
+
+void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
+                     const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
+                     const int32_t* sbig, float4* ps4, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_src_rank, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, soff, sidx, sbig, ps4);
+}
+
+
+void launch_count_bucket(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                         const BlockJob* qjobs, int nq, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err,
+                         const BlockJob* pjobs, int np, const float* px, const float* py, const float* pz,
+                         const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank, int32_t* sbig,
+                         int32_t* flags, hipStream_t s)
+{
+    if (nq + np <= 0) return;
+    launch_timed(k_count_bucket, dim3(nq + np), dim3(kThreads), s, qx, qy, qz, pd, qjobs, nq, hist, vox, rank, err,
+                 pjobs, px, py, pz, st, sh, skey, srank, sbig, flags);
+}
+
+void launch_scan_pair(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, uint2* dir,
+                      unsigned long long* status, uint32_t* ticket, const uint32_t* sh, int64_t nb, uint32_t* soff,
+                      unsigned long long* s_status, uint32_t* s_ticket, hipStream_t s)
+{
+    const int na = scan_tiles(total), nbt = scan_tiles(nb);
+    if (na + nbt <= 0) return;
+    launch_timed(k_scan_pair, dim3(na + nbt), dim3(kThreads), s, hist, total, off, vm, dir, status, ticket, na, sh, nb,
+                 soff, s_status, s_ticket);
+}
+
+void launch_place_pair(const PairDev* pd, const BlockJob* qjobs, int nq, const uint32_t* vox, const uint32_t* rank,
+                       const uint32_t* off, uint32_t* tmp, const BlockJob* pjobs, int np, const uint32_t* skey,
+                       const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s)
+{
+    if (nq + np <= 0) return;
+    launch_timed(k_place_pair, dim3(nq + np), dim3(kThreads), s, pd, qjobs, nq, vox, rank, off, tmp, pjobs, skey,
+                 srank, soff, sidx);
+}
+
+void launch_rank_pair(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* qjobs,
+                      int nq, const uint32_t* vox, const uint32_t* hist, const uint32_t* off, const uint32_t* tmp,
+                      uint32_t* vm, float4* qs4, const BlockJob* pjobs, int np, const float* px, const float* py,
+                      const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
+                      const int32_t* sbig, float4* ps4, hipStream_t s)
+{
+    if (nq + np <= 0) return;
+    launch_timed(k_rank_pair, dim3(nq + np), dim3(kThreads), s, qx, qy, qz, pd, qjobs, nq, vox, hist, off, tmp, vm,
+                 qs4, pjobs, px, py, pz, skey, soff, sidx, sbig, ps4);
 }
 
 }  // namespace vicp

@@ -37,30 +37,10 @@ namespace {
 
 constexpr int kWave = 64;
 
-__device__ __forceinline__ void transform(const float* __restrict__ R, float x, float y, float z, float& sx, float& sy,
-                                          float& sz)
-{
-    sx = __builtin_fmaf(R[0], x, __builtin_fmaf(R[1], y, __builtin_fmaf(R[2], z, R[9])));
-    sy = __builtin_fmaf(R[3], x, __builtin_fmaf(R[4], y, __builtin_fmaf(R[5], z, R[10])));
-    sz = __builtin_fmaf(R[6], x, __builtin_fmaf(R[7], y, __builtin_fmaf(R[8], z, R[11])));
-}
-
 __device__ __forceinline__ float dist2(float sx, float sy, float sz, float qx, float qy, float qz)
 {
     const float dx = sx - qx, dy = sy - qy, dz = sz - qz;
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-}
-
-// Voxel of a transformed point, or false when it is outside the grid.
-__device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, float sz, uint32_t& v)
-{
-    const float fx = (sx - P.ox) * P.inv;
-    const float fy = (sy - P.oy) * P.inv;
-    const float fz = (sz - P.oz) * P.inv;
-    // non-short-circuit: no branch waits on each bound's load in turn
-    const bool in = (fx >= 0.0f) & (fx < P.fDx) & (fy >= 0.0f) & (fy < P.fDy) & (fz >= 0.0f) & (fz < P.fDz);
-    if (in) v = (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
-    return in;
 }
 
 // The value of lane (this lane xor d): a DPP quad permutation for d = 1, 2
@@ -581,123 +561,6 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
     }
 }
 
-// --------------------------------------------------------------------------
-// source bucketing by target voxel at the current pose (outside -> bucket V)
-// --------------------------------------------------------------------------
-constexpr int kBThreads = 256;
-constexpr int kBSlots = 2 * kBThreads;
-
-__global__ __launch_bounds__(kBThreads) void k_src_bucket(const PairDev* __restrict__ pd,
-                                                          const BlockJob* __restrict__ jobs,
-                                                          const float* __restrict__ px, const float* __restrict__ py,
-                                                          const float* __restrict__ pz,
-                                                          const PairState* __restrict__ st, uint32_t* __restrict__ sh,
-                                                          uint32_t* __restrict__ skey, uint32_t* __restrict__ srank,
-                                                          int32_t* __restrict__ sbig, int32_t* __restrict__ flags)
-{
-    __shared__ uint32_t key_[kBSlots];
-    __shared__ uint32_t cnt_[kBSlots];
-    __shared__ uint32_t base_[kBSlots];
-    for (int s = threadIdx.x; s < kBSlots; s += kBThreads) {
-        key_[s] = kNone;
-        cnt_[s] = 0;
-    }
-    __syncthreads();
-    const BlockJob job = jobs[blockIdx.x];
-    const PairDev& P = pd[job.pair];
-    const int64_t i = (int64_t)job.start + threadIdx.x;
-    const bool valid = i < P.m;
-    uint32_t key = 0, slot = 0, lr = 0;
-    if (valid) {
-        const int64_t gp = P.p_base + i;
-        const float x = px[gp], y = py[gp], z = pz[gp];
-        // this pass reads every source point, so it also flags non-finite
-        // coordinates (bit 0 of the pair's fault flags)
-        if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(&flags[job.pair], 1);
-        float sx, sy, sz;
-        transform(st[job.pair].Rtf, x, y, z, sx, sy, sz);
-        uint32_t v;
-        int64_t b;
-        if (voxel_of(P, sx, sy, sz, v))
-            b = (int64_t)v * P.s_chunks + (P.s_shift < 62 ? (i >> P.s_shift) : 0);
-        else
-            b = P.V * P.s_chunks + (i >> kOutShift);
-        key = (uint32_t)(P.s_base + b);
-        slot = (key * 2654435761u) >> 23;
-        while (true) {
-            const uint32_t prev = atomicCAS(&key_[slot], kNone, key);
-            if (prev == kNone || prev == key) break;
-            slot = (slot + 1) & (kBSlots - 1);
-        }
-        lr = atomicAdd(&cnt_[slot], 1u);
-    }
-    __syncthreads();
-    // one global atomic per occupied slot, this thread's slots all in flight
-    // together (a loop of atomics waits for each return in turn)
-    {
-        constexpr int kPer = kBSlots / kBThreads;
-        uint32_t kk[kPer], cc[kPer], bb[kPer];
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            kk[j] = key_[threadIdx.x + j * kBThreads];
-            cc[j] = cnt_[threadIdx.x + j * kBThreads];
-        }
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) bb[j] = kk[j] != kNone ? atomicAdd(&sh[kk[j]], cc[j]) : 0u;
-        bool big = false;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            base_[threadIdx.x + j * kBThreads] = bb[j];
-            big |= kk[j] != kNone && bb[j] + cc[j] > kRankCap;
-        }
-        if (big) atomicOr(&sbig[job.pair], 1);
-    }
-    __syncthreads();
-    if (valid) {
-        skey[P.p_base + i] = key;
-        srank[P.p_base + i] = base_[slot] + lr;
-    }
-}
-
-// Puts each source point's index at its bucket position (a global position
-// inside the pair's range, because buckets are concatenated in pair order);
-// the order inside a bucket is whatever the counting atomics gave.
-__global__ __launch_bounds__(256) void k_src_place(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
-                                                   const uint32_t* __restrict__ skey,
-                                                   const uint32_t* __restrict__ srank,
-                                                   const uint32_t* __restrict__ soff, uint32_t* __restrict__ sidx)
-{
-    const BlockJob job = jobs[blockIdx.x];
-    const PairDev& P = pd[job.pair];
-    const int64_t i = (int64_t)job.start + threadIdx.x;
-    if (i >= P.m) return;
-    const int64_t gp = P.p_base + i;
-    sidx[(int64_t)soff[skey[gp]] + srank[gp]] = (uint32_t)i;
-}
-
-// Final position = bucket start + the number of smaller indices in the
-// bucket (ascending order within a bucket); a pair with a bucket above
-// kRankCap keeps its points in index order instead.
-__global__ __launch_bounds__(256) void k_src_rank(const PairDev* __restrict__ pd, const BlockJob* __restrict__ jobs,
-                                                  const float* __restrict__ px, const float* __restrict__ py,
-                                                  const float* __restrict__ pz, const uint32_t* __restrict__ skey,
-                                                  const uint32_t* __restrict__ soff, const uint32_t* __restrict__ sidx,
-                                                  const int32_t* __restrict__ sbig, float4* __restrict__ ps4)
-{
-    const BlockJob job = jobs[blockIdx.x];
-    const PairDev& P = pd[job.pair];
-    const int64_t i = (int64_t)job.start + threadIdx.x;
-    if (i >= P.m) return;
-    const int64_t gp = P.p_base + i;
-    int64_t pos = gp;
-    if (sbig[job.pair] == 0) {
-        const uint32_t key = skey[gp];
-        const uint32_t lo = soff[key], hi = soff[key + 1];
-        pos = (int64_t)lo + rank_in(sidx, lo, hi - lo, (uint32_t)i);
-    }
-    ps4[pos] = make_float4(px[gp], py[gp], pz[gp], __uint_as_float((uint32_t)i));
-}
-
 // Global search.  Work item = (pair, chunk of kFbQ listed queries, tile of
 // kFbT targets); items are enumerated from the device-side list lengths, so
 // the launch shape is fixed (graph-capturable) whatever the number of misses.
@@ -977,30 +840,6 @@ void launch_nns_local(const PairDev* pd, const BlockJob* jobs, int njobs, int bl
 #undef VICP_NNS_BS
 #undef VICP_NNS_L
 #undef VICP_NNS
-}
-
-void launch_src_bucket(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                       const float* pz, const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank,
-                       int32_t* sbig, int32_t* flags, hipStream_t s)
-{
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_src_bucket, dim3(njobs), dim3(kBThreads), 0, s, pd, jobs, px, py, pz, st, sh, skey, srank,
-                       sbig, flags);
-}
-
-void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const uint32_t* skey,
-                      const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s)
-{
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_src_place, dim3(njobs), dim3(256), 0, s, pd, jobs, skey, srank, soff, sidx);
-}
-
-void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
-                     const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
-                     const int32_t* sbig, float4* ps4, hipStream_t s)
-{
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_src_rank, dim3(njobs), dim3(256), 0, s, pd, jobs, px, py, pz, skey, soff, sidx, sbig, ps4);
 }
 
 bool launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,

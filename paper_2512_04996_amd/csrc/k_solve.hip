@@ -533,20 +533,7 @@ __device__ __forceinline__ void set_state_one(const PairDev* __restrict__ pd, Pa
                                               const double* rt, int npairs, int32_t* __restrict__ fb_count,
                                               int32_t* __restrict__ flags)
 {
-    fb_count[p] = 0;
-    fb_count[npairs + p] = 0;
-    flags[p] = 0;
-    PairState& S = st[p];
-    S.done = pd[p].m > 0 ? 0 : 1;
-    for (int j = 0; j < 12; ++j) {
-        S.Rt[j] = rt[j];
-        S.Rtf[j] = (float)rt[j];
-    }
-    S.prev_rmse = 0.0;
-    S.iters = 0;
-    S.degenerate = 0;
-    S.status = 0;
-    S.rot_ok = 0;   // a caller's rotation: the first solve checks it
+    init_pair_state(st, p, rt, pd[p].m, npairs, fb_count, flags);
 }
 
 // The poses travel in the launch's arguments (up to kInlinePairs pairs).

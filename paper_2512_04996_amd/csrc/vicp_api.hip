@@ -68,6 +68,39 @@ __global__ void k_clear4_blob(Blob blob, uint32_t* __restrict__ dst, int nwords,
     }
 }
 
+// The first launch of a paired refill and plan (vicp_rebuild_register): the
+// pair records (block 0), the zeroing of the refill's histogram, scan states,
+// tickets and error words and of the plan's bucket counts, scan states,
+// tickets and cap flags, and each pair's state at its pose (poses and source
+// sizes travel in the launch: at most kInlinePairs pairs).
+struct FrameStart {
+    double rt[12 * kInlinePairs];
+    int64_t m[kInlinePairs];
+    uint32_t* z32[6];
+    int64_t n32[6];
+    unsigned long long* z64[2];
+    int64_t n64[2];
+};
+
+__global__ void k_start_frame(Blob blob, uint32_t* __restrict__ dst, int nwords, FrameStart f, int npairs,
+                              PairState* __restrict__ st, int32_t* __restrict__ fb_count, int32_t* __restrict__ flags,
+                              int64_t n)
+{
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = blob.w[i];
+        if ((int)threadIdx.x < npairs)
+            init_pair_state(st, threadIdx.x, f.rt + 12 * threadIdx.x, f.m[threadIdx.x], npairs, fb_count, flags);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (i < f.n32[k]) f.z32[k][i] = 0u;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (i < f.n64[k]) f.z64[k][i] = 0ull;
+    }
+}
+
 void launch_clear4_blob(const Blob& blob, uint32_t* dst, int nwords, uint32_t* a, int64_t na, unsigned long long* b,
                         int64_t nb, uint32_t* c, int64_t nc, uint32_t* d, int64_t nd, hipStream_t s)
 {
@@ -1154,10 +1187,9 @@ bool count_packed(const vicp_grid* g)
 // histogram (Alg. 1 GPU part), offsets, and the segments in ascending
 // order (Alg. 2).  The fixed-grid check and the host-side offset scan
 // synchronise, so grid_fill runs those forms itself.
-void queue_build(vicp_grid* g, hipStream_t s, bool cap)
+void queue_build_rest(vicp_grid* g, hipStream_t s, bool cap)
 {
     const int64_t Vt = g->V_total;
-    clear_for_build(g, s);
     queue_count(g, g->qx, g->qy, g->qz, count_packed(g), s, cap);
     {
         ProfScope ps("scan", s, cap, true);
@@ -1172,6 +1204,12 @@ void queue_build(vicp_grid* g, hipStream_t s, bool cap)
         launch_rank_sort(g->qx, g->qy, g->qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots,
                          g->vm, g->qs4, s);
     }
+}
+
+void queue_build(vicp_grid* g, hipStream_t s, bool cap)
+{
+    clear_for_build(g, s);
+    queue_build_rest(g, s, cap);
 }
 
 // Fills (or refills) a grid from target coordinates: bounding box (the one
@@ -1770,8 +1808,11 @@ int check_register(const vicp_grid* g, const float* px, const float* py, const f
 }
 
 // The registration (vicp_register_batched).
+// started: the per-pair state and the source plan are already queued (by
+// vicp_rebuild_register, on its second stream, which s waits for).
 int register_impl(vicp_grid* g, const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
-                  const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats, hipStream_t s)
+                  const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats, hipStream_t s,
+                  bool started = false)
 {
     int rc = check_grid(g);
     if (rc) return rc;
@@ -1801,7 +1842,8 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
     int32_t* out_idx = o->nn_idx;
     float* out_d2 = o->nn_d2;
     constexpr const char* kTooMany = "too many pairs for the global search";
-    queue_start(g, Rt_io, px, py, pz, s);
+    if (!started) queue_start(g, Rt_io, px, py, pz, s);
+    const bool plan = g->sort_src && !started;
     vicp_grid::Captured& cg = g->reg;
     if (o->use_graph) {
         std::vector<uintptr_t> key = {(uintptr_t)px, (uintptr_t)py, (uintptr_t)pz, (uintptr_t)K, (uintptr_t)early,
@@ -1815,8 +1857,9 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
         memcpy(&eb, &eps, 8);
         key.push_back((uintptr_t)eb);
         key.push_back((uintptr_t)(g_prof.on ? 1 : 0));
+        key.push_back((uintptr_t)(plan ? 1 : 0));
         rc = capture_into(g, cg, key, [&](hipStream_t cs) {
-            if (g->sort_src) queue_plan(g, px, py, pz, cs, true);
+            if (plan) queue_plan(g, px, py, pz, cs, true);
             bool queued = true;
             for (int k = 0; k < K && queued; ++k)
                 queued = queue_iteration(g, px, py, pz, k, K, early, eps, cs, true, all_global, direct, out_idx,
@@ -1828,7 +1871,7 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
         VICP_HIP(hipGraphLaunch(cg.exec, s));
     } else {
         const bool cap = capturing(s);
-        if (g->sort_src) queue_plan(g, px, py, pz, s, cap);
+        if (plan) queue_plan(g, px, py, pz, s, cap);
         for (int k = 0; k < K; ++k)
             if (!queue_iteration(g, px, py, pz, k, K, early, eps, s, cap, all_global, direct, out_idx, out_d2))
                 return fail(VICP_ERR_INVALID_ARG, kTooMany);
@@ -1877,9 +1920,117 @@ int register_impl(vicp_grid* g, const float* px, const float* py, const float* p
     return VICP_OK;
 }
 
+// Refill, dilation and registration in one call (vicp_rebuild_register).
+// The refill's host part (bounding box, grid specification) comes first;
+// then the pair records and the per-pair state are written, and each of the
+// refill's count, scan, scatter and order passes runs in one launch with the
+// source plan's matching pass (the two are independent: the plan reads the
+// pair records, the pose state and the source, and writes only its own
+// buffers, the state, the global-search counts and the fault flags, none of
+// which the refill touches).  The dilation and the loop follow.  Forms that
+// synchronise inside the refill (given geometry, host-side offsets), searches
+// over the source in index order (no plan), the direct layout and the
+// exhaustive comparator run the three steps in turn.
+int rebuild_register_impl(vicp_grid* g, const float* qx, const float* qy, const float* qz, int32_t rings,
+                          const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                          const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats, hipStream_t s)
+{
+    if (!g) return fail(VICP_ERR_INVALID_ARG, "null grid");
+    if (!g->hist) return fail(VICP_ERR_STATE, "grid not built");
+    if (!qx || !qy || !qz) return fail(VICP_ERR_INVALID_ARG, "null pointer");
+    if (rings < 0 || rings > g->pad) return fail(VICP_ERR_INVALID_ARG, "rings must be in [0, pad_rings]");
+    int rc = check_register(g, px, py, pz, m_per_pair, o, Rt_io);
+    if (rc) return rc;
+    int64_t mt = 0;
+    for (int p = 0; p < g->B; ++p) mt += m_per_pair[p];
+    const bool paired = !g->fixed && !g->host_offsets && !g->packed_hash && g->sort_src && mt > 0 &&
+                        o->max_iter > 0 && o->layout == 0 && o->global_only == 0;
+    if (!paired) {
+        rc = grid_fill(g, qx, qy, qz, s);
+        if (rc) return rc;
+        rc = vicp_dilate(g, rings, s);
+        if (rc) return rc;
+        return register_impl(g, px, py, pz, m_per_pair, o, Rt_io, stats, s);
+    }
+    rc = grid_fill_host(g, qx, qy, qz, s);
+    if (rc) return rc;
+    rc = ensure_source(g, m_per_pair, o->max_iter, s);
+    if (rc) return rc;
+    fill_pairdev(g, g->h_pd);   // the pair records with the source's fields
+    const bool cap = capturing(s);
+    const int64_t Vt = g->V_total;
+    const int64_t nb = source_buckets(g, g->m);
+    const BlockJob* pj = g->jobs_p[kT256];
+    const int np = g->njobs_p[kT256];
+    const size_t pd_bytes = sizeof(PairDev) * g->h_pd.size();
+    if (g->B <= kInlinePairs && pd_bytes <= sizeof(Blob)) {
+        // one launch for the records, both passes' clears and the states
+        Blob bl;
+        memcpy(bl.w, g->h_pd.data(), pd_bytes);
+        FrameStart f{};
+        for (int p = 0; p < g->B; ++p) {
+            for (int j = 0; j < 12; ++j) f.rt[12 * p + j] = Rt_io[12 * p + j];
+            f.m[p] = g->m[p];
+        }
+        uint32_t* z32[6] = {g->hist, g->scan_ticket, g->err, g->sh, g->s_ticket, (uint32_t*)g->sbig};
+        const int64_t n32[6] = {Vt, 4, 4, nb, 4, g->B};
+        for (int k = 0; k < 6; ++k) {
+            f.z32[k] = z32[k];
+            f.n32[k] = n32[k];
+        }
+        f.z64[0] = g->scan_status;
+        f.n64[0] = scan_tiles(Vt);
+        f.z64[1] = g->s_status;
+        f.n64[1] = scan_tiles(nb);
+        const int64_t n = std::max(Vt, nb);
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+        hipLaunchKernelGGL(k_start_frame, dim3(blocks), dim3(256), 0, s, bl, (uint32_t*)g->d_pd, (int)(pd_bytes / 4), f,
+                           g->B, g->st, g->fb_count, g->flags, n);
+    } else {
+        clear_for_build(g, s);
+        queue_start(g, Rt_io, px, py, pz, s);
+        launch_clear4(g->sh, nb, g->s_status, scan_tiles(nb), g->s_ticket, 4, (uint32_t*)g->sbig, g->B, s);
+    }
+    {
+        ProfScope ps("count_bucket", s, cap, true);
+        launch_count_bucket(g->qx, g->qy, g->qz, g->d_pd, g->jobs_q, g->njobs_q, g->hist, g->vox, g->rank, g->err,
+                            pj, np, px, py, pz, g->st, g->sh, g->skey, g->srank, g->sbig, g->flags, s);
+    }
+    {
+        ProfScope ps("scan_pair", s, cap, true);
+        launch_scan_pair(g->hist, Vt, g->off, g->vm, g->dir, g->scan_status, g->scan_ticket, g->sh, nb, g->soff,
+                         g->s_status, g->s_ticket, s);
+    }
+    {
+        ProfScope ps("place_pair", s, cap, true);
+        launch_place_pair(g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->rank, g->off, g->slots, pj, np, g->skey,
+                          g->srank, g->soff, g->sidx, s);
+    }
+    {
+        ProfScope ps("rank_pair", s, cap, true);
+        launch_rank_pair(g->qx, g->qy, g->qz, g->d_pd, g->jobs_q, g->njobs_q, g->vox, g->hist, g->off, g->slots,
+                         g->vm, g->qs4, pj, np, px, py, pz, g->skey, g->soff, g->sidx, g->sbig, g->ps4, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VICP_ERR_HIP, std::string("grid build: ") + hipGetErrorString(e));
+    g->usable = true;
+    g->dilated = true;
+    g->rings_applied = rings;
+    queue_dilate(g, rings, s, cap);
+    return register_impl(g, px, py, pz, m_per_pair, o, Rt_io, stats, s, true);
+}
+
 }  // namespace
 
 extern "C" {
+
+int vicp_rebuild_register(vicp_grid* g, const float* qx, const float* qy, const float* qz, int32_t rings,
+                          const float* px, const float* py, const float* pz, const int64_t* m_per_pair,
+                          const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats, hipStream_t s)
+{
+    (void)hipGetLastError();   // an error left by other code is not ours to report
+    return rebuild_register_impl(g, qx, qy, qz, rings, px, py, pz, m_per_pair, o, Rt_io, stats, s);
+}
 
 int vicp_register_batched(const vicp_grid* gc, const float* px, const float* py, const float* pz,
                           const int64_t* m_per_pair, const vicp_icp_opts* o, double* Rt_io, vicp_icp_stats* stats,

@@ -129,6 +129,50 @@ struct PairState {
     int32_t rot_ok;     // Rt's rotation is a solve's result (orthogonal to rounding)
 };
 
+// Pair p's registration state at pose rt (float64, R row-major then t) for a
+// source of m points, with its global-search counts and fault flags zeroed.
+__device__ __forceinline__ void init_pair_state(PairState* __restrict__ st, int p, const double* rt, int64_t m,
+                                                int npairs, int32_t* __restrict__ fb_count,
+                                                int32_t* __restrict__ flags)
+{
+    fb_count[p] = 0;
+    fb_count[npairs + p] = 0;
+    flags[p] = 0;
+    PairState& S = st[p];
+    S.done = m > 0 ? 0 : 1;
+    for (int j = 0; j < 12; ++j) {
+        S.Rt[j] = rt[j];
+        S.Rtf[j] = (float)rt[j];
+    }
+    S.prev_rmse = 0.0;
+    S.iters = 0;
+    S.degenerate = 0;
+    S.status = 0;
+    S.rot_ok = 0;   // a caller's rotation: the first solve checks it
+}
+
+// The pose applied to a source point: s = R p + t (R row-major, then t).
+__device__ __forceinline__ void transform(const float* __restrict__ R, float x, float y, float z, float& sx, float& sy,
+                                          float& sz)
+{
+    sx = __builtin_fmaf(R[0], x, __builtin_fmaf(R[1], y, __builtin_fmaf(R[2], z, R[9])));
+    sy = __builtin_fmaf(R[3], x, __builtin_fmaf(R[4], y, __builtin_fmaf(R[5], z, R[10])));
+    sz = __builtin_fmaf(R[6], x, __builtin_fmaf(R[7], y, __builtin_fmaf(R[8], z, R[11])));
+}
+
+// Voxel of a transformed point, or false when it is outside the grid.
+__device__ __forceinline__ bool voxel_of(const PairDev& P, float sx, float sy, float sz, uint32_t& v)
+{
+    const float fx = (sx - P.ox) * P.inv;
+    const float fy = (sy - P.oy) * P.inv;
+    const float fz = (sz - P.oz) * P.inv;
+    // non-short-circuit: no branch waits on each bound's load in turn
+    const bool in = (fx >= 0.0f) & (fx < P.fDx) & (fy >= 0.0f) & (fy < P.fDy) & (fz >= 0.0f) & (fz < P.fDz);
+    if (in) v = (uint32_t)floorf(fx) + (uint32_t)P.Dx * ((uint32_t)floorf(fy) + (uint32_t)P.Dy * (uint32_t)floorf(fz));
+    return in;
+}
+
+
 // --------------------------------------------------------------------------
 // XCD-aware block order.  Workgroups are dealt to the 8 XCDs round-robin
 // (block b runs on XCD b mod 8), and each XCD has its own L2.  xcd_job maps
@@ -402,6 +446,26 @@ void launch_src_place(const PairDev* pd, const BlockJob* jobs, int njobs, const 
 void launch_src_rank(const PairDev* pd, const BlockJob* jobs, int njobs, const float* px, const float* py,
                      const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
                      const int32_t* sbig, float4* ps4, hipStream_t s);
+// The refill's count, scan, scatter and order passes each paired with the
+// source plan's matching pass in one launch (blocks [0, nq) the refill's,
+// the rest the plan's): k_count<false, 256> with k_src_bucket, the two
+// look-back scans, k_place with k_src_place, k_rank_sort with k_src_rank.
+void launch_count_bucket(const float* qx, const float* qy, const float* qz, const PairDev* pd,
+                         const BlockJob* qjobs, int nq, uint32_t* hist, uint32_t* vox, uint32_t* rank, uint32_t* err,
+                         const BlockJob* pjobs, int np, const float* px, const float* py, const float* pz,
+                         const PairState* st, uint32_t* sh, uint32_t* skey, uint32_t* srank, int32_t* sbig,
+                         int32_t* flags, hipStream_t s);
+void launch_scan_pair(const uint32_t* hist, int64_t total, uint32_t* off, uint32_t* vm, uint2* dir,
+                      unsigned long long* status, uint32_t* ticket, const uint32_t* sh, int64_t nb, uint32_t* soff,
+                      unsigned long long* s_status, uint32_t* s_ticket, hipStream_t s);
+void launch_place_pair(const PairDev* pd, const BlockJob* qjobs, int nq, const uint32_t* vox, const uint32_t* rank,
+                       const uint32_t* off, uint32_t* tmp, const BlockJob* pjobs, int np, const uint32_t* skey,
+                       const uint32_t* srank, const uint32_t* soff, uint32_t* sidx, hipStream_t s);
+void launch_rank_pair(const float* qx, const float* qy, const float* qz, const PairDev* pd, const BlockJob* qjobs,
+                      int nq, const uint32_t* vox, const uint32_t* hist, const uint32_t* off, const uint32_t* tmp,
+                      uint32_t* vm, float4* qs4, const BlockJob* pjobs, int np, const float* px, const float* py,
+                      const float* pz, const uint32_t* skey, const uint32_t* soff, const uint32_t* sidx,
+                      const int32_t* sbig, float4* ps4, hipStream_t s);
 // false (nothing launched) for npairs outside [1, kFbMaxPairs]
 bool launch_fallback(const PairDev* pd, int npairs, int grid, const float* qx, const float* qy, const float* qz,
                      const float* px, const float* py, const float* pz, const PairState* st, const int32_t* fb_count,
