@@ -210,6 +210,19 @@ def main():
             it = (np.asarray(ns) + np.asarray(fs)).reshape(prof_steps, P.iters).mean(0) * 1e-3
             per_iter = {"median_s": float(np.median(it)), "iter0_s": float(it[0]),
                         "nns_local_median_us": float(np.median(np.asarray(ns).reshape(prof_steps, P.iters).mean(0))) * 1e3}
+        if not a.separate_calls:
+            # the timed step's paired launches (refill pass + source plan pass)
+            api.prof_reset()
+            api.prof_enable(True)
+            for _ in range(prof_steps):
+                g.rebuild_register(q, P.rings, p, P.iters, use_graph=False)
+            torch.cuda.synchronize()
+            api.prof_enable(False)
+            for name in ("start_frame", "count_bucket", "scan_pair", "place_pair", "rank_pair"):
+                n_launch, tot = api.prof_read(name)
+                if n_launch:
+                    kernels[name] = {"launches_per_step": n_launch / prof_steps, "avg_us": 1e3 * tot / n_launch,
+                                     "ms_per_step": tot / prof_steps}
 
     F = np.asarray(res.fallbacks[0], np.int64)
     cand = np.asarray(res.candidates[0], np.int64)

@@ -1984,6 +1984,7 @@ int rebuild_register_impl(vicp_grid* g, const float* qx, const float* qy, const 
         f.n64[1] = scan_tiles(nb);
         const int64_t n = std::max(Vt, nb);
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+        ProfScope ps("start_frame", s, cap);
         hipLaunchKernelGGL(k_start_frame, dim3(blocks), dim3(256), 0, s, bl, (uint32_t*)g->d_pd, (int)(pd_bytes / 4), f,
                            g->B, g->st, g->fb_count, g->flags, n);
     } else {
