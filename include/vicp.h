@@ -172,9 +172,9 @@ int vicp_build_grid_fixed(const float* qx, const float* qy, const float* qz, int
  * reused when the voxel counts are unchanged.  The grid is left undilated:
  * call vicp_dilate again.  Waits once for the device (bounding box).
  * Errors as vicp_build_grid; STATE for a grid that was never built.  After a
- * rebuild of a given-geometry grid fails because a target point lies outside
- * it, every other entry point returns STATE for that grid until a rebuild
- * succeeds. */
+ * rebuild fails once the new bounding box is known (a target point outside a
+ * given-geometry grid, an allocation or a launch failure), every other entry
+ * point returns STATE for that grid until a rebuild succeeds. */
 int vicp_grid_rebuild(vicp_grid* g, const float* qx, const float* qy, const float* qz,
                       hipStream_t stream);
 
@@ -292,8 +292,9 @@ int vicp_register_batched(const vicp_grid* g, const float* px, const float* py, 
  * the two are independent; everything stays on `stream`.  Given-geometry
  * grids, host-side offsets, the packed-hash count, the direct layout,
  * global_only and searches over the source in index order take the three
- * calls' path.  Errors: as the three calls (the grid is left as the failing
- * step leaves it); STATE for a grid that was never built. */
+ * calls' path.  Errors: as the three calls; STATE for a grid that was never
+ * built.  A failure after the bounding box leaves the grid refusing every
+ * call with STATE until a rebuild succeeds, as a failed rebuild does. */
 int vicp_rebuild_register(vicp_grid* g, const float* qx, const float* qy, const float* qz,
                           int32_t rings, const float* px, const float* py, const float* pz,
                           const int64_t* m_per_pair, const vicp_icp_opts* opts, double* Rt_io,

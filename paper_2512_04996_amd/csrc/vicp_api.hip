@@ -542,7 +542,7 @@ struct vicp_grid {
     std::vector<PairDev> h_pd;   // the pair records of the last refill, written by its first launch
     // a given grid geometry (single pair) instead of the target's padded box
     bool fixed = false;
-    bool usable = true;   // false after a build whose target did not fit the given grid
+    bool usable = true;   // false from a refill's grid specification until its kernels are queued, or after it failed
     // the Alg. 1 ablation: host-side offset scan, fused 32-bit LDS hash entries
     bool host_offsets = false, packed_hash = false;
     std::vector<uint32_t> h_hist, h_off;
@@ -1218,6 +1218,7 @@ int grid_fill(vicp_grid* g, const float* qx, const float* qy, const float* qz, h
 {
     int rc = grid_fill_host(g, qx, qy, qz, s);
     if (rc) return rc;
+    g->usable = false;   // the grid's words are stale until the refill below is queued
     const int64_t Vt = g->V_total;
     if (!g->fixed && !g->host_offsets) {
         queue_build(g, s, false);
@@ -1954,6 +1955,7 @@ int rebuild_register_impl(vicp_grid* g, const float* qx, const float* qy, const 
     }
     rc = grid_fill_host(g, qx, qy, qz, s);
     if (rc) return rc;
+    g->usable = false;   // the grid's words are stale until the refill below is queued
     rc = ensure_source(g, m_per_pair, o->max_iter, s);
     if (rc) return rc;
     fill_pairdev(g, g->h_pd);   // the pair records with the source's fields
