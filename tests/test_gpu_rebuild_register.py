@@ -9,7 +9,8 @@ bit for bit, the RMSE, global-search, candidate and dilated-lookup histories,
 the iteration counts and the last iteration's correspondences.  Frames change
 the target's pose (same grid shape) and its scale (a new grid shape, so the
 voxel buffers and the source workspace are rebuilt inside the call); one
-call changes the source's size.  One frame is also checked against the
+call changes the source's size; batches of 5 and 64 pairs start from a
+distinct pose per pair.  One frame is also checked against the
 oracle, and the forms that take the plain path (source in index order) and
 the argument errors are covered.
 """
@@ -110,8 +111,11 @@ def test_frame_matches_oracle():
     g.free()
 
 
-def test_batched_frames_match_three_calls():
-    pairs = synth.config("batched_64")   # 64 pairs: the poses go up by upload, not in the launch
+@pytest.mark.parametrize("npairs", [5, 64])
+def test_batched_frames_match_three_calls(npairs):
+    # 5 pairs: poses and records travel in the start launch; 64 pairs: the
+    # poses go up by upload and the records by a separate copy
+    pairs = synth.config("batched_64")[:npairs]
     ns, ms, vox = [x.n for x in pairs], [x.m for x in pairs], [x.voxel for x in pairs]
     q0 = np.concatenate([x.q for x in pairs], 1)
     pc = dev(np.concatenate([x.p for x in pairs], 1))
@@ -119,12 +123,15 @@ def test_batched_frames_match_three_calls():
     ga = build_grid_batched(dev(q0), ns, vox, 3).dilate(3).set_schedule(**sched)
     gb = build_grid_batched(dev(q0), ns, vox, 3).dilate(3).set_schedule(**sched)
     frames = [np.concatenate([_frames(x.q)[i] for x in pairs], 1) for i in range(2)]
+    # a distinct starting pose per pair (each must reach its own pair's state)
+    rt0 = np.stack([np.concatenate([_rotz(0.2 * (b + 1)).reshape(-1), [1e-3 * b, 0.0, -1e-3 * b]])
+                    for b in range(npairs)])
     for f, q in enumerate(frames):
         qd = dev(q)
         ga.rebuild(qd).dilate(3)
-        ra = ga.register(pc, 30, m_per_pair=ms, use_graph=True, correspondences=True)
-        rb = gb.rebuild_register(qd, 3, pc, 30, m_per_pair=ms, use_graph=True, correspondences=True)
-        print(f"[rebuild_register] batched frame {f}", flush=True)
+        ra = ga.register(pc, 30, m_per_pair=ms, use_graph=True, correspondences=True, Rt0=rt0)
+        rb = gb.rebuild_register(qd, 3, pc, 30, m_per_pair=ms, use_graph=True, correspondences=True, Rt0=rt0)
+        print(f"[rebuild_register] {npairs} pairs, frame {f}", flush=True)
         _same(ra, rb, len(pairs))
     ga.free()
     gb.free()
