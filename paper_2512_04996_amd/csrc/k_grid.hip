@@ -1,6 +1,10 @@
 // k_grid.hip -- target grid build: bounding box, voxelise + count (Alg. 1,
 // GPU part), offsets by a single-pass scan (Alg. 1, CPU part, moved to the
-// GPU), scatter into segments and canonical in-segment order (Alg. 2).
+// GPU), scatter into segments and canonical in-segment order (Alg. 2); the
+// source's bucketing by target voxel (the search's query order), the same
+// count / scan / place / rank shape over the source; and each of those four
+// passes paired with the target's in one launch.  Kernel bodies are device
+// functions of a block index, so a paired launch runs either body.
 #include <algorithm>
 
 #include "vicp_internal.hpp"
