@@ -1,7 +1,8 @@
 """The GPU path's float64 rigid-transform solve, compiled for the host with
 hipcc, against the textbook SVD solution (numpy) on random correspondences,
 reflections, planar and far-from-origin clouds, and against the rank test on
-degenerate inputs (one target point, exactly collinear targets).  The polar
+degenerate inputs (one target point, exactly collinear targets) and on
+nearly collinear targets (refused, or solved with the SVD's objective).  The polar
 factor refined from a starting rotation (the previous pose in the ICP loop)
 must give the same answer from near, far, identity and non-orthogonal
 starts (the last two fall back to the Newton or SVD path)."""
@@ -124,3 +125,36 @@ def test_refined_solve_matches_svd_from_any_start(solve_lib):
         assert ok, (trial, kind, start)
         assert np.abs(out[:9].reshape(3, 3) - Rk).max() < 1e-11, (trial, kind, start)
         assert np.abs(out[9:] - tk).max() < 1e-11 * max(1.0, np.abs(tk).max()), (trial, kind, start)
+
+
+def test_nearly_collinear_targets_refused_or_optimal(solve_lib):
+    """Targets on a line up to a transverse spread eps: the rotation about the
+    line is then barely determined, so the solve may refuse (rank test) or
+    answer; an answer must be a proper rotation whose Eq. 1 objective is the
+    SVD solution's (the objective stays well determined when R is not).  A
+    spread of 1e-2 of the extent is well conditioned and must be solved."""
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        eps = [1e-2, 1e-4, 1e-6, 1e-8][trial % 4]
+        n = int(rng.integers(8, 200))
+        t = rng.standard_normal(n) * 5
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        q = np.outer(d, t) + rng.standard_normal((3, 1)) + rng.standard_normal((3, n)) * (5 * eps)
+        R = random_rotation(rng.standard_normal(3), rng.uniform(0, np.pi))
+        p = R.T @ (q - rng.standard_normal((3, 1))) + rng.standard_normal((3, n)) * 1e-3
+        p = p.astype(np.float32).astype(np.float64)
+        q = q.astype(np.float32).astype(np.float64)
+        c = np.round(q.mean(1), 1)
+        out = np.zeros(12)
+        ok = solve_lib.vicp_test_kabsch(_p(moments(p, q, c)), _p(c), _p(out))
+        if eps == 1e-2:
+            assert ok, trial
+        if not ok:
+            continue
+        Ro, to = out[:9].reshape(3, 3), out[9:]
+        assert np.abs(Ro @ Ro.T - np.eye(3)).max() < 1e-12 and np.linalg.det(Ro) > 0, trial
+        Rk, tk, _ = kabsch_svd(p, q)
+        e_out = float(((Ro @ p + to[:, None] - q) ** 2).sum())
+        e_svd = float(((Rk @ p + tk[:, None] - q) ** 2).sum())
+        assert e_out <= e_svd * (1 + 1e-9) + 1e-18, (trial, eps, e_out, e_svd)
