@@ -116,12 +116,16 @@ __device__ __forceinline__ void consider(const float4& q, float sx, float sy, fl
 // lane waits for two rounds of loads per batch, not one per voxel).
 constexpr int kShellFirst = 2;   // the smallest first cube: 5^3 voxels
 constexpr int kShellMax = 8;     // the largest: 17^3 voxels
-constexpr int kShellBatch = 6;   // directory loads in flight per lane
+constexpr int kShellBatch = 6;     // directory loads in flight per lane (registration)
+constexpr int kShellLoads = 4;     // point loads in flight per lane (registration)
+constexpr int kShellBatchNN = 12;  // the same in the correspondence search
+constexpr int kShellLoadsNN = 8;
 constexpr uint32_t kShellPoints = 384;   // points a lane may scan before the wave gives up
 
 // The point and every quantity derived from it are the same in all lanes
 // (scalar registers); a lane keeps only its best candidate's (d, j) and
 // segment slot, and the winner's coordinates are read once at the end.
+template <int kBatch, int kLoads>
 __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __restrict__ dir,
                                               const float4* __restrict__ qs4, float sx, float sy, float sz,
                                               float& rd, uint32_t& rj, float& rx, float& ry, float& rz)
@@ -156,11 +160,11 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
     while (true) {
         const int w = 2 * R + 1;
         const int items = w * w * w;
-        for (int i0 = lane; i0 < items; i0 += kWave * kShellBatch) {
+        for (int i0 = lane; i0 < items; i0 += kWave * kBatch) {
             // the batch's directory entries, all in flight together
-            uint2 e[kShellBatch];
+            uint2 e[kBatch];
 #pragma unroll
-            for (int u = 0; u < kShellBatch; ++u) {
+            for (int u = 0; u < kBatch; ++u) {
                 e[u] = make_uint2(0u, 0u);
                 const int it = i0 + u * kWave;
                 if (it >= items) continue;
@@ -173,26 +177,26 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
             }
             // the points of the batch's occupied voxels (own count, no mask:
             // a dilated voxel's entry points at its root, visited as itself)
-            // as one flat run, four loads in flight; a lane past its last
+            // as one flat run, kLoads loads in flight; a lane past its last
             // point repeats it (a repeat never wins)
-            uint32_t end[kShellBatch];
+            uint32_t end[kBatch];
             uint32_t total = 0u;
 #pragma unroll
-            for (int u = 0; u < kShellBatch; ++u) {
+            for (int u = 0; u < kBatch; ++u) {
                 total += (e[u].y & kMask) ? 0u : e[u].y;
                 end[u] = total;
             }
             scanned += total;
             if (__ballot(scanned > kShellPoints)) return false;   // uniform: too many points
-            for (uint32_t t0 = 0; t0 < total; t0 += 4) {
-                float4 q[4];
-                uint32_t sl[4];
+            for (uint32_t t0 = 0; t0 < total; t0 += kLoads) {
+                float4 q[kLoads];
+                uint32_t sl[kLoads];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+                for (int t = 0; t < kLoads; ++t) {
                     const uint32_t f = min(t0 + (uint32_t)t, total - 1u);
                     uint32_t slot = 0u, start = 0u;
 #pragma unroll
-                    for (int u = 0; u < kShellBatch; ++u) {
+                    for (int u = 0; u < kBatch; ++u) {
                         const bool here = f >= start && f < end[u];
                         slot = here ? e[u].x + (f - start) : slot;
                         start = end[u];
@@ -201,7 +205,7 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
                     q[t] = qs4[slot];
                 }
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+                for (int t = 0; t < kLoads; ++t) {
                     const float d = dist2(sx, sy, sz, q[t].x, q[t].y, q[t].z);
                     const uint32_t j = __float_as_uint(q[t].w);
                     const bool better = d < bd || (d == bd && j < bj);
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), L));
             const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), L));
             const float lz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz), L));
-            if (shell_nearest(P, dir, qsg, lx, ly, lz, rd, rj, rx, ry, rz)) {
+            if (shell_nearest<kMom ? kShellBatch : kShellBatchNN, kMom ? kShellLoads : kShellLoadsNN>(P, dir, qsg, lx, ly, lz, rd, rj, rx, ry, rz)) {
                 if (lane == L) {
                     shelled = true;
                     bd = rd;
