@@ -120,12 +120,13 @@ constexpr int kShellBatch = 6;     // directory loads in flight per lane (regist
 constexpr int kShellLoads = 4;     // point loads in flight per lane (registration)
 constexpr int kShellBatchNN = 12;  // the same in the correspondence search
 constexpr int kShellLoadsNN = 8;
+constexpr int kShellFirstNN = 4;   // its smallest first cube, 9^3 voxels: one round of 12 x 64 entries
 constexpr uint32_t kShellPoints = 384;   // points a lane may scan before the wave gives up
 
 // The point and every quantity derived from it are the same in all lanes
 // (scalar registers); a lane keeps only its best candidate's (d, j) and
 // segment slot, and the winner's coordinates are read once at the end.
-template <int kBatch, int kLoads>
+template <int kBatch, int kLoads, int kFirst>
 __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __restrict__ dir,
                                               const float4* __restrict__ qs4, float sx, float sy, float sz,
                                               float& rd, uint32_t& rj, float& rx, float& ry, float& rz)
@@ -156,7 +157,7 @@ __device__ __forceinline__ bool shell_nearest(const PairDev& P, const uint2* __r
     int done_r = -1;   // the cube of this radius has been visited
     // the first cube reaches one voxel past the dilation: a global search's
     // voxel has no occupied voxel within L1 distance L
-    int R = min(max(P.pad + 1, kShellFirst), kShellMax);
+    int R = min(max(P.pad + 1, kFirst), kShellMax);
     while (true) {
         const int w = 2 * R + 1;
         const int items = w * w * w;
@@ -458,7 +459,8 @@ __global__ __launch_bounds__(BS) void k_nns_local(const PairDev* __restrict__ pd
             const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), L));
             const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), L));
             const float lz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz), L));
-            if (shell_nearest<kMom ? kShellBatch : kShellBatchNN, kMom ? kShellLoads : kShellLoadsNN>(P, dir, qsg, lx, ly, lz, rd, rj, rx, ry, rz)) {
+            if (shell_nearest<kMom ? kShellBatch : kShellBatchNN, kMom ? kShellLoads : kShellLoadsNN,
+                              kMom ? kShellFirst : kShellFirstNN>(P, dir, qsg, lx, ly, lz, rd, rj, rx, ry, rz)) {
                 if (lane == L) {
                     shelled = true;
                     bd = rd;
